@@ -1,0 +1,134 @@
+/*
+ * dmala.h -- C ABI of the MI355X (gfx950) DMALA MIMO detector.
+ *
+ * The library runs the many-chain sampler of Zhou et al., "Near-Optimal MIMO
+ * Detection Using Gradient-Based MCMC in Discrete Spaces":
+ *   - target: posterior of eq. post with metric f(x) = -||y - Hx||^2 / sigma^2
+ *     (eq. f), tempered to f/tau as in Algorithm 2 (eq. aux);
+ *   - proposal: the discrete Langevin proposal of eqs. dis_prop..softmax, or its
+ *     preconditioned form (the Remark after Algorithm 1, M = (H^T H + gamma I)^-1);
+ *   - correction: the MH acceptance of eq. acc_prob, Algorithm 1;
+ *   - outputs: the minimum-residual hard decision (text after Algorithm 1), the
+ *     IS-based bit LLRs of eq. llr_is (log-sum-exp form, eq. llr_simple), and
+ *     symbol marginals from the symbol-level analogue of the IS estimator
+ *     (Appendix B), computed from the final sample of every chain (Section V-A).
+ *
+ * Conventions (all buffers are caller-owned; nothing here allocates device
+ * memory, synchronises the stream or keeps pointers after a call returns):
+ *   complex numbers are interleaved (re, im) pairs;
+ *   H of instance b is Nr x Nt, column-major: element (i, m) at
+ *     H[b*Nt*Nr + m*Nr + i];  y of instance b at y[b*Nr + i];
+ *   precision DMALA_FP64 takes double-precision H, y, sigma2; every other
+ *     precision takes single precision;
+ *   points of M-QAM are indexed a = kI*Q + kQ (Q = sqrt(M)), kI/kQ the
+ *     ascending level indices of the real/imaginary part, levels
+ *     s*(2k - Q + 1) with s = sqrt(3 / (2 (M - 1))) (unit average energy);
+ *   bit labels: per-axis binary-reflected Gray code of the level index, MSB
+ *     first, antenna bits ordered [I bits, Q bits]; LLR = log P(b=0)/P(b=1);
+ *   random numbers: Philox4x32-10, key (seed mod 2^32, seed >> 32), counter
+ *     (block, t, chain, instance); outputs are a pure function of the inputs,
+ *     the parameters and the seed.
+ * Errors: every entry point returns a dmala_status; dmala_last_error() gives a
+ * thread-local message for the last failure on the calling thread.  Argument
+ * errors are detected on the host before anything is enqueued.
+ */
+#ifndef DMALA_H
+#define DMALA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* dmala_stream_t; /* a hipStream_t; NULL = default stream */
+
+typedef enum {
+  DMALA_OK = 0,
+  DMALA_ERR_ARG = -1,         /* invalid argument (shape, sigma^2 <= 0, NULL input, ...) */
+  DMALA_ERR_UNSUPPORTED = -2, /* valid but not supported (non-square or unknown QAM, size limits) */
+  DMALA_ERR_WORKSPACE = -4,   /* workspace NULL or smaller than dmala_workspace_size() */
+  DMALA_ERR_HIP = -5          /* a HIP runtime call failed (message has the HIP error) */
+} dmala_status;
+
+/* Arithmetic of the chain update.
+ *   FP64: every step in double precision (parity mode).
+ *   FP32: the gradient contraction on MFMA with an exact two-term fp16 split of
+ *         the proposal matrix and a three-term split of the energy matrix
+ *         (chain states are small odd integers, exact in fp16), fp32
+ *         accumulation; proposal normalisers and the MH test in fp32.
+ *   BF16 / FP16: the proposal gradient from a single bf16 / fp16 MFMA pass;
+ *         the energy difference and all normalisers stay fp32-class. */
+typedef enum { DMALA_FP64 = 0, DMALA_FP32 = 1, DMALA_BF16 = 2, DMALA_FP16 = 3 } dmala_precision;
+
+/* Proposal: PRECOND = the preconditioned discrete Langevin proposal (the
+ * paper's evaluated variant); NAIVE = eq. exp_fac with the plain gradient. */
+typedef enum { DMALA_PRECOND = 0, DMALA_NAIVE = 1 } dmala_proposal;
+
+typedef struct {
+  int32_t n_chains;          /* parallel samplers per instance, 1..1024 */
+  int32_t n_iters;           /* MH transitions per chain (the paper's T - 1), 0..65535 */
+  uint64_t seed;             /* Philox key */
+  dmala_precision precision;
+  dmala_proposal proposal;
+  double tau;                /* temperature of pi_a (eq. aux); <= 0 selects 2 (Section V-A) */
+  double alpha_mult;         /* alpha = alpha_mult * sigma^2;          <= 0 selects 1 */
+  double beta_mult;          /* beta  = beta_mult * dmin^2 / sigma^2;  <= 0 selects 1 */
+  double gamma_mult;         /* gamma = gamma_mult * sigma^2 / (2 dmin^2); <= 0 selects 1 */
+} dmala_params;
+
+/* Device output buffers; any pointer may be NULL to skip that output. */
+typedef struct {
+  int32_t* symbols;          /* [n_inst][Nt] hard decision (point index) */
+  float* marginals;          /* [n_inst][Nt][M] symbol posterior estimates */
+  float* llrs;               /* [n_inst][Nt][log2 M] bit LLRs */
+  float* best_energy;        /* [n_inst] ||y - H x_hat||^2 of the hard decision */
+  int8_t* final_state;       /* [n_inst][n_chains][2 Nt] final level indices, dims (Re x_m, Im x_m) interleaved */
+  int32_t* accept_count;     /* [n_inst][n_chains] accepted transitions */
+  float* marginals_mc;       /* [n_inst][Nt][M] plain Monte Carlo histogram of the final samples */
+  uint32_t* trace_accept;    /* [n_inst][n_chains][ceil(n_iters/32)] accept bit of transition t at bit t%32 */
+  uint32_t* trace_hash;      /* [n_inst][n_chains][n_iters] state fingerprint after transition t:
+                                sum_n (k_n + 1) * ((2n + 1) * 0x9E3779B1) mod 2^32 */
+} dmala_outputs;
+
+/* Bytes of device workspace dmala_detect needs for this shape (0 on invalid
+ * arguments; see dmala_last_error()). */
+size_t dmala_workspace_size(int32_t n_inst, int32_t nt, int32_t nr, int32_t qam_order,
+                            const dmala_params* params);
+
+/* Detect n_inst independent problems of one shape (Algorithm 2 per instance).
+ *   H, y, sigma2: device inputs as described above; sigma2[b] > 0 (Lemma 1).
+ *   constellation: NULL, or host array of M complex float points that must
+ *     equal the canonical unit-energy QAM (validated; others are unsupported).
+ *   Limits: 1 <= nt <= 64, 1 <= nr <= 4096, M in {4, 16, 64, 256}; FP64 needs nt <= 32.
+ * Enqueues setup, sampler and estimator kernels on `stream` and returns. */
+dmala_status dmala_detect(const void* H, const void* y, const void* sigma2,
+                          int32_t n_inst, int32_t nt, int32_t nr, int32_t qam_order,
+                          const float* constellation, const dmala_params* params,
+                          const dmala_outputs* out, void* workspace, size_t workspace_bytes,
+                          dmala_stream_t stream);
+
+/* Evaluate the chain's transition quantities for given state pairs with the
+ * same device code as the sampler (tests build exact transition matrices from
+ * it).  x_from, x_to: device int8 [n_inst][n_pairs][2 Nt] level indices.
+ * out: device double [n_inst][n_pairs][4] = (log q(x_to | x_from),
+ * log q(x_from | x_to), f(x_to)/tau - f(x_from)/tau, log acceptance ratio),
+ * natural logs, as the sampler computes them.  Workspace as for
+ * dmala_detect with n_chains = n_pairs. */
+dmala_status dmala_debug_eval(const void* H, const void* y, const void* sigma2,
+                              int32_t n_inst, int32_t nt, int32_t nr, int32_t qam_order,
+                              const dmala_params* params, const int8_t* x_from, const int8_t* x_to,
+                              int32_t n_pairs, double* out, void* workspace, size_t workspace_bytes,
+                              dmala_stream_t stream);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* dmala_last_error(void);
+
+/* Library version string. */
+const char* dmala_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMALA_H */

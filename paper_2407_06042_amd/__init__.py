@@ -1,0 +1,184 @@
+"""Python binding of libdmala.so, the MI355X DMALA MIMO detector.
+
+Argument marshalling only: every step of detection runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current HIP stream.  The
+library is loaded from this directory; if it is missing or fails to load, every
+entry point raises -- there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmala.so")
+
+FP64, FP32, BF16, FP16 = 0, 1, 2, 3
+PRECOND, NAIVE = 0, 1
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp16": FP16}
+PROPOSALS = {"precond": PRECOND, "naive": NAIVE}
+STATUS = {0: "DMALA_OK", -1: "DMALA_ERR_ARG", -2: "DMALA_ERR_UNSUPPORTED", -4: "DMALA_ERR_WORKSPACE", -5: "DMALA_ERR_HIP"}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_chains", ctypes.c_int32), ("n_iters", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("precision", ctypes.c_int), ("proposal", ctypes.c_int), ("tau", ctypes.c_double),
+                ("alpha_mult", ctypes.c_double), ("beta_mult", ctypes.c_double), ("gamma_mult", ctypes.c_double)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("symbols", ctypes.c_void_p), ("marginals", ctypes.c_void_p), ("llrs", ctypes.c_void_p),
+                ("best_energy", ctypes.c_void_p), ("final_state", ctypes.c_void_p), ("accept_count", ctypes.c_void_p),
+                ("marginals_mc", ctypes.c_void_p), ("trace_accept", ctypes.c_void_p), ("trace_hash", ctypes.c_void_p)]
+
+
+class DmalaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libdmala.so is not built (run paper_2407_06042_amd.build.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        L.dmala_workspace_size.restype = sz
+        L.dmala_workspace_size.argtypes = [i32, i32, i32, i32, ctypes.POINTER(Params)]
+        L.dmala_detect.restype = ctypes.c_int
+        L.dmala_detect.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, ctypes.POINTER(Params),
+                                   ctypes.POINTER(Outputs), vp, sz, vp]
+        L.dmala_debug_eval.restype = ctypes.c_int
+        L.dmala_debug_eval.argtypes = [vp, vp, vp, i32, i32, i32, i32, ctypes.POINTER(Params), vp, vp, i32, vp, vp, sz, vp]
+        L.dmala_last_error.restype = ctypes.c_char_p
+        L.dmala_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["dmala_workspace_size", "dmala_detect", "dmala_debug_eval", "dmala_last_error", "dmala_version"]
+
+
+def last_error():
+    return lib().dmala_last_error().decode()
+
+
+def make_params(n_chains, n_iters, seed, precision="fp32", proposal="precond", tau=2.0,
+                alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0):
+    return Params(int(n_chains), int(n_iters), int(seed) & ((1 << 64) - 1), PRECISIONS[precision],
+                  PROPOSALS[proposal], float(tau), float(alpha_mult), float(beta_mult), float(gamma_mult))
+
+
+def workspace_size(n_inst, nt, nr, M, params):
+    n = lib().dmala_workspace_size(n_inst, nt, nr, M, ctypes.byref(params))
+    if n == 0:
+        raise DmalaError(-1, last_error())
+    return n
+
+
+def device_inputs(H, y, sigma2, precision="fp32", device="cuda"):
+    """Marshal host arrays into the library's device layout.
+
+    H: (B, Nr, Nt) complex, y: (B, Nr) complex, sigma2: (B,).  Returns torch
+    tensors (Hcm, y, sigma2): Hcm is (B, Nt, Nr), i.e. column-major per instance.
+    """
+    import torch
+    ct, rt = (np.complex128, np.float64) if precision == "fp64" else (np.complex64, np.float32)
+    Hcm = np.ascontiguousarray(np.transpose(np.asarray(H), (0, 2, 1))).astype(ct)
+    return (torch.from_numpy(Hcm).to(device), torch.from_numpy(np.ascontiguousarray(y).astype(ct)).to(device),
+            torch.from_numpy(np.ascontiguousarray(sigma2).astype(rt)).to(device))
+
+
+class Detector:
+    """Reusable detector for one problem shape: owns a workspace and output tensors."""
+
+    def __init__(self, n_inst, nt, nr, M, n_chains, n_iters, seed=0, precision="fp32", proposal="precond",
+                 tau=2.0, alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, device="cuda",
+                 outputs=("symbols", "marginals", "llrs", "best_energy"), trace=False):
+        import torch
+        self.torch = torch
+        self.n_inst, self.nt, self.nr, self.M = n_inst, nt, nr, M
+        self.precision = precision
+        self.params = make_params(n_chains, n_iters, seed, precision, proposal, tau, alpha_mult, beta_mult, gamma_mult)
+        self.ws_bytes = workspace_size(n_inst, nt, nr, M, self.params)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        nb = int(round(np.log2(M)))
+        shapes = dict(symbols=((n_inst, nt), torch.int32), marginals=((n_inst, nt, M), torch.float32),
+                      llrs=((n_inst, nt, nb), torch.float32), best_energy=((n_inst,), torch.float32),
+                      final_state=((n_inst, n_chains, 2 * nt), torch.int8),
+                      accept_count=((n_inst, n_chains), torch.int32),
+                      marginals_mc=((n_inst, nt, M), torch.float32))
+        want = set(outputs)
+        if trace:
+            want |= {"final_state", "accept_count"}
+        self.out = {k: torch.empty(s, dtype=d, device=device) for k, (s, d) in shapes.items() if k in want}
+        if trace:
+            self.out["trace_accept"] = torch.zeros((n_inst, n_chains, (n_iters + 31) // 32), dtype=torch.int32, device=device)
+            self.out["trace_hash"] = torch.zeros((n_inst, n_chains, n_iters), dtype=torch.int32, device=device)
+        o = Outputs()
+        for name, _ in Outputs._fields_:
+            setattr(o, name, self.out[name].data_ptr() if name in self.out else None)
+        self._outs = o
+
+    def _ws_ptr(self):
+        p = self.ws.data_ptr()
+        return (p + 255) // 256 * 256
+
+    def __call__(self, Hcm, y, sigma2, stream=None):
+        """Enqueue detection on the current (or given) stream; returns the output dict."""
+        torch = self.torch
+        self._check_inputs(Hcm, y, sigma2)
+        s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        st = lib().dmala_detect(Hcm.data_ptr(), y.data_ptr(), sigma2.data_ptr(), self.n_inst, self.nt, self.nr, self.M,
+                                None, ctypes.byref(self.params), ctypes.byref(self._outs), self._ws_ptr(),
+                                self.ws_bytes, s)
+        if st != 0:
+            raise DmalaError(st, last_error())
+        return self.out
+
+    def _check_inputs(self, Hcm, y, sigma2):
+        torch = self.torch
+        ct, rt = (torch.complex128, torch.float64) if self.precision == "fp64" else (torch.complex64, torch.float32)
+        if Hcm.dtype != ct or y.dtype != ct or sigma2.dtype != rt:
+            raise TypeError("inputs must be %s/%s for precision %s" % (ct, rt, self.precision))
+        if tuple(Hcm.shape) != (self.n_inst, self.nt, self.nr) or tuple(y.shape) != (self.n_inst, self.nr) \
+                or tuple(sigma2.shape) != (self.n_inst,):
+            raise ValueError("input shapes do not match the detector")
+        if not (Hcm.is_contiguous() and y.is_contiguous() and sigma2.is_contiguous()):
+            raise ValueError("inputs must be contiguous")
+        if not Hcm.is_cuda:
+            raise ValueError("inputs must be device tensors")
+
+
+def detect(Hcm, y, sigma2, M, n_chains, n_iters, seed, **kw):
+    """One-shot detection (allocates a workspace).  See Detector for keywords."""
+    n_inst, nt, nr = Hcm.shape
+    d = Detector(n_inst, nt, nr, M, n_chains, n_iters, seed, device=Hcm.device, **kw)
+    return d(Hcm, y, sigma2)
+
+
+def debug_eval(Hcm, y, sigma2, M, x_from, x_to, precision="fp32", proposal="precond", tau=2.0,
+               alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0):
+    """Transition quantities of the device chain for state pairs (see dmala_debug_eval)."""
+    import torch
+    n_inst, nt, nr = Hcm.shape
+    n_pairs = x_from.shape[1]
+    p = make_params(n_pairs, 0, 0, precision, proposal, tau, alpha_mult, beta_mult, gamma_mult)
+    ws_bytes = workspace_size(n_inst, nt, nr, M, p)
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=Hcm.device)
+    wp = (ws.data_ptr() + 255) // 256 * 256
+    out = torch.empty((n_inst, n_pairs, 4), dtype=torch.float64, device=Hcm.device)
+    xf = x_from.to(torch.int8).contiguous()
+    xt = x_to.to(torch.int8).contiguous()
+    st = lib().dmala_debug_eval(Hcm.data_ptr(), y.data_ptr(), sigma2.data_ptr(), n_inst, nt, nr, M, ctypes.byref(p),
+                                xf.data_ptr(), xt.data_ptr(), n_pairs, out.data_ptr(), wp, ws_bytes,
+                                torch.cuda.current_stream().cuda_stream)
+    if st != 0:
+        raise DmalaError(st, last_error())
+    return out

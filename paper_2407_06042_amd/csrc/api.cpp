@@ -1,0 +1,201 @@
+// C ABI of the DMALA library: argument validation, workspace layout, launches.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/dmala.h"
+#include "common.hpp"
+
+using namespace dmala;
+
+namespace {
+
+thread_local std::string g_err;
+
+dmala_status fail(dmala_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+dmala_status fail(dmala_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Plan {
+  Shape sh;
+  size_t inst_off, state_off, est_off, total;
+  double tau, am, bm, gm;
+  bool naive;
+};
+
+dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const dmala_params* p, Plan& pl) {
+  if (!p) return fail(DMALA_ERR_ARG, "params is NULL");
+  if (n_inst < 1) return fail(DMALA_ERR_ARG, "n_inst must be >= 1 (got %d)", n_inst);
+  if (nt < 1 || nr < 1) return fail(DMALA_ERR_ARG, "nt and nr must be >= 1 (got %d, %d)", nt, nr);
+  if (p->n_chains < 1 || p->n_chains > 1024) return fail(DMALA_ERR_ARG, "n_chains must be in [1, 1024] (got %d)", p->n_chains);
+  if (p->n_iters < 0 || p->n_iters > 65535) return fail(DMALA_ERR_ARG, "n_iters must be in [0, 65535] (got %d)", p->n_iters);
+  if (p->precision < DMALA_FP64 || p->precision > DMALA_FP16) return fail(DMALA_ERR_ARG, "unknown precision %d", (int)p->precision);
+  if (p->proposal != DMALA_PRECOND && p->proposal != DMALA_NAIVE) return fail(DMALA_ERR_ARG, "unknown proposal %d", (int)p->proposal);
+  if (!(std::isfinite(p->tau) && std::isfinite(p->alpha_mult) && std::isfinite(p->beta_mult) && std::isfinite(p->gamma_mult)))
+    return fail(DMALA_ERR_ARG, "non-finite tau/alpha/beta/gamma multiplier");
+  int Q = 0;
+  if (M == 4) Q = 2; else if (M == 16) Q = 4; else if (M == 64) Q = 8; else if (M == 256) Q = 16;
+  else return fail(DMALA_ERR_UNSUPPORTED, "qam_order must be 4, 16, 64 or 256 (got %d)", M);
+  if (nr > 4096) return fail(DMALA_ERR_UNSUPPORTED, "nr > 4096 is not supported (got %d)", nr);
+  const bool fp64 = p->precision == DMALA_FP64;
+  if (nt > 64) return fail(DMALA_ERR_UNSUPPORTED, "nt > 64 is not supported (got %d)", nt);
+  if (fp64 && nt > 32) return fail(DMALA_ERR_UNSUPPORTED, "DMALA_FP64 supports nt <= 32 (got %d)", nt);
+  Shape& sh = pl.sh;
+  sh.nt = nt; sh.nr = nr; sh.M = M; sh.Q = Q; sh.N = 2 * nt;
+  sh.Npad = 32 * ((sh.N + 31) / 32);
+  sh.RT = sh.Npad / 16; sh.KB = sh.RT / 2;
+  sh.C = p->n_chains; sh.Cpad = 16 * ((sh.C + 15) / 16); sh.T = p->n_iters;
+  sh.fp64 = fp64 ? 1 : 0;
+  pl.naive = p->proposal == DMALA_NAIVE;
+  if (pl.naive) sh.pm = PM_NAIVE;
+  else if (p->precision == DMALA_BF16) sh.pm = PM_BF16X1;
+  else if (p->precision == DMALA_FP16) sh.pm = PM_F16X1;
+  else sh.pm = PM_F16X2;
+  if (fp64) {
+    sh.frag_bytes = round_up((2 * (size_t)sh.Npad * sh.Npad + 2 * (size_t)sh.Npad) * 8, 16);
+  } else {
+    sh.frag_bytes = (size_t)(p_passes(sh.pm) + kEPasses) * sh.RT * sh.KB * 1024 + 2 * (size_t)sh.Npad * 4;
+  }
+  if (sampler_lds_bytes(sh) > 160 * 1024)
+    return fail(DMALA_ERR_UNSUPPORTED, "shape needs %zu bytes of LDS (> 160 KiB)", sampler_lds_bytes(sh));
+  sh.inst_bytes = round_up(kParamBytes + sh.frag_bytes, 256);
+  sh.state_bytes = state_offsets(sh.Cpad, sh.Npad).end;
+  const size_t R = fp64 ? 8 : 4;
+  sh.est_bytes = round_up(R * (2 * (size_t)sh.C * nr + (size_t)sh.C * nr + 2 * (size_t)sh.C * nt + 2 * (size_t)sh.C +
+                               2 * (size_t)sh.C * nt + nt + (size_t)nt * M), 256);
+  pl.inst_off = 0;
+  pl.state_off = round_up((size_t)n_inst * sh.inst_bytes, 256);
+  pl.est_off = round_up(pl.state_off + (size_t)n_inst * sh.state_bytes, 256);
+  pl.total = pl.est_off + (size_t)n_inst * sh.est_bytes;
+  pl.tau = p->tau > 0 ? p->tau : 2.0;
+  pl.am = p->alpha_mult > 0 ? p->alpha_mult : 1.0;
+  pl.bm = p->beta_mult > 0 ? p->beta_mult : 1.0;
+  pl.gm = p->gamma_mult > 0 ? p->gamma_mult : 1.0;
+  return DMALA_OK;
+}
+
+bool canonical_qam(const float* pts, int M) {
+  const int Q = (int)std::lround(std::sqrt((double)M));
+  const double s = std::sqrt(3.0 / (2.0 * (M - 1)));
+  for (int a = 0; a < M; ++a) {
+    const double re = s * (2 * (a / Q) - Q + 1), im = s * (2 * (a % Q) - Q + 1);
+    if (std::fabs(pts[2 * a] - re) > 1e-6 || std::fabs(pts[2 * a + 1] - im) > 1e-6) return false;
+  }
+  return true;
+}
+
+dmala_status hip_fail(hipError_t e, const char* what) {
+  return fail(DMALA_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+dmala_status run(const void* H, const void* y, const void* sigma2, int32_t n_inst, const Plan& pl,
+                 const dmala_params* p, const dmala_outputs* out, const int8_t* x_from, const int8_t* x_to,
+                 double* eval_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!H || !y || !sigma2) return fail(DMALA_ERR_ARG, "H, y and sigma2 must be non-NULL");
+  if (!ws) return fail(DMALA_ERR_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < pl.total) return fail(DMALA_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, pl.total);
+  if (((uintptr_t)ws & 255) != 0) return fail(DMALA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  const Shape& sh = pl.sh;
+  unsigned char* base = (unsigned char*)ws;
+
+  SetupArgs sa{};
+  sa.H = H; sa.y = y; sa.sigma2 = sigma2;
+  sa.ws_inst = base + pl.inst_off; sa.inst_stride = sh.inst_bytes;
+  sa.n_inst = n_inst; sa.nt = sh.nt; sa.nr = sh.nr; sa.Q = sh.Q; sa.N = sh.N; sa.Npad = sh.Npad;
+  sa.RT = sh.RT; sa.KB = sh.KB; sa.fp64 = sh.fp64; sa.pm = sh.pm; sa.naive = pl.naive ? 1 : 0;
+  sa.tau = pl.tau; sa.alpha_mult = pl.am; sa.beta_mult = pl.bm; sa.gamma_mult = pl.gm;
+  hipError_t e = launch_setup(sa, stream);
+  if (e != hipSuccess) return hip_fail(e, "setup launch");
+
+  SamplerArgs ka{};
+  ka.ws_inst = base + pl.inst_off; ka.inst_stride = sh.inst_bytes;
+  ka.ws_state = base + pl.state_off; ka.state_stride = sh.state_bytes;
+  ka.n_inst = n_inst; ka.N = sh.N; ka.Npad = sh.Npad; ka.C = sh.C; ka.Cpad = sh.Cpad; ka.T = sh.T;
+  ka.key0 = (uint32_t)(p->seed & 0xFFFFFFFFu); ka.key1 = (uint32_t)(p->seed >> 32);
+  ka.frag_bytes = (int)sh.frag_bytes;
+  const bool eval = eval_out != nullptr;
+  if (eval) {
+    ka.x_from = x_from; ka.x_to = x_to; ka.eval_out = eval_out;
+  } else if (out) {
+    ka.final_state = out->final_state; ka.accept_count = out->accept_count;
+    ka.trace_accept = out->trace_accept; ka.trace_hash = out->trace_hash;
+    ka.trace_words = (sh.T + 31) / 32;
+  }
+  e = launch_sampler(sh, ka, eval, stream);
+  if (e != hipSuccess) return hip_fail(e, "sampler launch");
+  if (eval || !out) return DMALA_OK;
+
+  if (out->symbols || out->marginals || out->llrs || out->best_energy || out->marginals_mc) {
+    EstArgs ea{};
+    ea.H = H; ea.y = y; ea.sigma2 = sigma2;
+    ea.ws_inst = base + pl.inst_off; ea.inst_stride = sh.inst_bytes;
+    ea.ws_state = base + pl.state_off; ea.state_stride = sh.state_bytes;
+    ea.ws_est = base + pl.est_off; ea.est_stride = sh.est_bytes;
+    ea.n_inst = n_inst; ea.nt = sh.nt; ea.nr = sh.nr; ea.Q = sh.Q; ea.N = sh.N; ea.Npad = sh.Npad;
+    ea.C = sh.C; ea.Cpad = sh.Cpad; ea.fp64 = sh.fp64;
+    ea.symbols = out->symbols; ea.marginals = out->marginals; ea.llrs = out->llrs;
+    ea.best_energy = out->best_energy; ea.marginals_mc = out->marginals_mc;
+    e = launch_estimate(ea, stream);
+    if (e != hipSuccess) return hip_fail(e, "estimator launch");
+  }
+  return DMALA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dmala_workspace_size(int32_t n_inst, int32_t nt, int32_t nr, int32_t qam_order, const dmala_params* params) {
+  Plan pl;
+  if (make_plan(n_inst, nt, nr, qam_order, params, pl) != DMALA_OK) return 0;
+  g_err.clear();
+  return pl.total;
+}
+
+dmala_status dmala_detect(const void* H, const void* y, const void* sigma2, int32_t n_inst, int32_t nt, int32_t nr,
+                          int32_t qam_order, const float* constellation, const dmala_params* params,
+                          const dmala_outputs* out, void* workspace, size_t workspace_bytes, dmala_stream_t stream) {
+  Plan pl;
+  dmala_status st = make_plan(n_inst, nt, nr, qam_order, params, pl);
+  if (st != DMALA_OK) return st;
+  if (constellation && !canonical_qam(constellation, qam_order))
+    return fail(DMALA_ERR_UNSUPPORTED, "constellation is not the canonical unit-energy square %d-QAM", qam_order);
+  st = run(H, y, sigma2, n_inst, pl, params, out, nullptr, nullptr, nullptr, workspace, workspace_bytes,
+           (hipStream_t)stream);
+  if (st == DMALA_OK) g_err.clear();
+  return st;
+}
+
+dmala_status dmala_debug_eval(const void* H, const void* y, const void* sigma2, int32_t n_inst, int32_t nt, int32_t nr,
+                              int32_t qam_order, const dmala_params* params, const int8_t* x_from, const int8_t* x_to,
+                              int32_t n_pairs, double* out, void* workspace, size_t workspace_bytes,
+                              dmala_stream_t stream) {
+  if (!params) return fail(DMALA_ERR_ARG, "params is NULL");
+  if (!x_from || !x_to || !out) return fail(DMALA_ERR_ARG, "x_from, x_to and out must be non-NULL");
+  dmala_params p = *params;
+  p.n_chains = n_pairs;
+  p.n_iters = 0;
+  Plan pl;
+  dmala_status st = make_plan(n_inst, nt, nr, qam_order, &p, pl);
+  if (st != DMALA_OK) return st;
+  st = run(H, y, sigma2, n_inst, pl, &p, nullptr, x_from, x_to, out, workspace, workspace_bytes, (hipStream_t)stream);
+  if (st == DMALA_OK) g_err.clear();
+  return st;
+}
+
+const char* dmala_last_error(void) { return g_err.c_str(); }
+
+const char* dmala_version(void) { return "dmala-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

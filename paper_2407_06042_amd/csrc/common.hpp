@@ -1,0 +1,135 @@
+// Shared declarations of the DMALA HIP library (host launchers and device helpers).
+//
+// Notation (index units): a chain state is a vector of level indices k_n in
+// [0, Q), real dimension n = 2m (Re x_m) or 2m+1 (Im x_m); the real value is
+// s * lv_n with lv_n = 2 k_n - Q + 1 an odd integer.  All log-probabilities in
+// the kernels are base-2 (exp2/log2 are the native transcendental ops).
+//
+// With the parameters of the preconditioned proposal (Remark after Algorithm
+// 1, tempered as in Algorithm 2) the factorised proposal of eq. dis_prop_fac2
+// over the levels j of dimension n is a discretised Gaussian in j:
+//     log2 q_n(j | x) = -kL (j - mu_n)^2 - lz_n,
+//     mu_n = k_n - shift_n,   shift = c_m (A x - b),   A = M G,  b = M z,
+// with G = H^T H, z = H^T y, M = (G + gamma I)^-1, c_m = alpha / (2 tau sigma^2 s),
+// kL = log2(e) * 2 s^2 / (alpha beta) and lz_n the log2 normaliser.  The naive
+// proposal (eq. exp_fac) is the same with A = G, b = z and beta -> 1.  The
+// tempered log acceptance ratio of eq. acc_prob uses the exact identity
+//     E(x') - E(x) = (x' - x)^T (g(x) + g(x')),   g = G x - z,   E = ||y - Hx||^2,
+// so the sampler carries the energy gradient eg = (2 s log2(e) / (tau sigma^2)) g
+// (in log2 units) and never forms a residual inside the loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dmala {
+
+constexpr double kLog2e = 1.4426950408889634074;
+
+// Per-instance constants written by the setup kernel (first 256 bytes of each
+// instance block of the workspace).
+struct InstParams {
+  double yy;       // ||y||^2
+  double eunit;    // tau sigma^2 / log2(e): energy per log2 unit of the tempered metric
+  double kL;       // log2(e) * 2 s^2 / (alpha beta')
+  double rho;      // naive proposal: shift = rho * eg
+  double sigma2;
+  double s;        // level step
+  double tau;
+  float scaleP;    // 2^-e of the packed proposal matrix
+  float scaleE;    // 2^-e of the packed energy matrix
+  int32_t nonfinite;
+  int32_t pad_[3];
+};
+static_assert(sizeof(InstParams) <= 256, "params block");
+constexpr int kParamBytes = 256;
+
+// Packing modes of the proposal matrix in the MFMA path.
+enum PMode : int { PM_NAIVE = 0, PM_F16X2 = 1, PM_F16X1 = 2, PM_BF16X1 = 3 };
+constexpr int kEPasses = 3;  // energy matrix: hi/mid/lo fp16 split
+
+__host__ __device__ constexpr int p_passes(int pm) { return pm == PM_NAIVE ? 0 : (pm == PM_F16X2 ? 2 : 1); }
+
+// Geometry of one problem shape.
+struct Shape {
+  int nt, nr, M, Q, N, Npad, RT, KB, C, Cpad, T;
+  int fp64;        // 1: double path
+  int pm;          // PMode (MFMA path)
+  size_t inst_bytes;   // per-instance setup block
+  size_t frag_bytes;   // MFMA fragments (MFMA path)
+  size_t state_bytes;  // per-instance sampler->estimator block
+  size_t est_bytes;    // per-instance estimator scratch
+};
+
+// Offsets inside the per-instance state block.
+struct StateOff {
+  size_t k, kbest, ebest, nacc, end;
+};
+__host__ __device__ inline StateOff state_offsets(int Cpad, int Npad) {
+  StateOff o;
+  o.k = 0;
+  o.kbest = o.k + (size_t)Cpad * Npad;
+  o.ebest = (o.kbest + (size_t)Cpad * Npad + 15) & ~(size_t)15;
+  o.nacc = o.ebest + (size_t)Cpad * 8;
+  o.end = (o.nacc + (size_t)Cpad * 4 + 255) & ~(size_t)255;
+  return o;
+}
+
+struct SetupArgs {
+  const void* H; const void* y; const void* sigma2;
+  unsigned char* ws_inst; size_t inst_stride;
+  int n_inst, nt, nr, Q, N, Npad, RT, KB, fp64, pm, naive;
+  double tau, alpha_mult, beta_mult, gamma_mult;
+};
+
+struct SamplerArgs {
+  const unsigned char* ws_inst; size_t inst_stride;
+  unsigned char* ws_state; size_t state_stride;
+  int n_inst, N, Npad, C, Cpad, T;
+  uint32_t key0, key1;
+  int frag_bytes;
+  int8_t* final_state; int32_t* accept_count; uint32_t* trace_accept; uint32_t* trace_hash;
+  int trace_words;
+  // debug-eval mode
+  const int8_t* x_from; const int8_t* x_to; double* eval_out;
+};
+
+struct EstArgs {
+  const void* H; const void* y; const void* sigma2;
+  const unsigned char* ws_inst; size_t inst_stride;
+  const unsigned char* ws_state; size_t state_stride;
+  unsigned char* ws_est; size_t est_stride;
+  int n_inst, nt, nr, Q, N, Npad, C, Cpad, fp64;
+  int32_t* symbols; float* marginals; float* llrs; float* best_energy; float* marginals_mc;
+};
+
+// Host launchers (defined in the .hip translation units).
+hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
+hipError_t launch_sampler(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s);
+hipError_t launch_estimate(const EstArgs& a, hipStream_t s);
+size_t sampler_lds_bytes(const Shape& sh);
+
+// ------------------------------------------------------------------ device helpers
+
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the 4x32 S-box, key bumped
+// by the Weyl constants between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[0] = n0; c[1] = (uint32_t)p1; c[2] = n2; c[3] = (uint32_t)p0;
+  }
+}
+
+__device__ __forceinline__ float u24f(uint32_t w) { return (float)(w >> 8) * 5.9604644775390625e-08f; }
+__device__ __forceinline__ double u24d(uint32_t w) { return (double)(w >> 8) * 5.9604644775390625e-08; }
+__device__ __forceinline__ uint32_t low_bytes24(uint32_t a, uint32_t b, uint32_t c) {
+  return (a & 0xFFu) | ((b & 0xFFu) << 8) | ((c & 0xFFu) << 16);
+}
+__device__ __forceinline__ uint32_t hash_mult(int n) { return (uint32_t)(2 * n + 1) * 0x9E3779B1u; }
+
+}  // namespace dmala

@@ -1,0 +1,8 @@
+// Sampler instances: float arithmetic, proposal mode PM_NAIVE.
+#include "sampler_impl.hpp"
+
+namespace dmala {
+hipError_t launch_sampler_naive(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+  return launch_rt<float, PM_NAIVE>(sh, a, eval, s);
+}
+}  // namespace dmala

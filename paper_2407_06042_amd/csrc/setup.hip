@@ -1,0 +1,256 @@
+// Instance setup: Gram matrix, matched filter, preconditioner and packing.
+//
+// One workgroup per instance, float64 arithmetic.  Computes in the complex
+// form (the real-equivalent matrices of eq. sys_model are expanded only when
+// packing):
+//   G = H^H H, z = H^H y, ||y||^2                      (gradient of eq. grad: grad f = -(2/sigma^2)(Gx - z))
+//   M = (G + gamma I)^-1 by in-place Gauss-Jordan       (preconditioner of the Remark after Algorithm 1;
+//                                                         G + gamma I is Hermitian positive definite, so no pivoting)
+//   A = M G = I - gamma M,  b = M z                     (so that M grad f = -(2/sigma^2)(A x - b))
+// and writes, scaled to the index units of the sampler (see common.hpp),
+//   energy matrix  EG = 2 s^2 log2(e)/(tau sigma^2) * R(G),  ez = 2 s log2(e)/(tau sigma^2) * R(z)
+//   proposal matrix P = alpha/(2 tau sigma^2) * R(A),       pb = alpha/(2 tau sigma^2 s) * R(b)
+// where R(.) is the Re/Im-interleaved real-equivalent.  On the MFMA path each
+// matrix is scaled by a power of two and split into fp16 (or bf16) terms laid
+// out as 16x16x32 MFMA A-operand fragments; on the float64 path it is stored
+// as a dense row-major array.
+#include "common.hpp"
+
+namespace dmala {
+
+struct cd { double re, im; };
+__device__ __forceinline__ cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cd cconjmul(cd a, cd b) { return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re}; }
+
+// Entry (n, n2) of the interleaved real-equivalent of complex X (ld = nt).
+__device__ __forceinline__ double realeq(const cd* X, int nt, int n, int n2) {
+  const cd v = X[(n >> 1) * nt + (n2 >> 1)];
+  const int a = n & 1, b = n2 & 1;
+  return (a == b) ? v.re : (a == 0 ? -v.im : v.im);
+}
+__device__ __forceinline__ double realeq_vec(const cd* v, int n) { return (n & 1) ? v[n >> 1].im : v[n >> 1].re; }
+
+__device__ double block_reduce(double v, double* red, bool is_max) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = is_max ? fmax(red[tid], red[tid + w]) : red[tid] + red[tid + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Pack c * R(X) (N x N, zero-padded to Npad) into MFMA fragments.
+// npass = 3 (fp16 lo, mid, hi), 2 (fp16 lo, hi) or 1 (fp16 or bf16 when bf16 != 0).
+// Fragment (pass p, row tile rt, K block kb) lane l element j holds entry
+// (16 rt + l%16, 16 (2 kb + j/4) + 4 (l/16) + j%4): the K order matches the
+// dimensions each lane owns in the accumulator layout, so the sampler builds
+// the B operand from its own registers.
+__device__ float pack_fragments(const cd* X, double c, int nt, int N, int RT, int KB, int npass, int bf16,
+                                unsigned char* dst, double* red) {
+  double mx = 0.0;
+  for (int e = threadIdx.x; e < nt * nt; e += blockDim.x) mx = fmax(mx, fmax(fabs(X[e].re), fabs(X[e].im)));
+  mx = block_reduce(mx, red, true) * fabs(c);
+  int ex = 0;
+  if (mx > 0.0) frexp(mx, &ex);
+  const int e2 = 14 - ex;  // scaled max in [2^13, 2^14)
+  const double sc = ldexp(c, e2);
+  const int items = npass * RT * KB * 64;
+  for (int it = threadIdx.x; it < items; it += blockDim.x) {
+    const int l = it & 63;
+    const int t = it >> 6;
+    const int kb = t % KB;
+    const int rt = (t / KB) % RT;
+    const int p = t / (KB * RT);
+    const int n = 16 * rt + (l & 15);
+    union { _Float16 h[8]; __bf16 b[8]; uint4 u; } frag;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int n2 = 16 * (2 * kb + (j >> 2)) + 4 * (l >> 4) + (j & 3);
+      const double v = (n < N && n2 < N) ? sc * realeq(X, nt, n, n2) : 0.0;
+      if (bf16) {
+        frag.b[j] = (__bf16)(float)v;
+      } else {
+        const _Float16 hi = (_Float16)(float)v;
+        const double r1 = v - (double)hi;
+        const _Float16 mid = (_Float16)(float)r1;
+        const double r2 = r1 - (double)mid;
+        const _Float16 lo = (_Float16)(float)r2;
+        // storage order = accumulation order: small terms first
+        _Float16 val;
+        if (npass == 3) val = (p == 0) ? lo : (p == 1 ? mid : hi);
+        else if (npass == 2) val = (p == 0) ? (_Float16)(float)r1 : hi;
+        else val = hi;
+        frag.h[j] = val;
+      }
+    }
+    *(uint4*)(dst + (size_t)((p * RT + rt) * KB + kb) * 1024 + l * 16) = frag.u;
+  }
+  return (float)ldexp(1.0, -e2);
+}
+
+// Dense row-major double copy of c * R(X), zero-padded to Npad x Npad.
+__device__ void pack_dense(const cd* X, double c, int nt, int N, int Npad, double* dst) {
+  for (int e = threadIdx.x; e < Npad * Npad; e += blockDim.x) {
+    const int n = e / Npad, n2 = e % Npad;
+    dst[e] = (n < N && n2 < N) ? c * realeq(X, nt, n, n2) : 0.0;
+  }
+}
+
+template <typename TIn>
+__global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
+  const int b = blockIdx.x, tid = threadIdx.x, nt = a.nt, nr = a.nr, N = a.N, Npad = a.Npad;
+  const TIn* H = (const TIn*)a.H + 2 * (size_t)b * nt * nr;
+  const TIn* y = (const TIn*)a.y + 2 * (size_t)b * nr;
+  const double sigma2 = (double)((const TIn*)a.sigma2)[b];
+  extern __shared__ double smem_setup[];
+  cd* W = (cd*)smem_setup;
+  cd* z = W + nt * nt;
+  cd* bv = z + nt;
+  cd* rowp = bv + nt;
+  cd* colp = rowp + nt;
+  double* red = (double*)(colp + nt);
+  unsigned char* blk = a.ws_inst + (size_t)b * a.inst_stride;
+
+  const int Q = a.Q, M = Q * Q;
+  const double s = sqrt(3.0 / (2.0 * (M - 1)));
+  const double tau = a.tau;
+  const double alpha = a.alpha_mult * sigma2;
+  const double beta = a.naive ? 1.0 : a.beta_mult * s * s / sigma2;
+  const double gamma = a.gamma_mult * sigma2 / (2.0 * s * s);
+
+  // G = H^H H, z = H^H y, ||y||^2, finiteness of the inputs
+  double nonfinite = 0.0;
+  for (int e = tid; e < nt * nt; e += blockDim.x) {
+    const int m = e / nt, m2 = e % nt;
+    cd acc = {0.0, 0.0};
+    for (int i = 0; i < nr; ++i) {
+      const cd hm = {(double)H[2 * ((size_t)m * nr + i)], (double)H[2 * ((size_t)m * nr + i) + 1]};
+      const cd hm2 = {(double)H[2 * ((size_t)m2 * nr + i)], (double)H[2 * ((size_t)m2 * nr + i) + 1]};
+      acc = cadd(acc, cconjmul(hm, hm2));
+    }
+    W[e] = acc;
+    if (!isfinite(acc.re) || !isfinite(acc.im)) nonfinite = 1.0;
+  }
+  for (int m = tid; m < nt; m += blockDim.x) {
+    cd acc = {0.0, 0.0};
+    for (int i = 0; i < nr; ++i) {
+      const cd hm = {(double)H[2 * ((size_t)m * nr + i)], (double)H[2 * ((size_t)m * nr + i) + 1]};
+      const cd yi = {(double)y[2 * i], (double)y[2 * i + 1]};
+      acc = cadd(acc, cconjmul(hm, yi));
+    }
+    z[m] = acc;
+  }
+  double yy = 0.0;
+  for (int i = tid; i < nr; i += blockDim.x) {
+    const double re = (double)y[2 * i], im = (double)y[2 * i + 1];
+    yy += re * re + im * im;
+  }
+  __syncthreads();
+  yy = block_reduce(yy, red, false);
+  if (!isfinite(yy) || !(sigma2 > 0.0)) nonfinite = 1.0;
+  nonfinite = block_reduce(nonfinite, red, true);
+
+  const double cE = 2.0 * s * s * kLog2e / (tau * sigma2);
+  const double cz = 2.0 * s * kLog2e / (tau * sigma2);
+  const double cP = alpha / (2.0 * tau * sigma2);
+  const double cb = alpha / (2.0 * tau * sigma2 * s);
+  const int npP = p_passes(a.pm);
+  unsigned char* frag = blk + kParamBytes;
+  float scaleE = 1.0f, scaleP = 1.0f;
+
+  // energy matrix and vector
+  if (a.fp64) {
+    double* EGd = (double*)(blk + kParamBytes) + (size_t)Npad * Npad;
+    pack_dense(W, cE, nt, N, Npad, EGd);
+    double* ezd = (double*)(blk + kParamBytes) + 2 * (size_t)Npad * Npad + Npad;
+    for (int n = tid; n < Npad; n += blockDim.x) ezd[n] = n < N ? cz * realeq_vec(z, n) : 0.0;
+  } else {
+    scaleE = pack_fragments(W, cE, nt, N, a.RT, a.KB, kEPasses, 0, frag + (size_t)npP * a.RT * a.KB * 1024, red);
+    float* ezf = (float*)(frag + (size_t)(npP + kEPasses) * a.RT * a.KB * 1024) + Npad;
+    for (int n = tid; n < Npad; n += blockDim.x) ezf[n] = n < N ? (float)(cz * realeq_vec(z, n)) : 0.0f;
+  }
+  __syncthreads();
+
+  if (!a.naive) {
+    // W <- (G + gamma I)^-1 by in-place Gauss-Jordan
+    for (int m = tid; m < nt; m += blockDim.x) W[m * nt + m].re += gamma;
+    __syncthreads();
+    for (int p = 0; p < nt; ++p) {
+      for (int j = tid; j < nt; j += blockDim.x) { rowp[j] = W[p * nt + j]; colp[j] = W[j * nt + p]; }
+      __syncthreads();
+      const cd piv = rowp[p];
+      const double den = piv.re * piv.re + piv.im * piv.im;
+      const cd inv = {piv.re / den, -piv.im / den};
+      for (int e = tid; e < nt * nt; e += blockDim.x) {
+        const int i = e / nt, j = e % nt;
+        cd v;
+        if (i == p && j == p) v = inv;
+        else if (i == p) v = cmul(rowp[j], inv);
+        else if (j == p) { const cd t = cmul(colp[i], inv); v = {-t.re, -t.im}; }
+        else { const cd t = cmul(cmul(colp[i], rowp[j]), inv); v = {W[e].re - t.re, W[e].im - t.im}; }
+        W[e] = v;
+      }
+      __syncthreads();
+    }
+    // b = M z, then W <- A = I - gamma M
+    for (int m = tid; m < nt; m += blockDim.x) {
+      cd acc = {0.0, 0.0};
+      for (int j = 0; j < nt; ++j) acc = cadd(acc, cmul(W[m * nt + j], z[j]));
+      bv[m] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < nt * nt; e += blockDim.x) {
+      const int i = e / nt, j = e % nt;
+      W[e] = {(i == j ? 1.0 : 0.0) - gamma * W[e].re, -gamma * W[e].im};
+    }
+    __syncthreads();
+    if (a.fp64) {
+      pack_dense(W, cP, nt, N, Npad, (double*)(blk + kParamBytes));
+      double* pbd = (double*)(blk + kParamBytes) + 2 * (size_t)Npad * Npad;
+      for (int n = tid; n < Npad; n += blockDim.x) pbd[n] = n < N ? cb * realeq_vec(bv, n) : 0.0;
+    } else {
+      scaleP = pack_fragments(W, cP, nt, N, a.RT, a.KB, npP, a.pm == PM_BF16X1, frag, red);
+      float* pbf = (float*)(frag + (size_t)(npP + kEPasses) * a.RT * a.KB * 1024);
+      for (int n = tid; n < Npad; n += blockDim.x) pbf[n] = n < N ? (float)(cb * realeq_vec(bv, n)) : 0.0f;
+    }
+  } else if (a.fp64) {
+    double* Pd = (double*)(blk + kParamBytes);
+    for (int e = tid; e < Npad * Npad; e += blockDim.x) Pd[e] = 0.0;
+    double* pbd = Pd + 2 * (size_t)Npad * Npad;
+    for (int n = tid; n < Npad; n += blockDim.x) pbd[n] = 0.0;
+  }
+
+  if (tid == 0) {
+    InstParams ip;
+    ip.yy = yy;
+    ip.eunit = tau * sigma2 / kLog2e;
+    ip.kL = kLog2e * 2.0 * s * s / (alpha * beta);
+    ip.rho = alpha / (4.0 * s * s * kLog2e);
+    ip.sigma2 = sigma2;
+    ip.s = s;
+    ip.tau = tau;
+    ip.scaleP = scaleP;
+    ip.scaleE = scaleE;
+    ip.nonfinite = nonfinite > 0.0 ? 1 : 0;
+    ip.pad_[0] = ip.pad_[1] = ip.pad_[2] = 0;
+    *(InstParams*)blk = ip;
+  }
+}
+
+hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
+  const size_t lds = (size_t)(a.nt * a.nt + 4 * a.nt) * sizeof(cd) + 256 * sizeof(double);
+  auto k = a.fp64 ? setup_kernel<double> : setup_kernel<float>;
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k, dim3(a.n_inst), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace dmala

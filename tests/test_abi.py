@@ -1,0 +1,56 @@
+"""The C-ABI library loads, exports every declared entry point, and rejects bad arguments on the host."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2407_06042_amd as dm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dmala.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmala_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = dm.lib()
+    names = _declared()
+    assert set(names) == set(dm.EXPORTED)
+    for n in names:
+        assert hasattr(L, n), n
+    assert b"gfx950" in L.dmala_version()
+
+
+def test_workspace_size_validation():
+    p = dm.make_params(32, 100, 1)
+    assert dm.workspace_size(8, 32, 32, 64, p) > 8 * 32 * 1024
+    for args, msg in [((8, 32, 32, 8), "qam_order"), ((0, 32, 32, 64), "n_inst"), ((8, 0, 4, 16), "nt"),
+                      ((8, 65, 65, 16), "nt > 64"), ((8, 4, 5000, 16), "nr")]:
+        with pytest.raises(dm.DmalaError) as e:
+            dm.workspace_size(*args, p)
+        assert msg in str(e.value)
+    with pytest.raises(dm.DmalaError):
+        dm.workspace_size(8, 4, 4, 16, dm.make_params(0, 10, 1))
+    with pytest.raises(dm.DmalaError):
+        dm.workspace_size(8, 40, 40, 16, dm.make_params(16, 10, 1, precision="fp64"))
+
+
+def test_detect_rejects_bad_workspace_before_launch():
+    L = dm.lib()
+    p = dm.make_params(16, 10, 1)
+    o = dm.Outputs()
+    fake = ctypes.c_void_p(0x1000)
+    need = dm.workspace_size(2, 4, 4, 16, p)
+    st = L.dmala_detect(fake, fake, fake, 2, 4, 4, 16, None, ctypes.byref(p), ctypes.byref(o), None, need, None)
+    assert st == -4 and "workspace" in dm.last_error()
+    st = L.dmala_detect(fake, fake, fake, 2, 4, 4, 16, None, ctypes.byref(p), ctypes.byref(o), ctypes.c_void_p(0x10000), need - 1, None)
+    assert st == -4 and "too small" in dm.last_error()
+    st = L.dmala_detect(None, fake, fake, 2, 4, 4, 16, None, ctypes.byref(p), ctypes.byref(o), ctypes.c_void_p(0x10000), need, None)
+    assert st == -1
+    bad = (ctypes.c_float * 32)(*([0.5] * 32))
+    st = L.dmala_detect(fake, fake, fake, 2, 4, 4, 16, bad, ctypes.byref(p), ctypes.byref(o), ctypes.c_void_p(0x10000), need, None)
+    assert st == -2 and "constellation" in dm.last_error()

@@ -1,0 +1,166 @@
+"""Parity of the HIP detector with the float64 oracle (needs an MI355X).
+
+Chains are compared trajectory by trajectory on the shared counter-based random
+numbers: a chain must follow the oracle exactly until its first near-tie draw
+(a categorical or MH decision whose oracle margin is below the stated
+threshold).  Estimators are compared on identical sample lists.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dmala as odm
+from oracle import exact
+from tests.helpers import gpu_available, run_gpu, run_oracle, compare_chains
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+# Near-tie thresholds (oracle margins).  FP64 path: decisions agree unless the
+# oracle margin is within a few ulps.  FP32 path: categorical CDF values carry
+# about 1e-6 relative error; the MH log ratio carries the fp32 rounding of the
+# energy difference (see the design notes for the derivation).
+EPS64 = (1e-9, 1e-9)
+EPS32 = (2e-5, 2e-3)
+
+
+def _print(tag, **kv):
+    print(tag, " ".join("%s=%s" % (k, v) for k, v in kv.items()), flush=True)
+
+
+@pytest.mark.parametrize("proposal", ["precond", "naive"])
+def test_fp64_chain_identity_small(proposal):
+    """4x4 16-QAM at 10 dB, 16 chains x 50 transitions, float64: every chain identical."""
+    batch = W.c1_small(n_inst=12)
+    seed = 0x1234
+    b, g = run_gpu(batch, 16, 50, seed, "fp64", proposal)
+    for i in range(12):
+        o = run_oracle(b, i, 16, 50, seed, proposal, estimators=False)
+        n_id, n_fd, bad = compare_chains(g["trace_hash"][i], o, *EPS64)
+        _print("fp64", inst=i, identical=n_id, flagged=n_fd, bad=bad[:3])
+        assert not bad
+        assert n_id >= 15
+        same = [c for c in range(16) if np.array_equal(g["trace_hash"][i, c], o["trace"]["hash"][:, c])]
+        np.testing.assert_array_equal(g["final_state"][i][same], o["k"][same])
+        np.testing.assert_array_equal(g["accept_count"][i][same], o["n_acc"][same])
+
+
+def test_fp64_outputs_match_oracle():
+    """Hard decision, LLRs and marginals of the float64 path vs the oracle on the same chains."""
+    batch = W.c1_small(n_inst=8)
+    seed = 99
+    b, g = run_gpu(batch, 16, 50, seed, "fp64")
+    for i in range(8):
+        o = run_oracle(b, i, 16, 50, seed)
+        if not np.array_equal(g["final_state"][i], o["k"]):
+            continue
+        np.testing.assert_array_equal(g["symbols"][i], o["symbols"])
+        np.testing.assert_allclose(g["best_energy"][i], o["best_energy"], rtol=1e-5)
+        np.testing.assert_allclose(g["marginals"][i], o["marginals"], atol=1e-6)
+        np.testing.assert_allclose(g["llrs"][i], o["llr"], atol=1e-4, rtol=1e-5)
+        np.testing.assert_allclose(g["marginals_mc"][i], o["marginals_mc"], atol=1e-7)
+
+
+@pytest.mark.parametrize("snr", [16.0, 22.0, 28.0])
+@pytest.mark.parametrize("precision,proposal", [("fp32", "precond"), ("fp32", "naive")])
+def test_fp32_chain_identity_32x32(snr, precision, proposal):
+    """32x32 64-QAM, 32 chains x 100 transitions: chains follow the oracle up to flagged near-ties."""
+    batch = W.make_batch(32, 32, 64, snr, 4, seed=int(snr), cfg_id=2)
+    seed = 0x2407060420 + int(snr)
+    b, g = run_gpu(batch, 32, 100, seed, precision, proposal)
+    tot_id = tot = 0
+    for i in range(4):
+        o = run_oracle(b, i, 32, 100, seed, proposal, estimators=False)
+        n_id, n_fd, bad = compare_chains(g["trace_hash"][i], o, *EPS32)
+        _print("fp32", snr=snr, prop=proposal, inst=i, identical=n_id, flagged=n_fd, bad=bad[:3])
+        assert not bad
+        tot_id += n_id
+        tot += 32
+    assert tot_id >= 0.75 * tot
+
+
+def test_fp32_estimators_on_gpu_samples():
+    """Estimator parity given identical sample lists (GPU final states fed to the oracle)."""
+    batch = W.make_batch(32, 32, 64, 20.0, 3, seed=5, cfg_id=2)
+    b, g = run_gpu(batch, 32, 100, 7, "fp32")
+    for i in range(3):
+        prob = odm.Problem(b.H[i], b.y[i], b.sigma2[i], b.M)
+        k = g["final_state"][i].astype(np.int64)
+        m_or = odm.marginals_is(prob, k)
+        l_or = odm.llr_is(prob, k)
+        np.testing.assert_allclose(g["marginals"][i], m_or, atol=1e-4)
+        np.testing.assert_allclose(g["llrs"][i], l_or, atol=2e-3 * np.maximum(1.0, np.abs(l_or)).max())
+        np.testing.assert_allclose(g["marginals_mc"][i], odm.marginals_mc(prob.Q, prob.Nt, k), atol=1e-6)
+        # the reported hard decision is one of the chains' states and its energy is reported correctly
+        sym = g["symbols"][i]
+        x = np.zeros(prob.N, dtype=np.int64)
+        x[0::2], x[1::2] = sym // prob.Q, sym % prob.Q
+        np.testing.assert_allclose(g["best_energy"][i], prob.energy(prob.x_of(x)), rtol=1e-4, atol=1e-6)
+
+
+@pytest.mark.parametrize("nt,nr,M,C,T", [(3, 5, 16, 20, 30), (1, 2, 4, 16, 40), (5, 5, 256, 16, 20), (8, 16, 64, 33, 25)])
+def test_edge_shapes_fp32(nt, nr, M, C, T):
+    """Odd antenna counts, Nr != Nt, QPSK and 256-QAM, chain counts off the 16-chain tile."""
+    batch = W.make_batch(nt, nr, M, 15.0, 3, seed=nt * 100 + M)
+    b, g = run_gpu(batch, C, T, 31337, "fp32")
+    for i in range(3):
+        o = run_oracle(b, i, C, T, 31337, estimators=False)
+        n_id, n_fd, bad = compare_chains(g["trace_hash"][i], o, *EPS32)
+        _print("edge", nt=nt, nr=nr, M=M, C=C, inst=i, identical=n_id, flagged=n_fd, bad=bad[:3])
+        assert not bad
+
+
+def test_zero_iterations_gives_initial_states():
+    batch = W.make_batch(6, 6, 16, 12.0, 2, seed=3)
+    b, g = run_gpu(batch, 16, 0, 555, "fp32", trace=False)
+    for i in range(2):
+        o = run_oracle(b, i, 16, 0, 555, trace=False, estimators=False)
+        np.testing.assert_array_equal(g["final_state"][i], o["k"])
+        np.testing.assert_array_equal(g["accept_count"][i], 0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16", "fp64"])
+@pytest.mark.parametrize("nt,M", [(2, 4), (1, 16), (2, 16)])
+def test_device_kernel_detailed_balance(precision, nt, M):
+    """Transition matrix from the device's own q and acceptance: stochastic and reversible w.r.t. pi_a.
+
+    The proposal values agree with the oracle to the precision of the mode.
+    """
+    import torch
+    import paper_2407_06042_amd as dm
+    b = W.make_batch(nt, 2, M, 8.0, 1, seed=17 + nt + M)
+    b = b.as_precision(np.float64 if precision == "fp64" else np.float32)
+    prob = odm.Problem(b.H[0], b.y[0], b.sigma2[0], M)
+    K = exact.all_states(prob.N, prob.Q)
+    S = len(K)
+    xf = np.repeat(K, S, axis=0)
+    xt = np.tile(K, (S, 1))
+    # at most 1024 pairs per instance: replicate the problem over instances
+    per = min(1024, S * S)
+    rep = (S * S) // per
+    Hcm, y, s2 = dm.device_inputs(np.repeat(b.H, rep, 0), np.repeat(b.y, rep, 0), np.repeat(b.sigma2, rep, 0), precision)
+    out = dm.debug_eval(Hcm, y, s2, M, torch.from_numpy(xf.reshape(rep, per, -1)).cuda(),
+                        torch.from_numpy(xt.reshape(rep, per, -1)).cuda(), precision=precision).cpu().numpy()
+    out = out.reshape(S * S, 4)
+    LQ = out[:, 0].reshape(S, S)          # log q(x_j | x_i)
+    DF = out[:, 2].reshape(S, S)          # f(x_j)/tau - f(x_i)/tau as the device computes it
+    R = out[:, 3].reshape(S, S)           # log acceptance ratio of i -> j
+    P = np.exp(LQ + np.minimum(0.0, R))
+    np.fill_diagonal(P, 0.0)
+    P[np.arange(S), np.arange(S)] = 1.0 - P.sum(1)
+    assert np.abs(P.sum(1) - 1).max() < 1e-9
+    assert P[~np.eye(S, dtype=bool)].min() > 0 and np.diag(P).min() > 0
+    # reversible with respect to the device's own tempered target exp(DF[0, j])
+    lt = DF[0] - DF[0].max()
+    pt = np.exp(lt) / np.exp(lt).sum()
+    F = pt[:, None] * P
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    assert np.abs(F - F.T).max() < tol * max(1.0, F.max())
+    # ... which is pi_a up to the arithmetic of the energy term, and the proposal agrees with the oracle
+    pi = np.exp(exact.log_target(prob, K))
+    assert exact.tv(pt, pi) < (1e-10 if precision == "fp64" else 1e-4)
+    _, LQo, LAo = exact.transition_matrix(prob, K)
+    qtol = {"fp64": 1e-9, "fp32": 1e-4, "bf16": 0.3, "fp16": 0.05}[precision]
+    assert np.abs(LQ - LQo).max() < qtol * max(1.0, np.abs(LQo).max())
+    fo = prob.f(prob.x_of(K)) / prob.tau
+    ftol = 1e-9 if precision == "fp64" else 1e-4
+    np.testing.assert_allclose(DF, fo[None, :] - fo[:, None], atol=ftol * max(1.0, np.abs(fo).max()))
