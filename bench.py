@@ -1,0 +1,225 @@
+#!/usr/bin/env python
+"""Throughput of the DMALA detector on one MI355X.
+
+Workload (default): 32x32 MIMO, 64-QAM (unit energy), i.i.d. Rayleigh CN(0, 1/Nr),
+SNR 16..28 dB in 2 dB steps with 1024 realisations per SNR (7168 detection
+problems), 32 chains x 100 MH transitions each, float32-class arithmetic,
+preconditioned proposal, tau = 2.  One step = one dmala_detect call over the
+whole batch (setup, sampler and estimator kernels), inputs resident in HBM.
+
+Prints one JSON line: chain-iterations/s (value), detected vectors/s, SER per
+SNR, the BF16-gradient form's throughput and SER, the sampler kernel's
+roofline figures measured with HIP events around that kernel, and the float64
+oracle timed on the host cores on a bounded sample of the same workload.
+"""
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+METRIC = "chain-iterations/s and detected vectors/s at matched SER (plain vs BF16/learned)"
+NT = NR = 32
+M = 64
+CHAINS, ITERS = 32, 100
+SNRS = (16, 18, 20, 22, 24, 26, 28)
+SEED = 0x240706042002
+
+# MI355X published peaks
+PEAK_FP32_VECTOR = 157.3e12
+PEAK_BF16_MFMA = 2.5e15
+
+
+def algorithmic_ops_per_chain_iter(nt, nr, M):
+    """VALU work of one chain-iteration that the method must do (per-unit figure).
+
+    Counts: logits + CDF 6 N Q, exponentials N Q, logarithms N, Philox
+    ceil((N+2)/4) blocks of 10 rounds x 6 ops, energy and MH terms 4 Nr + 2 N
+    (N = 2 Nt real dimensions, Q = sqrt(M)).  The G.x contraction (8 Nt^2
+    flops) runs on MFMA and is reported separately.
+    """
+    N, Q = 2 * nt, int(round(np.sqrt(M)))
+    return 6 * N * Q + N * Q + N + 60 * ((N + 2 + 3) // 4) + 4 * nr + 2 * N
+
+
+def gx_flops_per_chain_iter(nt):
+    return 8 * nt * nt
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("common.hpp", "sampler_impl.hpp", "sampler_f16x2.hip", "setup.hip"):
+        with open(os.path.join(ROOT, "paper_2407_06042_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _oracle_worker(args):
+    import threadpoolctl
+    threadpoolctl.threadpool_limits(1)
+    from oracle import dmala as odm
+    H, y, s2, inst = args
+    t = time.perf_counter()
+    r = odm.detect(H, y, s2, M, CHAINS, ITERS, SEED, instance=inst)
+    return time.perf_counter() - t, r["symbols"]
+
+
+def cpu_baseline(batch, per_snr):
+    """Time the float64 oracle (sampling + estimators) on a bounded sample, all host cores."""
+    import multiprocessing as mp
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    idx = np.concatenate([np.arange(k * 1024, k * 1024 + per_snr) for k in range(len(SNRS))])
+    work = [(batch.H[i], batch.y[i], batch.sigma2[i], int(i)) for i in idx]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, work, chunksize=1)
+    wall = time.perf_counter() - t0
+    cpu = sum(r[0] for r in res)
+    n = len(idx)
+    return dict(value=n * CHAINS * ITERS / wall, unit="chain-iterations/s", cores=cores, kind="oracle",
+                sample="%d of the 7168 problems (%d per SNR), %d chains x %d transitions + estimators, "
+                       "float64 numpy oracle, one process per core; %.1f s CPU in %.1f s wall"
+                       % (n, per_snr, CHAINS, ITERS, cpu, wall),
+                vectors_per_s=n / wall)
+
+
+class HipEvents:
+    def __init__(self, n):
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.ev = []
+        for _ in range(n):
+            e = ctypes.c_void_p()
+            if self.hip.hipEventCreate(ctypes.byref(e)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.ev.append(e.value)
+
+    def elapsed_ms(self, a, b):
+        ms = ctypes.c_float()
+        if self.hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(self.ev[a]), ctypes.c_void_p(self.ev[b])) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return ms.value
+
+
+def run_form(dm, torch, b, precision, steps, warmup):
+    Hcm, y, s2 = dm.device_inputs(b.H, b.y, b.sigma2, precision)
+    B = len(b.sigma2)
+    det = dm.Detector(B, NT, NR, M, CHAINS, ITERS, SEED, precision, "precond")
+    ev = HipEvents(4 * steps)
+    for _ in range(warmup):
+        det(Hcm, y, s2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        out = det(Hcm, y, s2, events=ev.ev[4 * k: 4 * k + 4])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [ev.elapsed_ms(4 * k, 4 * k + 3) for k in range(steps)]
+    samp_ms = [ev.elapsed_ms(4 * k + 1, 4 * k + 2) for k in range(steps)]
+    setup_ms = [ev.elapsed_ms(4 * k, 4 * k + 1) for k in range(steps)]
+    est_ms = [ev.elapsed_ms(4 * k + 2, 4 * k + 3) for k in range(steps)]
+    sym = out["symbols"].cpu().numpy()
+    err = (sym != b.x_idx)
+    ser = {str(s): float(err[k * 1024:(k + 1) * 1024].mean()) for k, s in enumerate(SNRS)}
+    return dict(wall_ms=wall * 1e3 / steps, step_ms=float(np.mean(step_ms)), sampler_ms=float(np.mean(samp_ms)),
+                setup_ms=float(np.mean(setup_ms)), estimator_ms=float(np.mean(est_ms)), ser=ser)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-per-snr", type=int, default=12)
+    ap.add_argument("--forms", default="fp32,bf16", help="comma list; the first is the reported value")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference kernel for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the detector has no multi-GPU path to time "
+              "(instances shard across GPUs with no communication); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes=1 << 30, reps=3)))
+        return
+
+    batch = W.c2_snr_sweep(n_per_snr=1024).as_precision(np.float32)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(batch, args.cpu_per_snr)   # before any GPU work in this process
+
+    import torch
+    import paper_2407_06042_amd as dm
+    dm.lib()  # raises if the HIP library is not built
+    forms = [f for f in args.forms.split(",") if f]
+    res = {}
+    for f in forms:
+        res[f] = run_form(dm, torch, batch, f, args.steps, args.warmup)
+
+    main_form = forms[0]
+    r = res[main_form]
+    B = len(batch.sigma2)
+    ci = B * CHAINS * ITERS
+    value = ci / (r["step_ms"] * 1e-3)
+    ops = algorithmic_ops_per_chain_iter(NT, NR, M) * ci
+    achieved = ops / (r["sampler_ms"] * 1e-3)
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "sampler_32x32_64qam_fp32_traffic.json")
+    if os.path.exists(tf):
+        t = json.load(open(tf))
+        if t.get("source_hash") == source_hash():
+            traffic = t.get("bytes_per_launch")
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "chain-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["step_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "32x32 64-QAM i.i.d. Rayleigh CN(0,1/Nr), SNR 16:2:28 dB x 1024 realisations "
+                               "(7168 problems), 32 chains x 100 transitions, preconditioned DMALA, tau=2, "
+                               "fp32-class (fp16-split MFMA)", "instances": B, "chains": CHAINS, "iters": ITERS},
+        "vectors_per_s": B / (r["step_ms"] * 1e-3),
+        "ser": r["ser"],
+        "stage_ms": {k: r[k] for k in ("setup_ms", "sampler_ms", "estimator_ms", "wall_ms")},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
+                     "kernel": "sampler_kernel<float,4,8,PM_F16X2>",
+                     "gx_mfma_tflops": gx_flops_per_chain_iter(NT) * ci / (r["sampler_ms"] * 1e-3) / 1e12,
+                     "ops_per_chain_iter": algorithmic_ops_per_chain_iter(NT, NR, M)},
+        "cpu_baseline": cpu,
+        "forms": {f: {"chain_iters_per_s": ci / (res[f]["step_ms"] * 1e-3), "ms_per_step": res[f]["step_ms"],
+                      "sampler_ms": res[f]["sampler_ms"], "ser": res[f]["ser"]} for f in forms},
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -90,6 +90,9 @@ typedef struct {
   uint32_t* trace_accept;    /* [n_inst][n_chains][ceil(n_iters/32)] accept bit of transition t at bit t%32 */
   uint32_t* trace_hash;      /* [n_inst][n_chains][n_iters] state fingerprint after transition t:
                                 sum_n (k_n + 1) * ((2n + 1) * 0x9E3779B1) mod 2^32 */
+  void* stage_events[4];     /* optional hipEvent_t handles recorded on `stream` before the setup,
+                                sampler and estimator kernels and after the last one (profiling);
+                                NULL entries are skipped */
 } dmala_outputs;
 
 /* Bytes of device workspace dmala_detect needs for this shape (0 on invalid

@@ -29,7 +29,8 @@ class Params(ctypes.Structure):
 class Outputs(ctypes.Structure):
     _fields_ = [("symbols", ctypes.c_void_p), ("marginals", ctypes.c_void_p), ("llrs", ctypes.c_void_p),
                 ("best_energy", ctypes.c_void_p), ("final_state", ctypes.c_void_p), ("accept_count", ctypes.c_void_p),
-                ("marginals_mc", ctypes.c_void_p), ("trace_accept", ctypes.c_void_p), ("trace_hash", ctypes.c_void_p)]
+                ("marginals_mc", ctypes.c_void_p), ("trace_accept", ctypes.c_void_p), ("trace_hash", ctypes.c_void_p),
+                ("stage_events", ctypes.c_void_p * 4)]
 
 
 class DmalaError(RuntimeError):
@@ -122,7 +123,7 @@ class Detector:
             self.out["trace_accept"] = torch.zeros((n_inst, n_chains, (n_iters + 31) // 32), dtype=torch.int32, device=device)
             self.out["trace_hash"] = torch.zeros((n_inst, n_chains, n_iters), dtype=torch.int32, device=device)
         o = Outputs()
-        for name, _ in Outputs._fields_:
+        for name, _ in Outputs._fields_[:-1]:
             setattr(o, name, self.out[name].data_ptr() if name in self.out else None)
         self._outs = o
 
@@ -130,11 +131,16 @@ class Detector:
         p = self.ws.data_ptr()
         return (p + 255) // 256 * 256
 
-    def __call__(self, Hcm, y, sigma2, stream=None):
-        """Enqueue detection on the current (or given) stream; returns the output dict."""
+    def __call__(self, Hcm, y, sigma2, stream=None, events=None):
+        """Enqueue detection on the current (or given) stream; returns the output dict.
+
+        events: optional 4 raw hipEvent_t handles recorded around the three kernels.
+        """
         torch = self.torch
         self._check_inputs(Hcm, y, sigma2)
         s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        for i in range(4):
+            self._outs.stage_events[i] = events[i] if events is not None else None
         st = lib().dmala_detect(Hcm.data_ptr(), y.data_ptr(), sigma2.data_ptr(), self.n_inst, self.nt, self.nr, self.M,
                                 None, ctypes.byref(self.params), ctypes.byref(self._outs), self._ws_ptr(),
                                 self.ws_bytes, s)

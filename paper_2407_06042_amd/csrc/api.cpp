@@ -115,6 +115,10 @@ dmala_status run(const void* H, const void* y, const void* sigma2, int32_t n_ins
   sa.n_inst = n_inst; sa.nt = sh.nt; sa.nr = sh.nr; sa.Q = sh.Q; sa.N = sh.N; sa.Npad = sh.Npad;
   sa.RT = sh.RT; sa.KB = sh.KB; sa.fp64 = sh.fp64; sa.pm = sh.pm; sa.naive = pl.naive ? 1 : 0;
   sa.tau = pl.tau; sa.alpha_mult = pl.am; sa.beta_mult = pl.bm; sa.gamma_mult = pl.gm;
+  auto mark = [&](int i) {
+    if (!eval_out && out && out->stage_events[i]) (void)hipEventRecord((hipEvent_t)out->stage_events[i], stream);
+  };
+  mark(0);
   hipError_t e = launch_setup(sa, stream);
   if (e != hipSuccess) return hip_fail(e, "setup launch");
 
@@ -132,8 +136,10 @@ dmala_status run(const void* H, const void* y, const void* sigma2, int32_t n_ins
     ka.trace_accept = out->trace_accept; ka.trace_hash = out->trace_hash;
     ka.trace_words = (sh.T + 31) / 32;
   }
+  mark(1);
   e = launch_sampler(sh, ka, eval, stream);
   if (e != hipSuccess) return hip_fail(e, "sampler launch");
+  mark(2);
   if (eval || !out) return DMALA_OK;
 
   if (out->symbols || out->marginals || out->llrs || out->best_energy || out->marginals_mc) {
@@ -149,6 +155,7 @@ dmala_status run(const void* H, const void* y, const void* sigma2, int32_t n_ins
     e = launch_estimate(ea, stream);
     if (e != hipSuccess) return hip_fail(e, "estimator launch");
   }
+  mark(3);
   return DMALA_OK;
 }
 
