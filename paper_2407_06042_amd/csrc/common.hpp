@@ -55,6 +55,7 @@ struct Shape {
   int nt, nr, M, Q, N, Npad, RT, KB, C, Cpad, T;
   int fp64;        // 1: double path
   int pm;          // PMode (MFMA path)
+  int win;         // proposal window half-width (0 = all levels), see the sampler
   size_t inst_bytes;   // per-instance setup block
   size_t frag_bytes;   // MFMA fragments (MFMA path)
   size_t state_bytes;  // per-instance sampler->estimator block

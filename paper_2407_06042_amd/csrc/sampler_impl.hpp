@@ -44,52 +44,111 @@ __device__ __forceinline__ R mode_of(R mu) {
   return j;
 }
 
-// log2 of the proposal normaliser sum_j exp2(-kL (j - mu)^2) (eq. softmax),
-// summed relative to the mode so that it never underflows.
+// Weights w_j = exp2(-kL ((j - mu)^2 - (js - mu)^2)) of the proposal over the
+// levels j = js - W .. js + W around the mode js (zero outside [0, Q)), in
+// ascending level order.  With delta = js - mu, F = exp2(-2 kL delta) and
+// c_o = exp2(-kL o^2), the weight of level js + o is c_o F^o above the mode and
+// c_o F^-o below it: two exponentials per dimension instead of one per level.
+// The window is used only when kL W (W + 1) >= 30, so that every omitted level
+// weighs less than 2^-30 of the mode -- below the fp32 rounding of the sums,
+// i.e. invisible in fp32.
+template <int Q, int W, typename R>
+__device__ __forceinline__ void window_weights(R mu, R kL, const R (&c)[W + 1], R (&e)[2 * W + 1], int& js, R& delta) {
+  const R jf = mode_of<Q>(mu);
+  js = (int)jf;
+  delta = jf - mu;
+  const R F = ex2(R(-2) * kL * delta);
+  const R G = ex2(R(2) * kL * delta);
+  R pf = R(1), pg = R(1);
+  e[W] = R(1);
+#pragma unroll
+  for (int o = 1; o <= W; ++o) {
+    pf *= F;
+    pg *= G;
+    e[W + o] = (js + o <= Q - 1) ? c[o] * pf : R(0);
+    e[W - o] = (js - o >= 0) ? c[o] * pg : R(0);
+  }
+}
+
+// All Q weights relative to the mode, one exponential per level (any kL).
 template <int Q, typename R>
-__device__ __forceinline__ R log2_norm(R mu, R kL) {
+__device__ __forceinline__ void level_weights(R mu, R kL, R (&e)[Q], R& base) {
   const R js = mode_of<Q>(mu);
-  const R base = (js - mu) * (js - mu);
-  R W = R(0);
+  base = (js - mu) * (js - mu);
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     const R t = R(j) - mu;
-    W += ex2(kL * (base - t * t));
+    e[j] = ex2(kL * (base - t * t));
   }
-  return lg2(W) - kL * base;
 }
 
-// Inverse-CDF draw: the smallest j with u W < sum_{i <= j} w_i (ascending
-// levels), w_i = exp2(-kL (i - mu)^2) relative to the mode, W = sum w.
-template <int Q, typename R>
-__device__ __forceinline__ int draw_level(R mu, R kL, R u) {
-  const R js = mode_of<Q>(mu);
-  const R base = (js - mu) * (js - mu);
-  R w[Q];
-  R W = R(0);
+// log2 of the proposal normaliser sum_j exp2(-kL (j - mu)^2) (eq. softmax).
+template <int Q, int WIN, int W, typename R>
+__device__ __forceinline__ R log2_norm(R mu, R kL, const R (&c)[W + 1]) {
+  R Z = R(0), base;
+  if constexpr (WIN > 0) {
+    R e[2 * W + 1];
+    int js;
+    window_weights<Q, W>(mu, kL, c, e, js, base);
 #pragma unroll
-  for (int j = 0; j < Q; ++j) {
-    const R t = R(j) - mu;
-    w[j] = ex2(kL * (base - t * t));
-    W += w[j];
-  }
-  const R target = u * W;
-  R cum = R(0);
-  int cnt = 0;
+    for (int i = 0; i <= 2 * W; ++i) Z += e[i];
+    base *= base;
+  } else {
+    R e[Q];
+    level_weights<Q>(mu, kL, e, base);
 #pragma unroll
-  for (int j = 0; j < Q - 1; ++j) {
-    cum += w[j];
-    cnt += (cum <= target) ? 1 : 0;
+    for (int j = 0; j < Q; ++j) Z += e[j];
   }
-  return cnt;
+  return lg2(Z) - kL * base;
 }
 
-// Hide a loop-invariant LDS base from the optimiser so that the A-operand
-// fragments are re-read from LDS every iteration instead of being hoisted into
-// (and permanently occupying) registers.
-__device__ __forceinline__ const unsigned char* opaque(const unsigned char* p) {
-  asm volatile("" : "+s"(p));
-  return p;
+// Inverse-CDF draw: the smallest level j with u Z < sum_{i <= j} w_i
+// (ascending levels), Z = sum_i w_i.
+template <int Q, int WIN, int W, typename R>
+__device__ __forceinline__ int draw_level(R mu, R kL, const R (&c)[W + 1], R u) {
+  if constexpr (WIN > 0) {
+    R e[2 * W + 1];
+    int js;
+    R delta;
+    window_weights<Q, W>(mu, kL, c, e, js, delta);
+    R Z = R(0);
+#pragma unroll
+    for (int i = 0; i <= 2 * W; ++i) Z += e[i];
+    const R target = u * Z;
+    R cum = R(0);
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 2 * W; ++i) {
+      cum += e[i];
+      cnt += (cum <= target) ? 1 : 0;
+    }
+    const int k = js - W + cnt;
+    return k < 0 ? 0 : (k > Q - 1 ? Q - 1 : k);
+  } else {
+    R e[Q], base;
+    level_weights<Q>(mu, kL, e, base);
+    R Z = R(0);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) Z += e[j];
+    const R target = u * Z;
+    R cum = R(0);
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < Q - 1; ++j) {
+      cum += e[j];
+      cnt += (cum <= target) ? 1 : 0;
+    }
+    return cnt;
+  }
+}
+
+// An opaque zero: added to LDS offsets inside the loop so that the optimiser
+// cannot hoist the loop-invariant A-operand fragment loads out of the loop
+// (that would pin every fragment in registers and halve the occupancy).
+__device__ __forceinline__ uint32_t opaque_zero() {
+  uint32_t z = 0;
+  asm volatile("" : "+s"(z));
+  return z;
 }
 
 template <typename R>
@@ -99,13 +158,14 @@ __device__ __forceinline__ R bfly4(R v) {
   return v;
 }
 
-template <typename Real, int RT, int Q, int PM, bool EVAL>
+template <typename Real, int RT, int Q, int PM, bool EVAL, int WIN>
 __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
   constexpr bool F64 = std::is_same<Real, double>::value;
   constexpr int D = 4 * RT;
   constexpr int KB = RT / 2;
   constexpr int NPP = p_passes(PM);
   constexpr int QM1 = Q - 1;
+  constexpr int W = WIN > 0 ? WIN : Q - 1;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
   const int inst = blockIdx.x;
@@ -128,6 +188,9 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
   const Real kL = (Real)ip.kL;
   const Real rho = (Real)ip.rho;
   const Real sP = (Real)ip.scaleP, sE = (Real)ip.scaleE;
+  Real cw[W + 1];  // exp2(-kL o^2)
+#pragma unroll
+  for (int o = 0; o <= W; ++o) cw[o] = ex2(-kL * Real(o * o));
   const Real* pbv;
   const Real* ezv;
   const double* Pd = nullptr;
@@ -174,7 +237,7 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
         accE[d] = se;
       }
     } else {
-      const unsigned char* fb = opaque(smem);
+      const uint32_t fo = opaque_zero() + (uint32_t)lane * 16;
       half8 bh[KB];
       bf16x8 bb[KB];
 #pragma unroll
@@ -194,7 +257,7 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
         for (int p = 0; p < kEPasses; ++p)
 #pragma unroll
           for (int kb = 0; kb < KB; ++kb) {
-            const half8 fa = *(const half8*)(fb + (size_t)(((NPP + p) * RT + rt) * KB + kb) * 1024 + lane * 16);
+            const half8 fa = *(const half8*)(smem + fo + (uint32_t)(((NPP + p) * RT + rt) * KB + kb) * 1024u);
             e = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa, bh[kb], e, 0, 0, 0);
           }
 #pragma unroll
@@ -205,7 +268,7 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
           for (int p = 0; p < NPP; ++p)
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb) {
-              const unsigned char* src = fb + (size_t)((p * RT + rt) * KB + kb) * 1024 + lane * 16;
+              const unsigned char* src = smem + fo + (uint32_t)((p * RT + rt) * KB + kb) * 1024u;
               if constexpr (PM == PM_BF16X1)
                 q = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*(const bf16x8*)src, bb[kb], q, 0, 0, 0);
               else
@@ -231,8 +294,14 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
       else shift = accP[d] * sP - pbv[n];
       eg[d] = g;
       mu[d] = Real(k[d]) - shift;
-      lz[d] = log2_norm<Q>(mu[d], kL);
+      lz[d] = log2_norm<Q, WIN, W>(mu[d], kL, cw);
     }
+  };
+
+  // log2 q_n(j | .) for a level j given the cached mode and normaliser
+  auto lq = [&](int j, Real mu, Real lz) {
+    const Real t = Real(j) - mu;
+    return -kL * t * t - lz;
   };
 
   int kc[D];
@@ -252,15 +321,14 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
     Real lqf = 0;
 #pragma unroll
     for (int d = 0; d < D; ++d)
-      if (dim_of(d) < N) { const Real t = Real(kt[d]) - mu[d]; lqf += -kL * t * t - lz[d]; }
+      if (dim_of(d) < N) lqf += lq(kt[d], mu[d], lz[d]);
     Real mup[D], lzp[D], egp[D];
     proposal_at(kt, mup, lzp, egp);
     Real lqr = 0, T2 = 0;
 #pragma unroll
     for (int d = 0; d < D; ++d)
       if (dim_of(d) < N) {
-        const Real t = Real(kc[d]) - mup[d];
-        lqr += -kL * t * t - lzp[d];
+        lqr += lq(kc[d], mup[d], lzp[d]);
         T2 -= Real(kt[d] - kc[d]) * (eg[d] + egp[d]);
       }
     lqf = bfly4(lqf); lqr = bfly4(lqr); T2 = bfly4(T2);
@@ -275,6 +343,9 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
     return;
   } else {
     const uint32_t key0 = a.key0, key1 = a.key1;
+    bool valid[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) valid[d] = dim_of(d) < N;
     // initial state from the t = 0 words
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
@@ -289,7 +360,7 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int n = dim_of(d);
-      if (n < N) ep += Real(2 * kc[d] - QM1) * (eg[d] - ezv[n]);
+      ep += valid[d] ? Real(2 * kc[d] - QM1) * (eg[d] - ezv[n]) : Real(0);
     }
     ep = bfly4(ep);
     const Real eunit = (Real)ip.eunit;
@@ -310,36 +381,37 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
         w[rt][0] = (uint32_t)(4 * rt + h); w[rt][1] = (uint32_t)t; w[rt][2] = (uint32_t)chain; w[rt][3] = (uint32_t)inst;
         philox4x32_10(w[rt], key0, key1);
       }
-      // 1. draw x' and log q(x'|x)
+      // 1. draw x' (padding dimensions never move) and -log q(x'|x)
       int kp[D];
-      Real lqf = 0;
+      Real S = 0;
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         Real u;
         if constexpr (F64) u = u24d(w[d >> 2][d & 3]);
         else u = u24f(w[d >> 2][d & 3]);
-        kp[d] = draw_level<Q>(mu[d], kL, u);
-        if (dim_of(d) < N) { const Real tt = Real(kp[d]) - mu[d]; lqf += -kL * tt * tt - lz[d]; }
+        const int kd = draw_level<Q, WIN, W>(mu[d], kL, cw, u);
+        kp[d] = valid[d] ? kd : kc[d];
+        S -= lq(kp[d], mu[d], lz[d]);
       }
-      // 2-3. gradient at x', proposal at x', log q(x|x')
+      // 2-3. gradient at x', proposal at x', + log q(x|x'), energy term.
+      // A padding dimension contributes exactly zero: its contraction rows are
+      // zero, so mu' = mu, lz' = lz and the two log q terms cancel.
       Real mup[D], lzp[D], egp[D];
       proposal_at(kp, mup, lzp, egp);
-      Real lqr = 0, T2 = 0;
+      Real T2 = 0;
 #pragma unroll
-      for (int d = 0; d < D; ++d)
-        if (dim_of(d) < N) {
-          const Real tt = Real(kc[d]) - mup[d];
-          lqr += -kL * tt * tt - lzp[d];
-          T2 -= Real(kp[d] - kc[d]) * (eg[d] + egp[d]);
-        }
-      // 4. MH: accept iff  log ratio > log u  (eq. acc_prob: A > u)
-      Real S = T2 + lqr - lqf;
-      if (h == 0) {
+      for (int d = 0; d < D; ++d) {
+        S += lq(kc[d], mup[d], lzp[d]);
+        T2 -= Real(kp[d] - kc[d]) * (eg[d] + egp[d]);
+      }
+      S += T2;
+      // 4. MH: accept iff  log ratio > log u  (eq. acc_prob: A > u); lanes h = 0 hold the MH word
+      {
         const uint32_t um = low_bytes24(w[0][0], w[0][1], w[0][2]);
         Real lu;
         if constexpr (F64) lu = lg2((double)um * 5.9604644775390625e-08);
         else lu = lg2((float)um * 5.9604644775390625e-08f);
-        S -= lu;
+        S -= (h == 0) ? lu : Real(0);
       }
       S = bfly4(S);
       T2 = bfly4(T2);
@@ -352,7 +424,8 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
         lz[d] = acc ? lzp[d] : lz[d];
         eg[d] = acc ? egp[d] : eg[d];
       }
-      if (acc) { E -= T2 * eunit; ++nacc; }
+      E = acc ? E - T2 * eunit : E;
+      nacc += acc ? 1 : 0;
       if (E < Ebest) {
         Ebest = E;
 #pragma unroll
@@ -369,10 +442,7 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
       if (a.trace_hash) {
         uint32_t hs = 0;
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-          const int n = dim_of(d);
-          if (n < N) hs += (uint32_t)(kc[d] + 1) * hash_mult(n);
-        }
+        for (int d = 0; d < D; ++d) hs += valid[d] ? (uint32_t)(kc[d] + 1) * hash_mult(dim_of(d)) : 0u;
         hs += __shfl_xor(hs, 16);
         hs += __shfl_xor(hs, 32);
         if (live && h == 0) a.trace_hash[trow * a.T + (t - 1)] = hs;
@@ -404,13 +474,13 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
   }
 }
 
-template <typename Real, int RT, int Q, int PM>
+template <typename Real, int RT, int Q, int PM, int WIN>
 hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
   const int chain_blocks = sh.Cpad / 16;
   const int waves = chain_blocks < 4 ? chain_blocks : 4;
   const dim3 grid(a.n_inst, (chain_blocks + waves - 1) / waves);
   const size_t lds = sampler_lds_bytes(sh);
-  auto k = eval ? sampler_kernel<Real, RT, Q, PM, true> : sampler_kernel<Real, RT, Q, PM, false>;
+  auto k = eval ? sampler_kernel<Real, RT, Q, PM, true, WIN> : sampler_kernel<Real, RT, Q, PM, false, WIN>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -421,11 +491,13 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
 
 template <typename Real, int RT, int PM>
 hipError_t launch_q(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+  // the 3-level window is used only for Q >= 8 (it would not be smaller otherwise)
+  const bool win = !std::is_same<Real, double>::value && sh.win == 3;
   switch (sh.Q) {
-    case 2: return launch_t<Real, RT, 2, PM>(sh, a, eval, s);
-    case 4: return launch_t<Real, RT, 4, PM>(sh, a, eval, s);
-    case 8: return launch_t<Real, RT, 8, PM>(sh, a, eval, s);
-    case 16: return launch_t<Real, RT, 16, PM>(sh, a, eval, s);
+    case 2: return launch_t<Real, RT, 2, PM, 0>(sh, a, eval, s);
+    case 4: return launch_t<Real, RT, 4, PM, 0>(sh, a, eval, s);
+    case 8: return win ? launch_t<Real, RT, 8, PM, 3>(sh, a, eval, s) : launch_t<Real, RT, 8, PM, 0>(sh, a, eval, s);
+    case 16: return win ? launch_t<Real, RT, 16, PM, 3>(sh, a, eval, s) : launch_t<Real, RT, 16, PM, 0>(sh, a, eval, s);
   }
   return hipErrorInvalidValue;
 }
