@@ -29,7 +29,7 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Plan {
   Shape sh;
-  size_t inst_off, state_off, est_off, total;
+  size_t inst_off, state_off, total;
   double tau, am, bm, gm;
   bool naive;
 };
@@ -78,13 +78,9 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
     return fail(DMALA_ERR_UNSUPPORTED, "shape needs %zu bytes of LDS (> 160 KiB)", sampler_lds_bytes(sh));
   sh.inst_bytes = round_up(kParamBytes + sh.frag_bytes, 256);
   sh.state_bytes = state_offsets(sh.Cpad, sh.Npad).end;
-  const size_t R = fp64 ? 8 : 4;
-  sh.est_bytes = round_up(R * (2 * (size_t)sh.C * nr + (size_t)sh.C * nr + 2 * (size_t)sh.C * nt + 2 * (size_t)sh.C +
-                               2 * (size_t)sh.C * nt + nt + (size_t)nt * M), 256);
   pl.inst_off = 0;
   pl.state_off = round_up((size_t)n_inst * sh.inst_bytes, 256);
-  pl.est_off = round_up(pl.state_off + (size_t)n_inst * sh.state_bytes, 256);
-  pl.total = pl.est_off + (size_t)n_inst * sh.est_bytes;
+  pl.total = pl.state_off + (size_t)n_inst * sh.state_bytes;
   pl.tau = p->tau > 0 ? p->tau : 2.0;
   pl.am = p->alpha_mult > 0 ? p->alpha_mult : 1.0;
   pl.bm = p->beta_mult > 0 ? p->beta_mult : 1.0;
@@ -154,9 +150,9 @@ dmala_status run(const void* H, const void* y, const void* sigma2, int32_t n_ins
     ea.H = H; ea.y = y; ea.sigma2 = sigma2;
     ea.ws_inst = base + pl.inst_off; ea.inst_stride = sh.inst_bytes;
     ea.ws_state = base + pl.state_off; ea.state_stride = sh.state_bytes;
-    ea.ws_est = base + pl.est_off; ea.est_stride = sh.est_bytes;
     ea.n_inst = n_inst; ea.nt = sh.nt; ea.nr = sh.nr; ea.Q = sh.Q; ea.N = sh.N; ea.Npad = sh.Npad;
     ea.C = sh.C; ea.Cpad = sh.Cpad; ea.fp64 = sh.fp64;
+    ea.chunk = estimate_chunk(sh.nt, sh.nr, sh.M, sh.N, sh.C, sh.fp64 != 0);
     ea.symbols = out->symbols; ea.marginals = out->marginals; ea.llrs = out->llrs;
     ea.best_energy = out->best_energy; ea.marginals_mc = out->marginals_mc;
     e = launch_estimate(ea, stream);

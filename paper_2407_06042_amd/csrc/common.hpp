@@ -59,7 +59,6 @@ struct Shape {
   size_t inst_bytes;   // per-instance setup block
   size_t frag_bytes;   // MFMA fragments (MFMA path)
   size_t state_bytes;  // per-instance sampler->estimator block
-  size_t est_bytes;    // per-instance estimator scratch
 };
 
 // Offsets inside the per-instance state block.
@@ -99,8 +98,8 @@ struct EstArgs {
   const void* H; const void* y; const void* sigma2;
   const unsigned char* ws_inst; size_t inst_stride;
   const unsigned char* ws_state; size_t state_stride;
-  unsigned char* ws_est; size_t est_stride;
   int n_inst, nt, nr, Q, N, Npad, C, Cpad, fp64;
+  int chunk;       // chains staged in LDS at a time
   int32_t* symbols; float* marginals; float* llrs; float* best_energy; float* marginals_mc;
 };
 
@@ -109,6 +108,7 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
 hipError_t launch_sampler(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s);
 hipError_t launch_estimate(const EstArgs& a, hipStream_t s);
 size_t sampler_lds_bytes(const Shape& sh);
+int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64);
 
 // ------------------------------------------------------------------ device helpers
 

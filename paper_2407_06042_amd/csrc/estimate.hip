@@ -13,6 +13,9 @@
 // whose I/Q parts separate because the real-equivalent columns of one antenna
 // are orthogonal.  The hard decision is the chain whose tracked best state has
 // the smallest freshly recomputed residual energy.
+//
+// Chains are processed in chunks staged in LDS; every (bit) and (antenna,
+// point) output keeps a running log-sum-exp in registers across chunks.
 #include "common.hpp"
 
 namespace dmala {
@@ -39,14 +42,17 @@ __device__ __forceinline__ int ungray(int g) {
   return g;
 }
 
-template <typename R, typename TIn>
+constexpr int kMaxLlrPerThread = 2;    // nt * log2(M) <= 64 * 8 = 512 = 2 * 256
+constexpr int kMaxMargPerThread = 64;  // nt * M <= 64 * 256 = 16384 = 64 * 256
+
+template <typename R, int MPT>
 __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
   const int b = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
-  const int nt = a.nt, nr = a.nr, Q = a.Q, M = Q * Q, C = a.C, Npad = a.Npad;
+  const int nt = a.nt, nr = a.nr, Q = a.Q, M = Q * Q, C = a.C, Npad = a.Npad, N = a.N, CH = a.chunk;
   int nb = 0;
   while ((1 << nb) < Q) ++nb;
-  const TIn* H = (const TIn*)a.H + 2 * (size_t)b * nt * nr;
-  const TIn* y = (const TIn*)a.y + 2 * (size_t)b * nr;
+  const R* H = (const R*)a.H + 2 * (size_t)b * nt * nr;
+  const R* y = (const R*)a.y + 2 * (size_t)b * nr;
   const InstParams ip = *(const InstParams*)(a.ws_inst + (size_t)b * a.inst_stride);
   const R sigma2 = (R)ip.sigma2, s = (R)ip.s, tau = (R)ip.tau;
   const R cw = (tau - R(1)) / tau;
@@ -55,118 +61,164 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
   const int8_t* K = (const int8_t*)(st + so.k);
   const int8_t* Kb = (const int8_t*)(st + so.kbest);
 
-  R* r = (R*)(a.ws_est + (size_t)b * a.est_stride);       // C x nr complex
-  R* rb2 = r + 2 * (size_t)C * nr;                           // C x nr
-  R* cc = rb2 + (size_t)C * nr;                              // C x nt complex
-  R* f = cc + 2 * (size_t)C * nt;                            // C
-  R* Efr = f + C;                                            // C
-  R* lse = Efr + C;                                          // C x nt x 2
-  R* Gd = lse + 2 * (size_t)C * nt;                          // nt
-  R* lp = Gd + nt;                                           // nt x M
+  extern __shared__ __attribute__((aligned(16))) unsigned char esm[];
+  R* rs = (R*)esm;                          // CH x nr complex residuals of the final states
+  R* rb2 = rs + 2 * (size_t)CH * nr;        // CH x nr |residual|^2 of the best states
+  R* cc = rb2 + (size_t)CH * nr;            // CH x nt complex H^H r
+  R* lse = cc + 2 * (size_t)CH * nt;        // CH x nt x 2 per-axis log normalisers
+  R* fs = lse + 2 * (size_t)CH * nt;        // CH
+  R* ebs = fs + CH;                         // CH
+  R* Gd = ebs + CH;                         // nt
+  R* lp = Gd + nt;                          // nt x M
+  int8_t* Ks = (int8_t*)(lp + (size_t)nt * M);  // CH x N
+  int8_t* Kbs = Ks + (size_t)CH * N;            // CH x N
+  __shared__ R best_e;
+  __shared__ int best_c;
 
   auto level = [&](int k) { return s * R(2 * k - Q + 1); };
 
-  // residuals of the final and of the best states
-  for (int it = tid; it < C * nr; it += nth) {
-    const int c = it / nr, i = it % nr;
-    R re = (R)y[2 * i], im = (R)y[2 * i + 1];
-    R bre = re, bim = im;
-    for (int m = 0; m < nt; ++m) {
-      const R hre = (R)H[2 * ((size_t)m * nr + i)], him = (R)H[2 * ((size_t)m * nr + i) + 1];
-      const R xr = level(K[(size_t)c * Npad + 2 * m]), xi = level(K[(size_t)c * Npad + 2 * m + 1]);
-      re -= hre * xr - him * xi;
-      im -= hre * xi + him * xr;
-      const R br = level(Kb[(size_t)c * Npad + 2 * m]), bi = level(Kb[(size_t)c * Npad + 2 * m + 1]);
-      bre -= hre * br - him * bi;
-      bim -= hre * bi + him * br;
-    }
-    r[2 * (size_t)it] = re;
-    r[2 * (size_t)it + 1] = im;
-    rb2[it] = bre * bre + bim * bim;
-  }
-  __syncthreads();
-  for (int it = tid; it < C * nt; it += nth) {
-    const int c = it / nt, m = it % nt;
-    R re = 0, im = 0;
-    for (int i = 0; i < nr; ++i) {
-      const R hre = (R)H[2 * ((size_t)m * nr + i)], him = (R)H[2 * ((size_t)m * nr + i) + 1];
-      const R rr = r[2 * ((size_t)c * nr + i)], ri = r[2 * ((size_t)c * nr + i) + 1];
-      re += hre * rr + him * ri;
-      im += hre * ri - him * rr;
-    }
-    cc[2 * (size_t)it] = re;
-    cc[2 * (size_t)it + 1] = im;
-  }
-  for (int c = tid; c < C; c += nth) {
-    R e = 0, eb = 0;
-    for (int i = 0; i < nr; ++i) {
-      e += r[2 * ((size_t)c * nr + i)] * r[2 * ((size_t)c * nr + i)] + r[2 * ((size_t)c * nr + i) + 1] * r[2 * ((size_t)c * nr + i) + 1];
-      eb += rb2[(size_t)c * nr + i];
-    }
-    f[c] = -e / sigma2;
-    Efr[c] = eb;
-  }
   for (int m = tid; m < nt; m += nth) {
     R g = 0;
     for (int i = 0; i < nr; ++i) {
-      const R hre = (R)H[2 * ((size_t)m * nr + i)], him = (R)H[2 * ((size_t)m * nr + i) + 1];
+      const R hre = H[2 * ((size_t)m * nr + i)], him = H[2 * ((size_t)m * nr + i) + 1];
       g += hre * hre + him * him;
     }
     Gd[m] = g;
   }
-  __syncthreads();
+  if (tid == 0) { best_e = R(INFINITY); best_c = 0; }
 
-  // change of f when coordinate n of sample c moves to level k
-  auto delta = [&](int c, int n, int k) {
-    const int m = n >> 1;
-    const R d = level(k) - level(K[(size_t)c * Npad + n]);
-    return (R(2) * d * cc[2 * ((size_t)c * nt + m) + (n & 1)] - d * d * Gd[m]) / sigma2;
-  };
+  // per-thread accumulators
+  const int n_llr = nt * 2 * nb, n_marg = nt * M;
+  OnlineLse<R> lnum[kMaxLlrPerThread], lden[kMaxLlrPerThread];
+  OnlineLse<R> lmarg[MPT];
+  int mc[MPT];
+#pragma unroll
+  for (int q = 0; q < MPT; ++q) mc[q] = 0;
 
-  // per-sample log normalisers of the tempered conditional of each axis
-  for (int it = tid; it < C * nt; it += nth) {
-    const int c = it / nt, m = it % nt;
-    for (int ax = 0; ax < 2; ++ax) {
-      OnlineLse<R> l;
-      for (int k = 0; k < Q; ++k) l.add(delta(c, 2 * m + ax, k) / tau);
-      lse[2 * (size_t)it + ax] = l.value();
-    }
-  }
-  __syncthreads();
-
-  // bit LLRs
-  if (a.llrs) {
-    for (int it = tid; it < nt * 2 * nb; it += nth) {
-      const int m = it / (2 * nb), ax = (it / nb) % 2, bit = it % nb;
-      const int n = 2 * m + ax;
-      const int mask = 1 << (nb - 1 - bit);
-      OnlineLse<R> num, den;
-      for (int c = 0; c < C; ++c) {
-        const int k = K[(size_t)c * Npad + n];
-        const int g = k ^ (k >> 1);
-        const R Fp = f[c] + delta(c, n, ungray(g & ~mask));
-        const R Fm = f[c] + delta(c, n, ungray(g | mask));
-        const R gm = (Fp - Fm) / tau;
-        num.add(cw * Fp - softplus(-gm));
-        den.add(cw * Fm - softplus(gm));
-      }
-      a.llrs[(size_t)b * nt * 2 * nb + it] = (float)(num.value() - den.value());
-    }
-  }
-
-  // symbol marginals
-  if (a.marginals) {
-    for (int it = tid; it < nt * M; it += nth) {
-      const int m = it / M, pt = it % M, kI = pt / Q, kQ = pt % Q;
-      OnlineLse<R> l;
-      for (int c = 0; c < C; ++c) {
-        const R v = cw * f[c] + delta(c, 2 * m, kI) + delta(c, 2 * m + 1, kQ)
-                    - lse[2 * ((size_t)c * nt + m)] - lse[2 * ((size_t)c * nt + m) + 1];
-        l.add(v);
-      }
-      lp[it] = l.value();
+  for (int c0 = 0; c0 < C; c0 += CH) {
+    const int ch = C - c0 < CH ? C - c0 : CH;
+    __syncthreads();
+    for (int it = tid; it < ch * N; it += nth) {
+      const int c = it / N, n = it % N;
+      Ks[it] = K[(size_t)(c0 + c) * Npad + n];
+      Kbs[it] = Kb[(size_t)(c0 + c) * Npad + n];
     }
     __syncthreads();
+    // residuals of the final and of the best states
+    for (int it = tid; it < ch * nr; it += nth) {
+      const int c = it / nr, i = it % nr;
+      R re = y[2 * i], im = y[2 * i + 1];
+      R bre = re, bim = im;
+      for (int m = 0; m < nt; ++m) {
+        const R hre = H[2 * ((size_t)m * nr + i)], him = H[2 * ((size_t)m * nr + i) + 1];
+        const R xr = level(Ks[c * N + 2 * m]), xi = level(Ks[c * N + 2 * m + 1]);
+        re -= hre * xr - him * xi;
+        im -= hre * xi + him * xr;
+        const R br = level(Kbs[c * N + 2 * m]), bi = level(Kbs[c * N + 2 * m + 1]);
+        bre -= hre * br - him * bi;
+        bim -= hre * bi + him * br;
+      }
+      rs[2 * it] = re;
+      rs[2 * it + 1] = im;
+      rb2[it] = bre * bre + bim * bim;
+    }
+    __syncthreads();
+    for (int it = tid; it < ch * nt; it += nth) {
+      const int c = it / nt, m = it % nt;
+      R re = 0, im = 0;
+      for (int i = 0; i < nr; ++i) {
+        const R hre = H[2 * ((size_t)m * nr + i)], him = H[2 * ((size_t)m * nr + i) + 1];
+        const R rr = rs[2 * (c * nr + i)], ri = rs[2 * (c * nr + i) + 1];
+        re += hre * rr + him * ri;
+        im += hre * ri - him * rr;
+      }
+      cc[2 * it] = re;
+      cc[2 * it + 1] = im;
+    }
+    for (int c = tid; c < ch; c += nth) {
+      R e = 0, eb = 0;
+      for (int i = 0; i < nr; ++i) {
+        e += rs[2 * (c * nr + i)] * rs[2 * (c * nr + i)] + rs[2 * (c * nr + i) + 1] * rs[2 * (c * nr + i) + 1];
+        eb += rb2[c * nr + i];
+      }
+      fs[c] = -e / sigma2;
+      ebs[c] = eb;
+    }
+    __syncthreads();
+
+    // change of f when coordinate n of sample c moves to level k
+    auto delta = [&](int c, int n, int k) {
+      const int m = n >> 1;
+      const R d = level(k) - level(Ks[c * N + n]);
+      return (R(2) * d * cc[2 * (c * nt + m) + (n & 1)] - d * d * Gd[m]) / sigma2;
+    };
+
+    for (int it = tid; it < ch * nt; it += nth) {
+      const int c = it / nt, m = it % nt;
+      for (int ax = 0; ax < 2; ++ax) {
+        OnlineLse<R> l;
+        for (int k = 0; k < Q; ++k) l.add(delta(c, 2 * m + ax, k) / tau);
+        lse[2 * it + ax] = l.value();
+      }
+    }
+    if (tid == 0) {
+      for (int c = 0; c < ch; ++c)
+        if (ebs[c] < best_e) { best_e = ebs[c]; best_c = c0 + c; }
+    }
+    __syncthreads();
+
+    // bit LLRs
+#pragma unroll
+    for (int q = 0; q < kMaxLlrPerThread; ++q) {
+      const int it = tid + q * nth;
+      if (it < n_llr) {
+        const int m = it / (2 * nb), ax = (it / nb) % 2, bit = it % nb;
+        const int n = 2 * m + ax;
+        const int mask = 1 << (nb - 1 - bit);
+        for (int c = 0; c < ch; ++c) {
+          const int k = Ks[c * N + n];
+          const int g = k ^ (k >> 1);
+          const R Fp = fs[c] + delta(c, n, ungray(g & ~mask));
+          const R Fm = fs[c] + delta(c, n, ungray(g | mask));
+          const R gm = (Fp - Fm) / tau;
+          lnum[q].add(cw * Fp - softplus(-gm));
+          lden[q].add(cw * Fm - softplus(gm));
+        }
+      }
+    }
+    // symbol marginals (IS) and the plain Monte Carlo histogram
+#pragma unroll
+    for (int q = 0; q < MPT; ++q) {
+      const int it = tid + q * nth;
+      if (it < n_marg) {
+        const int m = it / M, pt = it % M, kI = pt / Q, kQ = pt % Q;
+        for (int c = 0; c < ch; ++c) {
+          const R v = cw * fs[c] + delta(c, 2 * m, kI) + delta(c, 2 * m + 1, kQ)
+                      - lse[2 * (c * nt + m)] - lse[2 * (c * nt + m) + 1];
+          lmarg[q].add(v);
+          mc[q] += (Ks[c * N + 2 * m] == kI && Ks[c * N + 2 * m + 1] == kQ) ? 1 : 0;
+        }
+      }
+    }
+  }
+
+  if (a.llrs) {
+#pragma unroll
+    for (int q = 0; q < kMaxLlrPerThread; ++q) {
+      const int it = tid + q * nth;
+      if (it < n_llr) a.llrs[(size_t)b * n_llr + it] = (float)(lnum[q].value() - lden[q].value());
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < MPT; ++q) {
+    const int it = tid + q * nth;
+    if (it < n_marg) {
+      lp[it] = lmarg[q].value();
+      if (a.marginals_mc) a.marginals_mc[(size_t)b * n_marg + it] = (float)mc[q] / (float)C;
+    }
+  }
+  __syncthreads();
+  if (a.marginals) {
     for (int m = tid; m < nt; m += nth) {
       OnlineLse<R> l;
       for (int pt = 0; pt < M; ++pt) l.add(lp[(size_t)m * M + pt]);
@@ -174,34 +226,52 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
       for (int pt = 0; pt < M; ++pt) a.marginals[((size_t)b * nt + m) * M + pt] = (float)exp(lp[(size_t)m * M + pt] - z);
     }
   }
-
-  if (a.marginals_mc) {
-    for (int it = tid; it < nt * M; it += nth) {
-      const int m = it / M, pt = it % M;
-      int cnt = 0;
-      for (int c = 0; c < C; ++c) cnt += (K[(size_t)c * Npad + 2 * m] * Q + K[(size_t)c * Npad + 2 * m + 1]) == pt;
-      a.marginals_mc[(size_t)b * nt * M + it] = (float)cnt / (float)C;
-    }
-  }
-
   // hard decision: smallest recomputed energy among the chains' best states
   if (tid == 0) {
-    int best = 0;
-    for (int c = 1; c < C; ++c)
-      if (Efr[c] < Efr[best]) best = c;
-    if (a.best_energy) a.best_energy[b] = (float)Efr[best];
+    const int bc = best_c;
+    if (a.best_energy) a.best_energy[b] = (float)best_e;
     if (a.symbols)
       for (int m = 0; m < nt; ++m)
-        a.symbols[(size_t)b * nt + m] = Kb[(size_t)best * Npad + 2 * m] * Q + Kb[(size_t)best * Npad + 2 * m + 1];
+        a.symbols[(size_t)b * nt + m] = Kb[(size_t)bc * Npad + 2 * m] * Q + Kb[(size_t)bc * Npad + 2 * m + 1];
   }
 }
 
-hipError_t launch_estimate(const EstArgs& a, hipStream_t s) {
-  if (a.fp64)
-    hipLaunchKernelGGL((estimate_kernel<double, double>), dim3(a.n_inst), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((estimate_kernel<float, float>), dim3(a.n_inst), dim3(256), 0, s, a);
+size_t estimate_lds_bytes(int nt, int nr, int M, int N, int chunk, bool fp64) {
+  const size_t R = fp64 ? 8 : 4;
+  return R * (3 * (size_t)chunk * nr + 4 * (size_t)chunk * nt + 2 * (size_t)chunk + nt + (size_t)nt * M) +
+         2 * (size_t)chunk * N + 16;
+}
+
+int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64) {
+  int ch = C;
+  while (ch > 1 && estimate_lds_bytes(nt, nr, M, N, ch, fp64) > 96 * 1024) ch = (ch + 1) / 2;
+  return ch;
+}
+
+template <typename R, int MPT>
+static hipError_t launch_e(const EstArgs& a, hipStream_t s) {
+  const size_t lds = estimate_lds_bytes(a.nt, a.nr, a.Q * a.Q, a.N, a.chunk, a.fp64);
+  auto k = estimate_kernel<R, MPT>;
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k, dim3(a.n_inst), dim3(256), lds, s, a);
   return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_r(const EstArgs& a, hipStream_t s) {
+  const int items = a.nt * a.Q * a.Q;
+  if (items <= 256) return launch_e<R, 1>(a, s);
+  if (items <= 2048) return launch_e<R, 8>(a, s);
+  if (items <= 4096) return launch_e<R, 16>(a, s);
+  if (items <= 8192) return launch_e<R, 32>(a, s);
+  return launch_e<R, kMaxMargPerThread>(a, s);
+}
+
+hipError_t launch_estimate(const EstArgs& a, hipStream_t s) {
+  return a.fp64 ? launch_r<double>(a, s) : launch_r<float>(a, s);
 }
 
 }  // namespace dmala
