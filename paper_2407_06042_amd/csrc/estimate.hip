@@ -2,39 +2,47 @@
 //
 // One workgroup per instance.  For every chain's final state x^[s] (the sample
 // list of Section V-A) the kernel recomputes the residual r = y - H x from the
-// inputs, E = ||r||^2, f = -E/sigma^2 and c = H^H r.  A single-coordinate change
-// of dimension n by d then has the closed form
-//     f(x + d e_n) = f + (2 d c_n - d^2 ||h_m||^2) / sigma^2,
+// inputs, E = ||r||^2, f = -E/sigma^2 and c = H^H r.  Moving coordinate n of a
+// sample from level k_n to level k (e = k - k_n, real step d = 2 s e) changes f by
+//     delta(e) = (2 d c_n - d^2 ||h_m||^2) / sigma^2 = e (a_n - a2_m e),
+//     a_n = 4 s c_n / sigma^2,  a2_m = 4 s^2 ||h_m||^2 / sigma^2,
 // which gives, per bit (eq. llr_is in the log-sum-exp form of eq. llr_simple,
 // F(a) = log(1 + e^a) evaluated exactly)
 //     L = LSE_s[((tau-1)/tau) F+ - F(-g)] - LSE_s[((tau-1)/tau) F- - F(g)],  g = (F+ - F-)/tau,
-// and per antenna and point a the symbol-level IS estimate
-//     p(a) propto sum_s pi_a(a | x^[s]_-m) exp(((tau-1)/tau) f(x^[s]_{m<-a})),
-// whose I/Q parts separate because the real-equivalent columns of one antenna
-// are orthogonal.  The hard decision is the chain whose tracked best state has
-// the smallest freshly recomputed residual energy.
+// and per antenna and point a = (kI, kQ) the symbol-level IS estimate
+//     p(a) propto sum_s pi_a(a | x^[s]_-m) exp(((tau-1)/tau) f(x^[s]_{m<-a}))
+//          = sum_s exp(((tau-1)/tau) f_s + delta_I(kI) + delta_Q(kQ) - lse_I - lse_Q),
+// lse_{I,Q} = log sum_k exp(delta_{I,Q}(k)/tau): the I/Q parts separate because
+// the real-equivalent columns of one antenna are orthogonal.  The hard decision
+// is the chain whose tracked best state has the smallest recomputed energy.
 //
-// Chains are processed in chunks staged in LDS; every (bit) and (antenna,
-// point) output keeps a running log-sum-exp in registers across chunks.
+// Chains are processed in chunks staged in LDS; every output keeps a running
+// log-sum-exp in registers across chunks.  A thread owns (antenna, kI) and the
+// Q points (kI, 0..Q-1), so the inner loop has Q independent accumulators.
 #include "common.hpp"
 
 namespace dmala {
+
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
+__device__ __forceinline__ double fexp(double x) { return exp(x); }
+__device__ __forceinline__ double flog(double x) { return log(x); }
 
 template <typename R>
 struct OnlineLse {
   R mx, sum;
   __device__ OnlineLse() : mx(-INFINITY), sum(R(0)) {}
-  __device__ void add(R v) {
-    if (v == R(-INFINITY)) return;
-    if (v > mx) { sum = sum * exp(mx - v) + R(1); mx = v; }
-    else sum += exp(v - mx);
+  __device__ __forceinline__ void add(R v) {
+    if (v > mx) { sum = sum * fexp(mx - v) + R(1); mx = v; }
+    else sum += fexp(v - mx);
   }
-  __device__ R value() const { return mx + log(sum); }
+  __device__ R value() const { return mx + flog(sum); }
 };
 
 template <typename R>
 __device__ __forceinline__ R softplus(R a) {  // log(1 + e^a)
-  return a > R(0) ? a + log1p(exp(-a)) : log1p(exp(a));
+  const R z = fexp(-fabs(a));
+  return (a > R(0) ? a : R(0)) + flog(R(1) + z);
 }
 
 __device__ __forceinline__ int ungray(int g) {
@@ -42,36 +50,40 @@ __device__ __forceinline__ int ungray(int g) {
   return g;
 }
 
-constexpr int kMaxLlrPerThread = 2;    // nt * log2(M) <= 64 * 8 = 512 = 2 * 256
-constexpr int kMaxMargPerThread = 64;  // nt * M <= 64 * 256 = 16384 = 64 * 256
+// Per (chain, antenna) values staged in LDS.
+template <typename R>
+struct CM {
+  R aI, aQ, base;  // base = ((tau-1)/tau) f_s - lse_I - lse_Q
+  int kI, kQ;
+};
 
-template <typename R, int MPT>
+template <typename R, int Q>
 __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
+  constexpr int M = Q * Q;
+  constexpr int NB = Q == 2 ? 1 : (Q == 4 ? 2 : (Q == 8 ? 3 : 4));
   const int b = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
-  const int nt = a.nt, nr = a.nr, Q = a.Q, M = Q * Q, C = a.C, Npad = a.Npad, N = a.N, CH = a.chunk;
-  int nb = 0;
-  while ((1 << nb) < Q) ++nb;
+  const int nt = a.nt, nr = a.nr, C = a.C, Npad = a.Npad, N = a.N, CH = a.chunk;
   const R* H = (const R*)a.H + 2 * (size_t)b * nt * nr;
   const R* y = (const R*)a.y + 2 * (size_t)b * nr;
   const InstParams ip = *(const InstParams*)(a.ws_inst + (size_t)b * a.inst_stride);
-  const R sigma2 = (R)ip.sigma2, s = (R)ip.s, tau = (R)ip.tau;
-  const R cw = (tau - R(1)) / tau;
+  const R s = (R)ip.s, tau = (R)ip.tau;
+  const R inv_s2 = R(1) / (R)ip.sigma2, inv_tau = R(1) / tau;
+  const R cw = (tau - R(1)) * inv_tau;
   const StateOff so = state_offsets(a.Cpad, Npad);
   const unsigned char* st = a.ws_state + (size_t)b * a.state_stride;
   const int8_t* K = (const int8_t*)(st + so.k);
   const int8_t* Kb = (const int8_t*)(st + so.kbest);
 
   extern __shared__ __attribute__((aligned(16))) unsigned char esm[];
-  R* rs = (R*)esm;                          // CH x nr complex residuals of the final states
-  R* rb2 = rs + 2 * (size_t)CH * nr;        // CH x nr |residual|^2 of the best states
-  R* cc = rb2 + (size_t)CH * nr;            // CH x nt complex H^H r
-  R* lse = cc + 2 * (size_t)CH * nt;        // CH x nt x 2 per-axis log normalisers
-  R* fs = lse + 2 * (size_t)CH * nt;        // CH
-  R* ebs = fs + CH;                         // CH
-  R* Gd = ebs + CH;                         // nt
-  R* lp = Gd + nt;                          // nt x M
-  int8_t* Ks = (int8_t*)(lp + (size_t)nt * M);  // CH x N
-  int8_t* Kbs = Ks + (size_t)CH * N;            // CH x N
+  CM<R>* cm = (CM<R>*)esm;                           // CH x nt
+  R* rs = (R*)(cm + (size_t)CH * nt);                // CH x nr complex residuals of the final states
+  R* rb2 = rs + 2 * (size_t)CH * nr;                 // CH x nr |residual|^2 of the best states
+  R* fs = rb2 + (size_t)CH * nr;                     // CH
+  R* ebs = fs + CH;                                  // CH
+  R* a2 = ebs + CH;                                  // nt
+  R* lp = a2 + nt;                                   // nt x M
+  int8_t* Ks = (int8_t*)(lp + (size_t)nt * M);       // CH x N
+  int8_t* Kbs = Ks + (size_t)CH * N;                 // CH x N
   __shared__ R best_e;
   __shared__ int best_c;
 
@@ -83,138 +95,151 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
       const R hre = H[2 * ((size_t)m * nr + i)], him = H[2 * ((size_t)m * nr + i) + 1];
       g += hre * hre + him * him;
     }
-    Gd[m] = g;
+    a2[m] = R(4) * s * s * g * inv_s2;
   }
   if (tid == 0) { best_e = R(INFINITY); best_c = 0; }
 
-  // per-thread accumulators
-  const int n_llr = nt * 2 * nb, n_marg = nt * M;
-  OnlineLse<R> lnum[kMaxLlrPerThread], lden[kMaxLlrPerThread];
-  OnlineLse<R> lmarg[MPT];
-  int mc[MPT];
+  // ownership: marginal rows (m, kI), in blocks of one row per thread, and bits (m, ax, bit)
+  const int n_rows = nt * Q, n_llr = nt * 2 * NB;
+  const int n_rb = (n_rows + nth - 1) / nth;
+  const bool single_chunk = CH >= C;
+  OnlineLse<R> lnum[2], lden[2];
+
+  for (int rb = 0; rb < n_rb; ++rb) {
+    const int row = rb * nth + tid;
+    OnlineLse<R> acc[Q];
+    int cnt[Q];
 #pragma unroll
-  for (int q = 0; q < MPT; ++q) mc[q] = 0;
+    for (int j = 0; j < Q; ++j) cnt[j] = 0;
 
-  for (int c0 = 0; c0 < C; c0 += CH) {
-    const int ch = C - c0 < CH ? C - c0 : CH;
-    __syncthreads();
-    for (int it = tid; it < ch * N; it += nth) {
-      const int c = it / N, n = it % N;
-      Ks[it] = K[(size_t)(c0 + c) * Npad + n];
-      Kbs[it] = Kb[(size_t)(c0 + c) * Npad + n];
-    }
-    __syncthreads();
-    // residuals of the final and of the best states
-    for (int it = tid; it < ch * nr; it += nth) {
-      const int c = it / nr, i = it % nr;
-      R re = y[2 * i], im = y[2 * i + 1];
-      R bre = re, bim = im;
-      for (int m = 0; m < nt; ++m) {
-        const R hre = H[2 * ((size_t)m * nr + i)], him = H[2 * ((size_t)m * nr + i) + 1];
-        const R xr = level(Ks[c * N + 2 * m]), xi = level(Ks[c * N + 2 * m + 1]);
-        re -= hre * xr - him * xi;
-        im -= hre * xi + him * xr;
-        const R br = level(Kbs[c * N + 2 * m]), bi = level(Kbs[c * N + 2 * m + 1]);
-        bre -= hre * br - him * bi;
-        bim -= hre * bi + him * br;
-      }
-      rs[2 * it] = re;
-      rs[2 * it + 1] = im;
-      rb2[it] = bre * bre + bim * bim;
-    }
-    __syncthreads();
-    for (int it = tid; it < ch * nt; it += nth) {
-      const int c = it / nt, m = it % nt;
-      R re = 0, im = 0;
-      for (int i = 0; i < nr; ++i) {
-        const R hre = H[2 * ((size_t)m * nr + i)], him = H[2 * ((size_t)m * nr + i) + 1];
-        const R rr = rs[2 * (c * nr + i)], ri = rs[2 * (c * nr + i) + 1];
-        re += hre * rr + him * ri;
-        im += hre * ri - him * rr;
-      }
-      cc[2 * it] = re;
-      cc[2 * it + 1] = im;
-    }
-    for (int c = tid; c < ch; c += nth) {
-      R e = 0, eb = 0;
-      for (int i = 0; i < nr; ++i) {
-        e += rs[2 * (c * nr + i)] * rs[2 * (c * nr + i)] + rs[2 * (c * nr + i) + 1] * rs[2 * (c * nr + i) + 1];
-        eb += rb2[c * nr + i];
-      }
-      fs[c] = -e / sigma2;
-      ebs[c] = eb;
-    }
-    __syncthreads();
-
-    // change of f when coordinate n of sample c moves to level k
-    auto delta = [&](int c, int n, int k) {
-      const int m = n >> 1;
-      const R d = level(k) - level(Ks[c * N + n]);
-      return (R(2) * d * cc[2 * (c * nt + m) + (n & 1)] - d * d * Gd[m]) / sigma2;
-    };
-
-    for (int it = tid; it < ch * nt; it += nth) {
-      const int c = it / nt, m = it % nt;
-      for (int ax = 0; ax < 2; ++ax) {
-        OnlineLse<R> l;
-        for (int k = 0; k < Q; ++k) l.add(delta(c, 2 * m + ax, k) / tau);
-        lse[2 * it + ax] = l.value();
-      }
-    }
-    if (tid == 0) {
-      for (int c = 0; c < ch; ++c)
-        if (ebs[c] < best_e) { best_e = ebs[c]; best_c = c0 + c; }
-    }
-    __syncthreads();
-
-    // bit LLRs
+    for (int c0 = 0; c0 < C; c0 += CH) {
+      const int ch = C - c0 < CH ? C - c0 : CH;
+      if (!single_chunk || rb == 0) {
+        __syncthreads();
+        for (int it = tid; it < ch * N; it += nth) {
+          const int c = it / N, n = it % N;
+          Ks[it] = K[(size_t)(c0 + c) * Npad + n];
+          Kbs[it] = Kb[(size_t)(c0 + c) * Npad + n];
+        }
+        __syncthreads();
+        // residuals of the final and of the best states
+        for (int it = tid; it < ch * nr; it += nth) {
+          const int c = it / nr, i = it % nr;
+          R re = y[2 * i], im = y[2 * i + 1];
+          R bre = re, bim = im;
+          for (int m = 0; m < nt; ++m) {
+            const R hre = H[2 * ((size_t)m * nr + i)], him = H[2 * ((size_t)m * nr + i) + 1];
+            const R xr = level(Ks[c * N + 2 * m]), xi = level(Ks[c * N + 2 * m + 1]);
+            re -= hre * xr - him * xi;
+            im -= hre * xi + him * xr;
+            const R br = level(Kbs[c * N + 2 * m]), bi = level(Kbs[c * N + 2 * m + 1]);
+            bre -= hre * br - him * bi;
+            bim -= hre * bi + him * br;
+          }
+          rs[2 * it] = re;
+          rs[2 * it + 1] = im;
+          rb2[it] = bre * bre + bim * bim;
+        }
+        __syncthreads();
+        for (int c = tid; c < ch; c += nth) {
+          R e = 0, eb = 0;
+          for (int i = 0; i < nr; ++i) {
+            e += rs[2 * (c * nr + i)] * rs[2 * (c * nr + i)] + rs[2 * (c * nr + i) + 1] * rs[2 * (c * nr + i) + 1];
+            eb += rb2[c * nr + i];
+          }
+          fs[c] = -e * inv_s2;
+          ebs[c] = eb;
+        }
+        __syncthreads();
+        // per (chain, antenna): H^H r, the per-axis log normalisers, the base term
+        for (int it = tid; it < ch * nt; it += nth) {
+          const int c = it / nt, m = it % nt;
+          R re = 0, im = 0;
+          for (int i = 0; i < nr; ++i) {
+            const R hre = H[2 * ((size_t)m * nr + i)], him = H[2 * ((size_t)m * nr + i) + 1];
+            const R rr = rs[2 * (c * nr + i)], ri = rs[2 * (c * nr + i) + 1];
+            re += hre * rr + him * ri;
+            im += hre * ri - him * rr;
+          }
+          CM<R> v;
+          v.aI = R(4) * s * re * inv_s2;
+          v.aQ = R(4) * s * im * inv_s2;
+          v.kI = Ks[c * N + 2 * m];
+          v.kQ = Ks[c * N + 2 * m + 1];
+          const R q2 = a2[m];
+          OnlineLse<R> li, lq;
 #pragma unroll
-    for (int q = 0; q < kMaxLlrPerThread; ++q) {
-      const int it = tid + q * nth;
-      if (it < n_llr) {
-        const int m = it / (2 * nb), ax = (it / nb) % 2, bit = it % nb;
-        const int n = 2 * m + ax;
-        const int mask = 1 << (nb - 1 - bit);
+          for (int k = 0; k < Q; ++k) {
+            const R eI = R(k - v.kI), eQ = R(k - v.kQ);
+            li.add(eI * (v.aI - q2 * eI) * inv_tau);
+            lq.add(eQ * (v.aQ - q2 * eQ) * inv_tau);
+          }
+          v.base = cw * fs[c] - li.value() - lq.value();
+          cm[it] = v;
+        }
+        if (tid == 0 && rb == 0) {
+          for (int c = 0; c < ch; ++c)
+            if (ebs[c] < best_e) { best_e = ebs[c]; best_c = c0 + c; }
+        }
+        __syncthreads();
+      }
+
+      // symbol marginals and the plain Monte Carlo histogram: row (m, kI)
+      if (row < n_rows) {
+        const int m = row / Q, kIt = row % Q;
+        const R q2 = a2[m];
         for (int c = 0; c < ch; ++c) {
-          const int k = Ks[c * N + n];
-          const int g = k ^ (k >> 1);
-          const R Fp = fs[c] + delta(c, n, ungray(g & ~mask));
-          const R Fm = fs[c] + delta(c, n, ungray(g | mask));
-          const R gm = (Fp - Fm) / tau;
-          lnum[q].add(cw * Fp - softplus(-gm));
-          lden[q].add(cw * Fm - softplus(gm));
+          const CM<R> v = cm[c * nt + m];
+          const R eI = R(kIt - v.kI);
+          const R b0 = v.base + eI * (v.aI - q2 * eI);
+#pragma unroll
+          for (int kQt = 0; kQt < Q; ++kQt) {
+            const R eQ = R(kQt - v.kQ);
+            acc[kQt].add(b0 + eQ * (v.aQ - q2 * eQ));
+            cnt[kQt] += (v.kI == kIt && v.kQ == kQt) ? 1 : 0;
+          }
+        }
+      }
+      // bit LLRs: item (m, ax, bit)
+      if (rb == 0) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int it = tid + q * nth;
+          if (it < n_llr) {
+            const int m = it / (2 * NB), ax = (it / NB) % 2, bit = it % NB;
+            const int mask = 1 << (NB - 1 - bit);
+            const R q2 = a2[m];
+            for (int c = 0; c < ch; ++c) {
+              const CM<R> v = cm[c * nt + m];
+              const int k = ax ? v.kQ : v.kI;
+              const R av = ax ? v.aQ : v.aI;
+              const int g = k ^ (k >> 1);
+              const R ep = R(ungray(g & ~mask) - k), em = R(ungray(g | mask) - k);
+              const R Fp = fs[c] + ep * (av - q2 * ep);
+              const R Fm = fs[c] + em * (av - q2 * em);
+              const R gm = (Fp - Fm) * inv_tau;
+              lnum[q].add(cw * Fp - softplus(-gm));
+              lden[q].add(cw * Fm - softplus(gm));
+            }
+          }
         }
       }
     }
-    // symbol marginals (IS) and the plain Monte Carlo histogram
+    if (row < n_rows) {
+      const int m = row / Q, kIt = row % Q;
 #pragma unroll
-    for (int q = 0; q < MPT; ++q) {
-      const int it = tid + q * nth;
-      if (it < n_marg) {
-        const int m = it / M, pt = it % M, kI = pt / Q, kQ = pt % Q;
-        for (int c = 0; c < ch; ++c) {
-          const R v = cw * fs[c] + delta(c, 2 * m, kI) + delta(c, 2 * m + 1, kQ)
-                      - lse[2 * (c * nt + m)] - lse[2 * (c * nt + m) + 1];
-          lmarg[q].add(v);
-          mc[q] += (Ks[c * N + 2 * m] == kI && Ks[c * N + 2 * m + 1] == kQ) ? 1 : 0;
-        }
+      for (int j = 0; j < Q; ++j) {
+        lp[(size_t)m * M + kIt * Q + j] = acc[j].value();
+        if (a.marginals_mc) a.marginals_mc[((size_t)b * nt + m) * M + kIt * Q + j] = (float)cnt[j] / (float)C;
       }
     }
   }
 
   if (a.llrs) {
 #pragma unroll
-    for (int q = 0; q < kMaxLlrPerThread; ++q) {
+    for (int q = 0; q < 2; ++q) {
       const int it = tid + q * nth;
       if (it < n_llr) a.llrs[(size_t)b * n_llr + it] = (float)(lnum[q].value() - lden[q].value());
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < MPT; ++q) {
-    const int it = tid + q * nth;
-    if (it < n_marg) {
-      lp[it] = lmarg[q].value();
-      if (a.marginals_mc) a.marginals_mc[(size_t)b * n_marg + it] = (float)mc[q] / (float)C;
     }
   }
   __syncthreads();
@@ -223,7 +248,7 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
       OnlineLse<R> l;
       for (int pt = 0; pt < M; ++pt) l.add(lp[(size_t)m * M + pt]);
       const R z = l.value();
-      for (int pt = 0; pt < M; ++pt) a.marginals[((size_t)b * nt + m) * M + pt] = (float)exp(lp[(size_t)m * M + pt] - z);
+      for (int pt = 0; pt < M; ++pt) a.marginals[((size_t)b * nt + m) * M + pt] = (float)fexp(lp[(size_t)m * M + pt] - z);
     }
   }
   // hard decision: smallest recomputed energy among the chains' best states
@@ -238,20 +263,24 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
 
 size_t estimate_lds_bytes(int nt, int nr, int M, int N, int chunk, bool fp64) {
   const size_t R = fp64 ? 8 : 4;
-  return R * (3 * (size_t)chunk * nr + 4 * (size_t)chunk * nt + 2 * (size_t)chunk + nt + (size_t)nt * M) +
+  const size_t cm = fp64 ? 32 : 20;
+  return cm * (size_t)chunk * nt + R * (3 * (size_t)chunk * nr + 2 * (size_t)chunk + nt + (size_t)nt * M) +
          2 * (size_t)chunk * N + 16;
 }
 
+// Chains per chunk (LDS budget 96 KiB).  When the (antenna, kI) rows outnumber
+// the 256 threads and there are several chunks, the chunks are staged again
+// for every block of rows.
 int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64) {
   int ch = C;
   while (ch > 1 && estimate_lds_bytes(nt, nr, M, N, ch, fp64) > 96 * 1024) ch = (ch + 1) / 2;
   return ch;
 }
 
-template <typename R, int MPT>
+template <typename R, int Q>
 static hipError_t launch_e(const EstArgs& a, hipStream_t s) {
-  const size_t lds = estimate_lds_bytes(a.nt, a.nr, a.Q * a.Q, a.N, a.chunk, a.fp64);
-  auto k = estimate_kernel<R, MPT>;
+  const size_t lds = estimate_lds_bytes(a.nt, a.nr, Q * Q, a.N, a.chunk, a.fp64);
+  auto k = estimate_kernel<R, Q>;
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -262,12 +291,13 @@ static hipError_t launch_e(const EstArgs& a, hipStream_t s) {
 
 template <typename R>
 static hipError_t launch_r(const EstArgs& a, hipStream_t s) {
-  const int items = a.nt * a.Q * a.Q;
-  if (items <= 256) return launch_e<R, 1>(a, s);
-  if (items <= 2048) return launch_e<R, 8>(a, s);
-  if (items <= 4096) return launch_e<R, 16>(a, s);
-  if (items <= 8192) return launch_e<R, 32>(a, s);
-  return launch_e<R, kMaxMargPerThread>(a, s);
+  switch (a.Q) {
+    case 2: return launch_e<R, 2>(a, s);
+    case 4: return launch_e<R, 4>(a, s);
+    case 8: return launch_e<R, 8>(a, s);
+    case 16: return launch_e<R, 16>(a, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_estimate(const EstArgs& a, hipStream_t s) {

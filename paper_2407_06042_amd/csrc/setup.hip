@@ -45,7 +45,8 @@ __device__ double block_reduce(double v, double* red, bool is_max) {
 }
 
 // Pack c * R(X) (N x N, zero-padded to Npad) into MFMA fragments.
-// npass = 3 (fp16 lo, mid, hi), 2 (fp16 lo, hi) or 1 (fp16 or bf16 when bf16 != 0).
+// npass = 3 (fp16 lo, mid, hi), 2 (fp16 lo, hi) or 1 (fp16 or bf16 when bf16 != 0);
+// the terms are stored in accumulation order, small terms first.
 // Fragment (pass p, row tile rt, K block kb) lane l element j holds entry
 // (16 rt + l%16, 16 (2 kb + j/4) + 4 (l/16) + j%4): the K order matches the
 // dimensions each lane owns in the accumulator layout, so the sampler builds
@@ -59,36 +60,35 @@ __device__ float pack_fragments(const cd* X, double c, int nt, int N, int RT, in
   if (mx > 0.0) frexp(mx, &ex);
   const int e2 = 14 - ex;  // scaled max in [2^13, 2^14)
   const double sc = ldexp(c, e2);
-  const int items = npass * RT * KB * 64;
+  const size_t pass_stride = (size_t)RT * KB * 1024;
+  const int items = RT * KB * 64;
   for (int it = threadIdx.x; it < items; it += blockDim.x) {
     const int l = it & 63;
     const int t = it >> 6;
     const int kb = t % KB;
-    const int rt = (t / KB) % RT;
-    const int p = t / (KB * RT);
+    const int rt = t / KB;
     const int n = 16 * rt + (l & 15);
-    union { _Float16 h[8]; __bf16 b[8]; uint4 u; } frag;
+    union { _Float16 h[8]; __bf16 b[8]; uint4 u; } f0, f1, f2;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int n2 = 16 * (2 * kb + (j >> 2)) + 4 * (l >> 4) + (j & 3);
       const double v = (n < N && n2 < N) ? sc * realeq(X, nt, n, n2) : 0.0;
       if (bf16) {
-        frag.b[j] = (__bf16)(float)v;
+        f0.b[j] = (__bf16)(float)v;
       } else {
         const _Float16 hi = (_Float16)(float)v;
         const double r1 = v - (double)hi;
         const _Float16 mid = (_Float16)(float)r1;
         const double r2 = r1 - (double)mid;
-        const _Float16 lo = (_Float16)(float)r2;
-        // storage order = accumulation order: small terms first
-        _Float16 val;
-        if (npass == 3) val = (p == 0) ? lo : (p == 1 ? mid : hi);
-        else if (npass == 2) val = (p == 0) ? (_Float16)(float)r1 : hi;
-        else val = hi;
-        frag.h[j] = val;
+        if (npass == 3) { f0.h[j] = (_Float16)(float)r2; f1.h[j] = mid; f2.h[j] = hi; }
+        else if (npass == 2) { f0.h[j] = mid; f1.h[j] = hi; }
+        else f0.h[j] = hi;
       }
     }
-    *(uint4*)(dst + (size_t)((p * RT + rt) * KB + kb) * 1024 + l * 16) = frag.u;
+    unsigned char* o = dst + (size_t)(rt * KB + kb) * 1024 + l * 16;
+    *(uint4*)o = f0.u;
+    if (npass > 1) *(uint4*)(o + pass_stride) = f1.u;
+    if (npass > 2) *(uint4*)(o + 2 * pass_stride) = f2.u;
   }
   return (float)ldexp(1.0, -e2);
 }
@@ -182,10 +182,14 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
     __syncthreads();
     for (int p = 0; p < nt; ++p) {
       for (int j = tid; j < nt; j += blockDim.x) { rowp[j] = W[p * nt + j]; colp[j] = W[j * nt + p]; }
+      if (tid == 0) {
+        const cd piv = W[p * nt + p];
+        const double den = piv.re * piv.re + piv.im * piv.im;
+        red[0] = piv.re / den;
+        red[1] = -piv.im / den;
+      }
       __syncthreads();
-      const cd piv = rowp[p];
-      const double den = piv.re * piv.re + piv.im * piv.im;
-      const cd inv = {piv.re / den, -piv.im / den};
+      const cd inv = {red[0], red[1]};
       for (int e = tid; e < nt * nt; e += blockDim.x) {
         const int i = e / nt, j = e % nt;
         cd v;
