@@ -57,13 +57,13 @@ struct CM {
   int kI, kQ;
 };
 
-template <typename R, int Q>
+template <typename R, int Q, bool SH>
 __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
   constexpr int M = Q * Q;
   constexpr int NB = Q == 2 ? 1 : (Q == 4 ? 2 : (Q == 8 ? 3 : 4));
   const int b = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
   const int nt = a.nt, nr = a.nr, C = a.C, Npad = a.Npad, N = a.N, CH = a.chunk;
-  const R* H = (const R*)a.H + 2 * (size_t)b * nt * nr;
+  const R* Hg = (const R*)a.H + 2 * (size_t)b * nt * nr;
   const R* y = (const R*)a.y + 2 * (size_t)b * nr;
   const InstParams ip = *(const InstParams*)(a.ws_inst + (size_t)b * a.inst_stride);
   const R s = (R)ip.s, tau = (R)ip.tau;
@@ -86,6 +86,14 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
   int8_t* Kbs = Ks + (size_t)CH * N;                 // CH x N
   __shared__ R best_e;
   __shared__ int best_c;
+  // H is read many times per element: stage it in LDS when it fits
+  const R* H = Hg;
+  if constexpr (SH) {
+    R* Hs = (R*)(((uintptr_t)(Kbs + (size_t)CH * N) + 15) & ~(uintptr_t)15);
+    for (int e = tid; e < 2 * nt * nr; e += nth) Hs[e] = Hg[e];
+    __syncthreads();
+    H = Hs;
+  }
 
   auto level = [&](int k) { return s * R(2 * k - Q + 1); };
 
@@ -279,8 +287,10 @@ int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64) {
 
 template <typename R, int Q>
 static hipError_t launch_e(const EstArgs& a, hipStream_t s) {
-  const size_t lds = estimate_lds_bytes(a.nt, a.nr, Q * Q, a.N, a.chunk, a.fp64);
-  auto k = estimate_kernel<R, Q>;
+  const size_t hbytes = 2 * (size_t)a.nt * a.nr * sizeof(R);
+  const bool sh = hbytes <= 32768;
+  const size_t lds = estimate_lds_bytes(a.nt, a.nr, Q * Q, a.N, a.chunk, a.fp64) + (sh ? hbytes + 16 : 0);
+  auto k = sh ? estimate_kernel<R, Q, true> : estimate_kernel<R, Q, false>;
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

@@ -101,10 +101,10 @@ __device__ void pack_dense(const cd* X, double c, int nt, int N, int Npad, doubl
   }
 }
 
-template <typename TIn>
+template <typename TIn, bool SH>
 __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   const int b = blockIdx.x, tid = threadIdx.x, nt = a.nt, nr = a.nr, N = a.N, Npad = a.Npad;
-  const TIn* H = (const TIn*)a.H + 2 * (size_t)b * nt * nr;
+  const TIn* Hg = (const TIn*)a.H + 2 * (size_t)b * nt * nr;
   const TIn* y = (const TIn*)a.y + 2 * (size_t)b * nr;
   const double sigma2 = (double)((const TIn*)a.sigma2)[b];
   extern __shared__ double smem_setup[];
@@ -115,6 +115,14 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   cd* colp = rowp + nt;
   double* red = (double*)(colp + nt);
   unsigned char* blk = a.ws_inst + (size_t)b * a.inst_stride;
+  // H is read 2 Nt times per element below: stage it in LDS when it fits
+  const TIn* H = Hg;
+  if constexpr (SH) {
+    TIn* Hs = (TIn*)(red + 256);
+    for (int e = tid; e < 2 * nt * nr; e += blockDim.x) Hs[e] = Hg[e];
+    __syncthreads();
+    H = Hs;
+  }
 
   const int Q = a.Q, M = Q * Q;
   const double s = sqrt(3.0 / (2.0 * (M - 1)));
@@ -247,8 +255,11 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
 }
 
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)(a.nt * a.nt + 4 * a.nt) * sizeof(cd) + 256 * sizeof(double);
-  auto k = a.fp64 ? setup_kernel<double> : setup_kernel<float>;
+  const size_t hbytes = 2 * (size_t)a.nt * a.nr * (a.fp64 ? sizeof(double) : sizeof(float));
+  const bool sh = hbytes <= 32768;
+  const size_t lds = (size_t)(a.nt * a.nt + 4 * a.nt) * sizeof(cd) + 256 * sizeof(double) + (sh ? hbytes : 0);
+  auto k = a.fp64 ? (sh ? setup_kernel<double, true> : setup_kernel<double, false>)
+                  : (sh ? setup_kernel<float, true> : setup_kernel<float, false>);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
