@@ -86,22 +86,29 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
   int8_t* Kbs = Ks + (size_t)CH * N;                 // CH x N
   __shared__ R best_e;
   __shared__ int best_c;
-  // H is read many times per element: stage it in LDS when it fits
-  const R* H = Hg;
+  // H is read many times per element: stage it in LDS when it fits, transposed
+  // with a padded row (Ht[i][m], leading dimension nt + 1) so that both the
+  // row-wise (residual) and the column-wise (H^H r) sweeps are conflict-free.
+  const int ldh = nt + 1;
+  R* Ht = (R*)(((uintptr_t)(Kbs + (size_t)CH * N) + 15) & ~(uintptr_t)15);
   if constexpr (SH) {
-    R* Hs = (R*)(((uintptr_t)(Kbs + (size_t)CH * N) + 15) & ~(uintptr_t)15);
-    for (int e = tid; e < 2 * nt * nr; e += nth) Hs[e] = Hg[e];
+    for (int e = tid; e < nt * nr; e += nth) {
+      const int m = e / nr, i = e % nr;
+      Ht[2 * (i * ldh + m)] = Hg[2 * (size_t)e];
+      Ht[2 * (i * ldh + m) + 1] = Hg[2 * (size_t)e + 1];
+    }
     __syncthreads();
-    H = Hs;
   }
+  auto hre = [&](int m, int i) -> R { if constexpr (SH) return Ht[2 * (i * ldh + m)]; else return Hg[2 * ((size_t)m * nr + i)]; };
+  auto him = [&](int m, int i) -> R { if constexpr (SH) return Ht[2 * (i * ldh + m) + 1]; else return Hg[2 * ((size_t)m * nr + i) + 1]; };
 
   auto level = [&](int k) { return s * R(2 * k - Q + 1); };
 
   for (int m = tid; m < nt; m += nth) {
     R g = 0;
     for (int i = 0; i < nr; ++i) {
-      const R hre = H[2 * ((size_t)m * nr + i)], him = H[2 * ((size_t)m * nr + i) + 1];
-      g += hre * hre + him * him;
+      const R hr = hre(m, i), hi = him(m, i);
+      g += hr * hr + hi * hi;
     }
     a2[m] = R(4) * s * s * g * inv_s2;
   }
@@ -136,13 +143,13 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
           R re = y[2 * i], im = y[2 * i + 1];
           R bre = re, bim = im;
           for (int m = 0; m < nt; ++m) {
-            const R hre = H[2 * ((size_t)m * nr + i)], him = H[2 * ((size_t)m * nr + i) + 1];
+            const R hr = hre(m, i), hi = him(m, i);
             const R xr = level(Ks[c * N + 2 * m]), xi = level(Ks[c * N + 2 * m + 1]);
-            re -= hre * xr - him * xi;
-            im -= hre * xi + him * xr;
+            re -= hr * xr - hi * xi;
+            im -= hr * xi + hi * xr;
             const R br = level(Kbs[c * N + 2 * m]), bi = level(Kbs[c * N + 2 * m + 1]);
-            bre -= hre * br - him * bi;
-            bim -= hre * bi + him * br;
+            bre -= hr * br - hi * bi;
+            bim -= hr * bi + hi * br;
           }
           rs[2 * it] = re;
           rs[2 * it + 1] = im;
@@ -164,10 +171,10 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
           const int c = it / nt, m = it % nt;
           R re = 0, im = 0;
           for (int i = 0; i < nr; ++i) {
-            const R hre = H[2 * ((size_t)m * nr + i)], him = H[2 * ((size_t)m * nr + i) + 1];
+            const R hr = hre(m, i), hi = him(m, i);
             const R rr = rs[2 * (c * nr + i)], ri = rs[2 * (c * nr + i) + 1];
-            re += hre * rr + him * ri;
-            im += hre * ri - him * rr;
+            re += hr * rr + hi * ri;
+            im += hr * ri - hi * rr;
           }
           CM<R> v;
           v.aI = R(4) * s * re * inv_s2;
@@ -287,7 +294,7 @@ int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64) {
 
 template <typename R, int Q>
 static hipError_t launch_e(const EstArgs& a, hipStream_t s) {
-  const size_t hbytes = 2 * (size_t)a.nt * a.nr * sizeof(R);
+  const size_t hbytes = 2 * (size_t)(a.nt + 1) * a.nr * sizeof(R);
   const bool sh = hbytes <= 32768;
   const size_t lds = estimate_lds_bytes(a.nt, a.nr, Q * Q, a.N, a.chunk, a.fp64) + (sh ? hbytes + 16 : 0);
   auto k = sh ? estimate_kernel<R, Q, true> : estimate_kernel<R, Q, false>;

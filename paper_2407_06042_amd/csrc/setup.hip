@@ -23,9 +23,9 @@ __device__ __forceinline__ cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.i
 __device__ __forceinline__ cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __device__ __forceinline__ cd cconjmul(cd a, cd b) { return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re}; }
 
-// Entry (n, n2) of the interleaved real-equivalent of complex X (ld = nt).
-__device__ __forceinline__ double realeq(const cd* X, int nt, int n, int n2) {
-  const cd v = X[(n >> 1) * nt + (n2 >> 1)];
+// Entry (n, n2) of the interleaved real-equivalent of complex X (leading dimension ld).
+__device__ __forceinline__ double realeq(const cd* X, int ld, int n, int n2) {
+  const cd v = X[(n >> 1) * ld + (n2 >> 1)];
   const int a = n & 1, b = n2 & 1;
   return (a == b) ? v.re : (a == 0 ? -v.im : v.im);
 }
@@ -51,10 +51,13 @@ __device__ double block_reduce(double v, double* red, bool is_max) {
 // (16 rt + l%16, 16 (2 kb + j/4) + 4 (l/16) + j%4): the K order matches the
 // dimensions each lane owns in the accumulator layout, so the sampler builds
 // the B operand from its own registers.
-__device__ float pack_fragments(const cd* X, double c, int nt, int N, int RT, int KB, int npass, int bf16,
+__device__ float pack_fragments(const cd* X, int ld, double c, int nt, int N, int RT, int KB, int npass, int bf16,
                                 unsigned char* dst, double* red) {
   double mx = 0.0;
-  for (int e = threadIdx.x; e < nt * nt; e += blockDim.x) mx = fmax(mx, fmax(fabs(X[e].re), fabs(X[e].im)));
+  for (int e = threadIdx.x; e < nt * nt; e += blockDim.x) {
+    const cd v = X[(e / nt) * ld + e % nt];
+    mx = fmax(mx, fmax(fabs(v.re), fabs(v.im)));
+  }
   mx = block_reduce(mx, red, true) * fabs(c);
   int ex = 0;
   if (mx > 0.0) frexp(mx, &ex);
@@ -72,7 +75,7 @@ __device__ float pack_fragments(const cd* X, double c, int nt, int N, int RT, in
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int n2 = 16 * (2 * kb + (j >> 2)) + 4 * (l >> 4) + (j & 3);
-      const double v = (n < N && n2 < N) ? sc * realeq(X, nt, n, n2) : 0.0;
+      const double v = (n < N && n2 < N) ? sc * realeq(X, ld, n, n2) : 0.0;
       if (bf16) {
         f0.b[j] = (__bf16)(float)v;
       } else {
@@ -94,35 +97,28 @@ __device__ float pack_fragments(const cd* X, double c, int nt, int N, int RT, in
 }
 
 // Dense row-major double copy of c * R(X), zero-padded to Npad x Npad.
-__device__ void pack_dense(const cd* X, double c, int nt, int N, int Npad, double* dst) {
+__device__ void pack_dense(const cd* X, int ld, double c, int N, int Npad, double* dst) {
   for (int e = threadIdx.x; e < Npad * Npad; e += blockDim.x) {
     const int n = e / Npad, n2 = e % Npad;
-    dst[e] = (n < N && n2 < N) ? c * realeq(X, nt, n, n2) : 0.0;
+    dst[e] = (n < N && n2 < N) ? c * realeq(X, ld, n, n2) : 0.0;
   }
 }
 
-template <typename TIn, bool SH>
+template <typename TIn>
 __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   const int b = blockIdx.x, tid = threadIdx.x, nt = a.nt, nr = a.nr, N = a.N, Npad = a.Npad;
+  const int ld = nt + 1;  // padded leading dimension of the LDS matrices (no bank conflicts on columns)
   const TIn* Hg = (const TIn*)a.H + 2 * (size_t)b * nt * nr;
   const TIn* y = (const TIn*)a.y + 2 * (size_t)b * nr;
   const double sigma2 = (double)((const TIn*)a.sigma2)[b];
   extern __shared__ double smem_setup[];
-  cd* W = (cd*)smem_setup;
-  cd* z = W + nt * nt;
+  cd* W = (cd*)smem_setup;             // nt x ld
+  cd* z = W + nt * ld;
   cd* bv = z + nt;
   cd* rowp = bv + nt;
   cd* colp = rowp + nt;
   double* red = (double*)(colp + nt);
   unsigned char* blk = a.ws_inst + (size_t)b * a.inst_stride;
-  // H is read 2 Nt times per element below: stage it in LDS when it fits
-  const TIn* H = Hg;
-  if constexpr (SH) {
-    TIn* Hs = (TIn*)(red + 256);
-    for (int e = tid; e < 2 * nt * nr; e += blockDim.x) Hs[e] = Hg[e];
-    __syncthreads();
-    H = Hs;
-  }
 
   const int Q = a.Q, M = Q * Q;
   const double s = sqrt(3.0 / (2.0 * (M - 1)));
@@ -131,27 +127,56 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   const double beta = a.naive ? 1.0 : a.beta_mult * s * s / sigma2;
   const double gamma = a.gamma_mult * sigma2 / (2.0 * s * s);
 
-  // G = H^H H, z = H^H y, ||y||^2, finiteness of the inputs
+  // G = H^H H and z = H^H y.  H is staged in LDS in chunks of receive
+  // antennas, transposed with a padded row (Ht[i][m]); each thread accumulates
+  // its (m, m2) entries (and entries of z) in registers across the chunks.
   double nonfinite = 0.0;
-  for (int e = tid; e < nt * nt; e += blockDim.x) {
-    const int m = e / nt, m2 = e % nt;
-    cd acc = {0.0, 0.0};
-    for (int i = 0; i < nr; ++i) {
-      const cd hm = {(double)H[2 * ((size_t)m * nr + i)], (double)H[2 * ((size_t)m * nr + i) + 1]};
-      const cd hm2 = {(double)H[2 * ((size_t)m2 * nr + i)], (double)H[2 * ((size_t)m2 * nr + i) + 1]};
-      acc = cadd(acc, cconjmul(hm, hm2));
+  {
+    constexpr int kIC = 64, kEPT = 17;  // (64*64 + 64) / 256 entries per thread at most
+    typedef struct { TIn re, im; } tc;
+    tc* Ht = (tc*)(red + 256);          // kIC x (nt + 1)
+    tc* yc = Ht + kIC * ld;              // kIC
+    const int total = nt * nt + nt;
+    double are[kEPT], aim[kEPT];
+#pragma unroll
+    for (int q = 0; q < kEPT; ++q) { are[q] = 0.0; aim[q] = 0.0; }
+    for (int i0 = 0; i0 < nr; i0 += kIC) {
+      const int ic = nr - i0 < kIC ? nr - i0 : kIC;
+      for (int e = tid; e < ic * nt; e += blockDim.x) {
+        const int m = e / ic, ii = e % ic;
+        Ht[ii * ld + m] = {Hg[2 * ((size_t)m * nr + i0 + ii)], Hg[2 * ((size_t)m * nr + i0 + ii) + 1]};
+      }
+      for (int ii = tid; ii < ic; ii += blockDim.x) yc[ii] = {y[2 * (i0 + ii)], y[2 * (i0 + ii) + 1]};
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kEPT; ++q) {
+        const int e = tid + q * (int)blockDim.x;
+        if (e < total) {
+          const bool isz = e >= nt * nt;
+          const int m = isz ? e - nt * nt : e / nt, m2 = isz ? 0 : e % nt;
+          double re = are[q], im = aim[q];
+          for (int ii = 0; ii < ic; ++ii) {
+            const tc hv = Ht[ii * ld + m];
+            const tc bvv = isz ? yc[ii] : Ht[ii * ld + m2];
+            const double ar = hv.re, ai = hv.im, br = bvv.re, bi = bvv.im;
+            re += ar * br + ai * bi;
+            im += ar * bi - ai * br;
+          }
+          are[q] = re;
+          aim[q] = im;
+        }
+      }
+      __syncthreads();
     }
-    W[e] = acc;
-    if (!isfinite(acc.re) || !isfinite(acc.im)) nonfinite = 1.0;
-  }
-  for (int m = tid; m < nt; m += blockDim.x) {
-    cd acc = {0.0, 0.0};
-    for (int i = 0; i < nr; ++i) {
-      const cd hm = {(double)H[2 * ((size_t)m * nr + i)], (double)H[2 * ((size_t)m * nr + i) + 1]};
-      const cd yi = {(double)y[2 * i], (double)y[2 * i + 1]};
-      acc = cadd(acc, cconjmul(hm, yi));
+#pragma unroll
+    for (int q = 0; q < kEPT; ++q) {
+      const int e = tid + q * (int)blockDim.x;
+      if (e < total) {
+        if (e >= nt * nt) z[e - nt * nt] = {are[q], aim[q]};
+        else W[(e / nt) * ld + e % nt] = {are[q], aim[q]};
+        if (!isfinite(are[q]) || !isfinite(aim[q])) nonfinite = 1.0;
+      }
     }
-    z[m] = acc;
   }
   double yy = 0.0;
   for (int i = tid; i < nr; i += blockDim.x) {
@@ -174,11 +199,11 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   // energy matrix and vector
   if (a.fp64) {
     double* EGd = (double*)(blk + kParamBytes) + (size_t)Npad * Npad;
-    pack_dense(W, cE, nt, N, Npad, EGd);
+    pack_dense(W, ld, cE, N, Npad, EGd);
     double* ezd = (double*)(blk + kParamBytes) + 2 * (size_t)Npad * Npad + Npad;
     for (int n = tid; n < Npad; n += blockDim.x) ezd[n] = n < N ? cz * realeq_vec(z, n) : 0.0;
   } else {
-    scaleE = pack_fragments(W, cE, nt, N, a.RT, a.KB, kEPasses, 0, frag + (size_t)npP * a.RT * a.KB * 1024, red);
+    scaleE = pack_fragments(W, ld, cE, nt, N, a.RT, a.KB, kEPasses, 0, frag + (size_t)npP * a.RT * a.KB * 1024, red);
     float* ezf = (float*)(frag + (size_t)(npP + kEPasses) * a.RT * a.KB * 1024) + Npad;
     for (int n = tid; n < Npad; n += blockDim.x) ezf[n] = n < N ? (float)(cz * realeq_vec(z, n)) : 0.0f;
   }
@@ -186,12 +211,12 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
 
   if (!a.naive) {
     // W <- (G + gamma I)^-1 by in-place Gauss-Jordan
-    for (int m = tid; m < nt; m += blockDim.x) W[m * nt + m].re += gamma;
+    for (int m = tid; m < nt; m += blockDim.x) W[m * ld + m].re += gamma;
     __syncthreads();
     for (int p = 0; p < nt; ++p) {
-      for (int j = tid; j < nt; j += blockDim.x) { rowp[j] = W[p * nt + j]; colp[j] = W[j * nt + p]; }
+      for (int j = tid; j < nt; j += blockDim.x) { rowp[j] = W[p * ld + j]; colp[j] = W[j * ld + p]; }
       if (tid == 0) {
-        const cd piv = W[p * nt + p];
+        const cd piv = W[p * ld + p];
         const double den = piv.re * piv.re + piv.im * piv.im;
         red[0] = piv.re / den;
         red[1] = -piv.im / den;
@@ -204,29 +229,29 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
         if (i == p && j == p) v = inv;
         else if (i == p) v = cmul(rowp[j], inv);
         else if (j == p) { const cd t = cmul(colp[i], inv); v = {-t.re, -t.im}; }
-        else { const cd t = cmul(cmul(colp[i], rowp[j]), inv); v = {W[e].re - t.re, W[e].im - t.im}; }
-        W[e] = v;
+        else { const cd t = cmul(cmul(colp[i], rowp[j]), inv); v = {W[i * ld + j].re - t.re, W[i * ld + j].im - t.im}; }
+        W[i * ld + j] = v;
       }
       __syncthreads();
     }
     // b = M z, then W <- A = I - gamma M
     for (int m = tid; m < nt; m += blockDim.x) {
       cd acc = {0.0, 0.0};
-      for (int j = 0; j < nt; ++j) acc = cadd(acc, cmul(W[m * nt + j], z[j]));
+      for (int j = 0; j < nt; ++j) acc = cadd(acc, cmul(W[m * ld + j], z[j]));
       bv[m] = acc;
     }
     __syncthreads();
     for (int e = tid; e < nt * nt; e += blockDim.x) {
       const int i = e / nt, j = e % nt;
-      W[e] = {(i == j ? 1.0 : 0.0) - gamma * W[e].re, -gamma * W[e].im};
+      W[i * ld + j] = {(i == j ? 1.0 : 0.0) - gamma * W[i * ld + j].re, -gamma * W[i * ld + j].im};
     }
     __syncthreads();
     if (a.fp64) {
-      pack_dense(W, cP, nt, N, Npad, (double*)(blk + kParamBytes));
+      pack_dense(W, ld, cP, N, Npad, (double*)(blk + kParamBytes));
       double* pbd = (double*)(blk + kParamBytes) + 2 * (size_t)Npad * Npad;
       for (int n = tid; n < Npad; n += blockDim.x) pbd[n] = n < N ? cb * realeq_vec(bv, n) : 0.0;
     } else {
-      scaleP = pack_fragments(W, cP, nt, N, a.RT, a.KB, npP, a.pm == PM_BF16X1, frag, red);
+      scaleP = pack_fragments(W, ld, cP, nt, N, a.RT, a.KB, npP, a.pm == PM_BF16X1, frag, red);
       float* pbf = (float*)(frag + (size_t)(npP + kEPasses) * a.RT * a.KB * 1024);
       for (int n = tid; n < Npad; n += blockDim.x) pbf[n] = n < N ? (float)(cb * realeq_vec(bv, n)) : 0.0f;
     }
@@ -255,11 +280,10 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
 }
 
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
-  const size_t hbytes = 2 * (size_t)a.nt * a.nr * (a.fp64 ? sizeof(double) : sizeof(float));
-  const bool sh = hbytes <= 32768;
-  const size_t lds = (size_t)(a.nt * a.nt + 4 * a.nt) * sizeof(cd) + 256 * sizeof(double) + (sh ? hbytes : 0);
-  auto k = a.fp64 ? (sh ? setup_kernel<double, true> : setup_kernel<double, false>)
-                  : (sh ? setup_kernel<float, true> : setup_kernel<float, false>);
+  const size_t in_bytes = a.fp64 ? 16 : 8;  // complex input element
+  const size_t lds = (size_t)(a.nt * (a.nt + 1) + 4 * a.nt) * sizeof(cd) + 256 * sizeof(double) +
+                     (64 * (size_t)(a.nt + 1) + 64) * in_bytes;
+  auto k = a.fp64 ? setup_kernel<double> : setup_kernel<float>;
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
