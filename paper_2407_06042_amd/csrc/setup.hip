@@ -132,8 +132,8 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   // its (m, m2) entries (and entries of z) in registers across the chunks.
   double nonfinite = 0.0;
   {
-    constexpr int kIC = 64, kEPT = 17;  // (64*64 + 64) / 256 entries per thread at most
-    typedef struct { TIn re, im; } tc;
+    constexpr int kIC = 32, kEPT = 17;  // (64*64 + 64) / 256 entries per thread at most
+    typedef cd tc;
     tc* Ht = (tc*)(red + 256);          // kIC x (nt + 1)
     tc* yc = Ht + kIC * ld;              // kIC
     const int total = nt * nt + nt;
@@ -144,9 +144,9 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
       const int ic = nr - i0 < kIC ? nr - i0 : kIC;
       for (int e = tid; e < ic * nt; e += blockDim.x) {
         const int m = e / ic, ii = e % ic;
-        Ht[ii * ld + m] = {Hg[2 * ((size_t)m * nr + i0 + ii)], Hg[2 * ((size_t)m * nr + i0 + ii) + 1]};
+        Ht[ii * ld + m] = {(double)Hg[2 * ((size_t)m * nr + i0 + ii)], (double)Hg[2 * ((size_t)m * nr + i0 + ii) + 1]};
       }
-      for (int ii = tid; ii < ic; ii += blockDim.x) yc[ii] = {y[2 * (i0 + ii)], y[2 * (i0 + ii) + 1]};
+      for (int ii = tid; ii < ic; ii += blockDim.x) yc[ii] = {(double)y[2 * (i0 + ii)], (double)y[2 * (i0 + ii) + 1]};
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < kEPT; ++q) {
@@ -213,24 +213,36 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
     // W <- (G + gamma I)^-1 by in-place Gauss-Jordan
     for (int m = tid; m < nt; m += blockDim.x) W[m * ld + m].re += gamma;
     __syncthreads();
+    // Gauss-Jordan step p: row p is scaled by the pivot inverse (sr), every
+    // other row i subtracts col[i] * sr, where column p is treated as zero so
+    // that it receives -col[i] * inv.  Entries are visited in row-major order
+    // with incremental indices (no integer division in the loop).
+    const int di = (int)blockDim.x / nt, dj = (int)blockDim.x % nt;
+    const int i_start = tid / nt, j_start = tid % nt;
     for (int p = 0; p < nt; ++p) {
-      for (int j = tid; j < nt; j += blockDim.x) { rowp[j] = W[p * ld + j]; colp[j] = W[j * ld + p]; }
-      if (tid == 0) {
+      for (int j = tid; j < nt; j += blockDim.x) {
         const cd piv = W[p * ld + p];
         const double den = piv.re * piv.re + piv.im * piv.im;
-        red[0] = piv.re / den;
-        red[1] = -piv.im / den;
+        const cd inv = {piv.re / den, -piv.im / den};
+        rowp[j] = (j == p) ? inv : cmul(W[p * ld + j], inv);
+        colp[j] = W[j * ld + p];
       }
       __syncthreads();
-      const cd inv = {red[0], red[1]};
+      int i = i_start, j = j_start;
       for (int e = tid; e < nt * nt; e += blockDim.x) {
-        const int i = e / nt, j = e % nt;
+        const cd sr = rowp[j];
         cd v;
-        if (i == p && j == p) v = inv;
-        else if (i == p) v = cmul(rowp[j], inv);
-        else if (j == p) { const cd t = cmul(colp[i], inv); v = {-t.re, -t.im}; }
-        else { const cd t = cmul(cmul(colp[i], rowp[j]), inv); v = {W[i * ld + j].re - t.re, W[i * ld + j].im - t.im}; }
+        if (i == p) {
+          v = sr;
+        } else {
+          const cd t = cmul(colp[i], sr);
+          const cd w = (j == p) ? cd{0.0, 0.0} : W[i * ld + j];
+          v = {w.re - t.re, w.im - t.im};
+        }
         W[i * ld + j] = v;
+        i += di;
+        j += dj;
+        if (j >= nt) { j -= nt; ++i; }
       }
       __syncthreads();
     }
@@ -280,9 +292,8 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
 }
 
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
-  const size_t in_bytes = a.fp64 ? 16 : 8;  // complex input element
   const size_t lds = (size_t)(a.nt * (a.nt + 1) + 4 * a.nt) * sizeof(cd) + 256 * sizeof(double) +
-                     (64 * (size_t)(a.nt + 1) + 64) * in_bytes;
+                     (32 * (size_t)(a.nt + 1) + 32) * sizeof(cd);
   auto k = a.fp64 ? setup_kernel<double> : setup_kernel<float>;
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
