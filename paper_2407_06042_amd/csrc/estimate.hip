@@ -32,9 +32,10 @@ template <typename R>
 struct OnlineLse {
   R mx, sum;
   __device__ OnlineLse() : mx(-INFINITY), sum(R(0)) {}
-  __device__ __forceinline__ void add(R v) {
-    if (v > mx) { sum = sum * fexp(mx - v) + R(1); mx = v; }
-    else sum += fexp(v - mx);
+  __device__ __forceinline__ void add(R v) {  // branch-free: both lanes of a divergent update cost the same
+    const R m2 = v > mx ? v : mx;
+    sum = sum * fexp(mx - m2) + fexp(v - m2);
+    mx = m2;
   }
   __device__ R value() const { return mx + flog(sum); }
 };
@@ -113,6 +114,7 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
     a2[m] = R(4) * s * s * g * inv_s2;
   }
   if (tid == 0) { best_e = R(INFINITY); best_c = 0; }
+  for (int e = tid; e < nt * M; e += nth) ((int*)lp)[e] = 0;
 
   // ownership: marginal rows (m, kI), in blocks of one row per thread, and bits (m, ax, bit)
   const int n_rows = nt * Q, n_llr = nt * 2 * NB;
@@ -123,9 +125,6 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
   for (int rb = 0; rb < n_rb; ++rb) {
     const int row = rb * nth + tid;
     OnlineLse<R> acc[Q];
-    int cnt[Q];
-#pragma unroll
-    for (int j = 0; j < Q; ++j) cnt[j] = 0;
 
     for (int c0 = 0; c0 < C; c0 += CH) {
       const int ch = C - c0 < CH ? C - c0 : CH;
@@ -196,6 +195,14 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
           for (int c = 0; c < ch; ++c)
             if (ebs[c] < best_e) { best_e = ebs[c]; best_c = c0 + c; }
         }
+        if (rb == 0 && a.marginals_mc) {
+          // plain Monte Carlo histogram of the final samples (eq. mc), in LDS
+          int* hist = (int*)lp;
+          for (int it = tid; it < ch * nt; it += nth) {
+            const int c = it / nt, m = it % nt;
+            atomicAdd(&hist[m * M + Ks[c * N + 2 * m] * Q + Ks[c * N + 2 * m + 1]], 1);
+          }
+        }
         __syncthreads();
       }
 
@@ -211,7 +218,6 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
           for (int kQt = 0; kQt < Q; ++kQt) {
             const R eQ = R(kQt - v.kQ);
             acc[kQt].add(b0 + eQ * (v.aQ - q2 * eQ));
-            cnt[kQt] += (v.kI == kIt && v.kQ == kQt) ? 1 : 0;
           }
         }
       }
@@ -240,13 +246,16 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
         }
       }
     }
+    if (rb == 0 && a.marginals_mc) {
+      __syncthreads();
+      const int* hist = (const int*)lp;
+      for (int e = tid; e < nt * M; e += nth) a.marginals_mc[(size_t)b * nt * M + e] = (float)hist[e] / (float)C;
+      __syncthreads();
+    }
     if (row < n_rows) {
       const int m = row / Q, kIt = row % Q;
 #pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        lp[(size_t)m * M + kIt * Q + j] = acc[j].value();
-        if (a.marginals_mc) a.marginals_mc[((size_t)b * nt + m) * M + kIt * Q + j] = (float)cnt[j] / (float)C;
-      }
+      for (int j = 0; j < Q; ++j) lp[(size_t)m * M + kIt * Q + j] = acc[j].value();
     }
   }
 
