@@ -57,7 +57,7 @@ def gx_flops_per_chain_iter(nt):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("common.hpp", "sampler_impl.hpp", "sampler_f16x2.hip", "setup.hip"):
+    for f in ("common.hpp", "sampler_impl.hpp", "sampler_f16x2.hip"):
         with open(os.path.join(ROOT, "paper_2407_06042_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
