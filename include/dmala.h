@@ -76,6 +76,14 @@ typedef struct {
   double alpha_mult;         /* alpha = alpha_mult * sigma^2;          <= 0 selects 1 */
   double beta_mult;          /* beta  = beta_mult * dmin^2 / sigma^2;  <= 0 selects 1 */
   double gamma_mult;         /* gamma = gamma_mult * sigma^2 / (2 dmin^2); <= 0 selects 1 */
+  int32_t tile_config;       /* sampler work layout: 0 = automatic; k >= 1 selects layout k - 1:
+                                0: 32 dims, 1 wave / 16 chains, matrices in LDS
+                                1: 64 dims, 1 wave / 16 chains, LDS
+                                2: 128 dims, 1 wave / 16 chains, LDS
+                                3: 128 dims, 2 waves / 16 chains, matrices read from L2
+                                4: 256 dims, 4 waves / 16 chains, L2
+                                (dims = 2 Nt rounded up to 32; a layout that does not match the
+                                shape returns DMALA_ERR_UNSUPPORTED) */
 } dmala_params;
 
 /* Device output buffers; any pointer may be NULL to skip that output. */
@@ -104,7 +112,7 @@ size_t dmala_workspace_size(int32_t n_inst, int32_t nt, int32_t nr, int32_t qam_
  *   H, y, sigma2: device inputs as described above; sigma2[b] > 0 (Lemma 1).
  *   constellation: NULL, or host array of M complex float points that must
  *     equal the canonical unit-energy QAM (validated; others are unsupported).
- *   Limits: 1 <= nt <= 64, 1 <= nr <= 4096, M in {4, 16, 64, 256}; FP64 needs nt <= 32.
+ *   Limits: 1 <= nt <= 128, 1 <= nr <= 4096, M in {4, 16, 64, 256}; FP64 needs nt <= 32.
  * Enqueues setup, sampler and estimator kernels on `stream` and returns. */
 dmala_status dmala_detect(const void* H, const void* y, const void* sigma2,
                           int32_t n_inst, int32_t nt, int32_t nr, int32_t qam_order,

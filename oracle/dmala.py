@@ -273,22 +273,24 @@ def _lse(a, axis):
     return np.squeeze(mx, axis=axis) + np.log(np.sum(np.exp(a - mx), axis=axis))
 
 
-def llr_is(prob, k_samples, log_w=None):
+def llr_is(prob, k_samples, log_w=None, antennas=None):
     """IS-based bit LLRs (eq. llr_is, computed as eq. llr_simple in the log domain).
 
     k_samples: (S, N) level indices of samples from pi_a.  log_w: optional
     per-sample log weights replacing the uniform 1/S (used to pin the
     estimator to the exact expectation).  Returns (Nt, 2*log2(Q)) LLRs,
-    L = log p(b=+1)/p(b=-1), bits ordered [I MSB..LSB, Q MSB..LSB].
+    L = log p(b=+1)/p(b=-1), bits ordered [I MSB..LSB, Q MSB..LSB]; with
+    `antennas` only those rows are computed (the others are NaN).
     """
     k_samples = np.asarray(k_samples)
     S = k_samples.shape[0]
     lw = np.zeros(S) if log_w is None else np.asarray(log_w, dtype=np.float64)
     nb, tau = prob.nbits_axis, prob.tau
     c = (tau - 1.0) / tau
-    out = np.zeros((prob.Nt, 2 * nb))
+    out = np.full((prob.Nt, 2 * nb), np.nan)
     labels = gray_bits(k_samples, nb)                       # demap: (S, N, nb)
-    for n in range(prob.N):
+    ants = range(prob.Nt) if antennas is None else antennas
+    for n in [2 * m + ax for m in ants for ax in (0, 1)]:
         m, axis = n // 2, n % 2
         for b in range(nb):
             lab_p = labels[:, n, :].copy()
@@ -308,10 +310,11 @@ def llr_is(prob, k_samples, log_w=None):
     return out
 
 
-def marginals_is(prob, k_samples, log_w=None):
+def marginals_is(prob, k_samples, log_w=None, antennas=None):
     """Symbol posterior marginals, IS estimator at symbol level (see module doc).
 
-    Returns (Nt, M) probabilities over points indexed k_I * Q + k_Q.
+    Returns (Nt, M) probabilities over points indexed k_I * Q + k_Q; with
+    `antennas` only those rows are computed (the others are NaN).
     """
     k_samples = np.asarray(k_samples)
     S = k_samples.shape[0]
@@ -320,8 +323,8 @@ def marginals_is(prob, k_samples, log_w=None):
     c = (tau - 1.0) / tau
     kI, kQ = np.meshgrid(np.arange(Q), np.arange(Q), indexing="ij")
     kI, kQ = kI.reshape(-1), kQ.reshape(-1)                  # point a = kI*Q + kQ
-    out = np.zeros((prob.Nt, Q * Q))
-    for m in range(prob.Nt):
+    out = np.full((prob.Nt, Q * Q), np.nan)
+    for m in (range(prob.Nt) if antennas is None else antennas):
         ks = np.repeat(k_samples[:, None, :], Q * Q, axis=1)  # (S, M, N)
         ks[:, :, 2 * m] = kI[None, :]
         ks[:, :, 2 * m + 1] = kQ[None, :]

@@ -23,7 +23,8 @@ STATUS = {0: "DMALA_OK", -1: "DMALA_ERR_ARG", -2: "DMALA_ERR_UNSUPPORTED", -4: "
 class Params(ctypes.Structure):
     _fields_ = [("n_chains", ctypes.c_int32), ("n_iters", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("precision", ctypes.c_int), ("proposal", ctypes.c_int), ("tau", ctypes.c_double),
-                ("alpha_mult", ctypes.c_double), ("beta_mult", ctypes.c_double), ("gamma_mult", ctypes.c_double)]
+                ("alpha_mult", ctypes.c_double), ("beta_mult", ctypes.c_double), ("gamma_mult", ctypes.c_double),
+                ("tile_config", ctypes.c_int32)]
 
 
 class Outputs(ctypes.Structure):
@@ -71,9 +72,10 @@ def last_error():
 
 
 def make_params(n_chains, n_iters, seed, precision="fp32", proposal="precond", tau=2.0,
-                alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0):
+                alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, tile_config=0):
     return Params(int(n_chains), int(n_iters), int(seed) & ((1 << 64) - 1), PRECISIONS[precision],
-                  PROPOSALS[proposal], float(tau), float(alpha_mult), float(beta_mult), float(gamma_mult))
+                  PROPOSALS[proposal], float(tau), float(alpha_mult), float(beta_mult), float(gamma_mult),
+                  int(tile_config))
 
 
 def workspace_size(n_inst, nt, nr, M, params):
@@ -101,12 +103,13 @@ class Detector:
 
     def __init__(self, n_inst, nt, nr, M, n_chains, n_iters, seed=0, precision="fp32", proposal="precond",
                  tau=2.0, alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, device="cuda",
-                 outputs=("symbols", "marginals", "llrs", "best_energy"), trace=False):
+                 outputs=("symbols", "marginals", "llrs", "best_energy"), trace=False, tile_config=0):
         import torch
         self.torch = torch
         self.n_inst, self.nt, self.nr, self.M = n_inst, nt, nr, M
         self.precision = precision
-        self.params = make_params(n_chains, n_iters, seed, precision, proposal, tau, alpha_mult, beta_mult, gamma_mult)
+        self.params = make_params(n_chains, n_iters, seed, precision, proposal, tau, alpha_mult, beta_mult,
+                                  gamma_mult, tile_config)
         self.ws_bytes = workspace_size(n_inst, nt, nr, M, self.params)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
         nb = int(round(np.log2(M)))
@@ -170,12 +173,12 @@ def detect(Hcm, y, sigma2, M, n_chains, n_iters, seed, **kw):
 
 
 def debug_eval(Hcm, y, sigma2, M, x_from, x_to, precision="fp32", proposal="precond", tau=2.0,
-               alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0):
+               alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, tile_config=0):
     """Transition quantities of the device chain for state pairs (see dmala_debug_eval)."""
     import torch
     n_inst, nt, nr = Hcm.shape
     n_pairs = x_from.shape[1]
-    p = make_params(n_pairs, 0, 0, precision, proposal, tau, alpha_mult, beta_mult, gamma_mult)
+    p = make_params(n_pairs, 0, 0, precision, proposal, tau, alpha_mult, beta_mult, gamma_mult, tile_config)
     ws_bytes = workspace_size(n_inst, nt, nr, M, p)
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=Hcm.device)
     wp = (ws.data_ptr() + 255) // 256 * 256

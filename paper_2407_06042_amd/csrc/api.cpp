@@ -29,7 +29,7 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Plan {
   Shape sh;
-  size_t inst_off, state_off, total;
+  size_t inst_off, state_off, wscratch_off, total;
   double tau, am, bm, gm;
   bool naive;
 };
@@ -49,11 +49,12 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
   else return fail(DMALA_ERR_UNSUPPORTED, "qam_order must be 4, 16, 64 or 256 (got %d)", M);
   if (nr > 4096) return fail(DMALA_ERR_UNSUPPORTED, "nr > 4096 is not supported (got %d)", nr);
   const bool fp64 = p->precision == DMALA_FP64;
-  if (nt > 64) return fail(DMALA_ERR_UNSUPPORTED, "nt > 64 is not supported (got %d)", nt);
+  if (nt > 128) return fail(DMALA_ERR_UNSUPPORTED, "nt > 128 is not supported (got %d)", nt);
   if (fp64 && nt > 32) return fail(DMALA_ERR_UNSUPPORTED, "DMALA_FP64 supports nt <= 32 (got %d)", nt);
   Shape& sh = pl.sh;
   sh.nt = nt; sh.nr = nr; sh.M = M; sh.Q = Q; sh.N = 2 * nt;
-  sh.Npad = 32 * ((sh.N + 31) / 32);
+  sh.Npad = 32;  // the sampler layouts cover 32, 64, 128 or 256 real dimensions
+  while (sh.Npad < sh.N) sh.Npad *= 2;
   sh.RT = sh.Npad / 16; sh.KB = sh.RT / 2;
   sh.C = p->n_chains; sh.Cpad = 16 * ((sh.C + 15) / 16); sh.T = p->n_iters;
   sh.fp64 = fp64 ? 1 : 0;
@@ -74,13 +75,23 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
   } else {
     sh.frag_bytes = (size_t)(p_passes(sh.pm) + kEPasses) * sh.RT * sh.KB * 1024 + 2 * (size_t)sh.Npad * 4;
   }
+  if (p->tile_config < 0 || p->tile_config > 5) return fail(DMALA_ERR_ARG, "tile_config must be in [0, 5]");
+  if (fp64 || p->tile_config == 0) {
+      sh.cfg = fp64 ? 0 : sampler_default_cfg(sh);
+  } else {
+    if (!sampler_cfg_valid(sh, p->tile_config - 1))
+      return fail(DMALA_ERR_UNSUPPORTED, "tile_config %d does not fit this shape", p->tile_config);
+    sh.cfg = p->tile_config - 1;
+  }
   if (sampler_lds_bytes(sh) > 160 * 1024)
     return fail(DMALA_ERR_UNSUPPORTED, "shape needs %zu bytes of LDS (> 160 KiB)", sampler_lds_bytes(sh));
   sh.inst_bytes = round_up(kParamBytes + sh.frag_bytes, 256);
   sh.state_bytes = state_offsets(sh.Cpad, sh.Npad).end;
+  sh.wscratch_bytes = setup_w_global(nt) ? round_up((size_t)nt * (nt + 1) * 16, 256) : 0;
   pl.inst_off = 0;
   pl.state_off = round_up((size_t)n_inst * sh.inst_bytes, 256);
-  pl.total = pl.state_off + (size_t)n_inst * sh.state_bytes;
+  pl.wscratch_off = round_up(pl.state_off + (size_t)n_inst * sh.state_bytes, 256);
+  pl.total = pl.wscratch_off + (size_t)n_inst * sh.wscratch_bytes;
   pl.tau = p->tau > 0 ? p->tau : 2.0;
   pl.am = p->alpha_mult > 0 ? p->alpha_mult : 1.0;
   pl.bm = p->beta_mult > 0 ? p->beta_mult : 1.0;
@@ -115,6 +126,7 @@ dmala_status run(const void* H, const void* y, const void* sigma2, int32_t n_ins
   SetupArgs sa{};
   sa.H = H; sa.y = y; sa.sigma2 = sigma2;
   sa.ws_inst = base + pl.inst_off; sa.inst_stride = sh.inst_bytes;
+  sa.wscratch = base + pl.wscratch_off; sa.wscratch_stride = sh.wscratch_bytes;
   sa.n_inst = n_inst; sa.nt = sh.nt; sa.nr = sh.nr; sa.Q = sh.Q; sa.N = sh.N; sa.Npad = sh.Npad;
   sa.RT = sh.RT; sa.KB = sh.KB; sa.fp64 = sh.fp64; sa.pm = sh.pm; sa.naive = pl.naive ? 1 : 0;
   sa.tau = pl.tau; sa.alpha_mult = pl.am; sa.beta_mult = pl.bm; sa.gamma_mult = pl.gm;

@@ -56,9 +56,11 @@ struct Shape {
   int fp64;        // 1: double path
   int pm;          // PMode (MFMA path)
   int win;         // proposal window half-width (0 = all levels), see the sampler
+  int cfg;         // sampler work layout (see sampler_impl.hpp launch_rt)
   size_t inst_bytes;   // per-instance setup block
   size_t frag_bytes;   // MFMA fragments (MFMA path)
   size_t state_bytes;  // per-instance sampler->estimator block
+  size_t wscratch_bytes;  // per-instance setup working matrix (large nt)
 };
 
 // Offsets inside the per-instance state block.
@@ -78,6 +80,7 @@ __host__ __device__ inline StateOff state_offsets(int Cpad, int Npad) {
 struct SetupArgs {
   const void* H; const void* y; const void* sigma2;
   unsigned char* ws_inst; size_t inst_stride;
+  unsigned char* wscratch; size_t wscratch_stride;  // per-instance working matrix when nt > 64
   int n_inst, nt, nr, Q, N, Npad, RT, KB, fp64, pm, naive;
   double tau, alpha_mult, beta_mult, gamma_mult;
 };
@@ -105,9 +108,12 @@ struct EstArgs {
 
 // Host launchers (defined in the .hip translation units).
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
+bool setup_w_global(int nt);
 hipError_t launch_sampler(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s);
 hipError_t launch_estimate(const EstArgs& a, hipStream_t s);
 size_t sampler_lds_bytes(const Shape& sh);
+bool sampler_cfg_valid(const Shape& sh, int cfg);
+int sampler_default_cfg(const Shape& sh);
 int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64);
 
 // ------------------------------------------------------------------ device helpers

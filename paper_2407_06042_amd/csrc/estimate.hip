@@ -51,6 +51,8 @@ __device__ __forceinline__ int ungray(int g) {
   return g;
 }
 
+constexpr int kLlrPerThread = 4;  // bits per instance <= 128 antennas x 8 bits = 4 x 256 threads
+
 // Per (chain, antenna) values staged in LDS.
 template <typename R>
 struct CM {
@@ -82,8 +84,7 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
   R* fs = rb2 + (size_t)CH * nr;                     // CH
   R* ebs = fs + CH;                                  // CH
   R* a2 = ebs + CH;                                  // nt
-  R* lp = a2 + nt;                                   // nt x M
-  int8_t* Ks = (int8_t*)(lp + (size_t)nt * M);       // CH x N
+  int8_t* Ks = (int8_t*)(a2 + nt);                   // CH x N
   int8_t* Kbs = Ks + (size_t)CH * N;                 // CH x N
   __shared__ R best_e;
   __shared__ int best_c;
@@ -114,17 +115,20 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
     a2[m] = R(4) * s * s * g * inv_s2;
   }
   if (tid == 0) { best_e = R(INFINITY); best_c = 0; }
-  for (int e = tid; e < nt * M; e += nth) ((int*)lp)[e] = 0;
 
   // ownership: marginal rows (m, kI), in blocks of one row per thread, and bits (m, ax, bit)
   const int n_rows = nt * Q, n_llr = nt * 2 * NB;
   const int n_rb = (n_rows + nth - 1) / nth;
   const bool single_chunk = CH >= C;
-  OnlineLse<R> lnum[2], lden[2];
+  const bool want_mc = a.marginals_mc != nullptr;
+  OnlineLse<R> lnum[kLlrPerThread], lden[kLlrPerThread];
 
   for (int rb = 0; rb < n_rb; ++rb) {
     const int row = rb * nth + tid;
     OnlineLse<R> acc[Q];
+    int cnt[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) cnt[j] = 0;
 
     for (int c0 = 0; c0 < C; c0 += CH) {
       const int ch = C - c0 < CH ? C - c0 : CH;
@@ -195,14 +199,6 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
           for (int c = 0; c < ch; ++c)
             if (ebs[c] < best_e) { best_e = ebs[c]; best_c = c0 + c; }
         }
-        if (rb == 0 && a.marginals_mc) {
-          // plain Monte Carlo histogram of the final samples (eq. mc), in LDS
-          int* hist = (int*)lp;
-          for (int it = tid; it < ch * nt; it += nth) {
-            const int c = it / nt, m = it % nt;
-            atomicAdd(&hist[m * M + Ks[c * N + 2 * m] * Q + Ks[c * N + 2 * m + 1]], 1);
-          }
-        }
         __syncthreads();
       }
 
@@ -219,12 +215,16 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
             const R eQ = R(kQt - v.kQ);
             acc[kQt].add(b0 + eQ * (v.aQ - q2 * eQ));
           }
+          if (want_mc) {
+#pragma unroll
+            for (int kQt = 0; kQt < Q; ++kQt) cnt[kQt] += (v.kI == kIt && v.kQ == kQt) ? 1 : 0;
+          }
         }
       }
       // bit LLRs: item (m, ax, bit)
       if (rb == 0) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < kLlrPerThread; ++q) {
           const int it = tid + q * nth;
           if (it < n_llr) {
             const int m = it / (2 * NB), ax = (it / NB) % 2, bit = it % NB;
@@ -246,33 +246,40 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
         }
       }
     }
-    if (rb == 0 && a.marginals_mc) {
-      __syncthreads();
-      const int* hist = (const int*)lp;
-      for (int e = tid; e < nt * M; e += nth) a.marginals_mc[(size_t)b * nt * M + e] = (float)hist[e] / (float)C;
-      __syncthreads();
-    }
-    if (row < n_rows) {
-      const int m = row / Q, kIt = row % Q;
+    // normalise over the M points of antenna m: its Q rows sit in Q consecutive
+    // lanes of one wavefront, so the log-sum-exp is a Q-lane butterfly
+    {
+      R lv[Q];
+      R mx = R(-INFINITY);
 #pragma unroll
-      for (int j = 0; j < Q; ++j) lp[(size_t)m * M + kIt * Q + j] = acc[j].value();
+      for (int j = 0; j < Q; ++j) { lv[j] = acc[j].value(); mx = lv[j] > mx ? lv[j] : mx; }
+#pragma unroll
+      for (int off = 1; off < Q; off <<= 1) { const R o = __shfl_xor(mx, off); mx = o > mx ? o : mx; }
+      R sm = R(0);
+#pragma unroll
+      for (int j = 0; j < Q; ++j) sm += fexp(lv[j] - mx);
+#pragma unroll
+      for (int off = 1; off < Q; off <<= 1) sm += __shfl_xor(sm, off);
+      if (row < n_rows) {
+        const int m = row / Q, kIt = row % Q;
+        const R inv = R(1) / sm;
+        if (a.marginals) {
+#pragma unroll
+          for (int j = 0; j < Q; ++j) a.marginals[((size_t)b * nt + m) * M + kIt * Q + j] = (float)(fexp(lv[j] - mx) * inv);
+        }
+        if (want_mc) {
+#pragma unroll
+          for (int j = 0; j < Q; ++j) a.marginals_mc[((size_t)b * nt + m) * M + kIt * Q + j] = (float)cnt[j] / (float)C;
+        }
+      }
     }
   }
 
   if (a.llrs) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < kLlrPerThread; ++q) {
       const int it = tid + q * nth;
       if (it < n_llr) a.llrs[(size_t)b * n_llr + it] = (float)(lnum[q].value() - lden[q].value());
-    }
-  }
-  __syncthreads();
-  if (a.marginals) {
-    for (int m = tid; m < nt; m += nth) {
-      OnlineLse<R> l;
-      for (int pt = 0; pt < M; ++pt) l.add(lp[(size_t)m * M + pt]);
-      const R z = l.value();
-      for (int pt = 0; pt < M; ++pt) a.marginals[((size_t)b * nt + m) * M + pt] = (float)fexp(lp[(size_t)m * M + pt] - z);
     }
   }
   // hard decision: smallest recomputed energy among the chains' best states
@@ -288,7 +295,7 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
 size_t estimate_lds_bytes(int nt, int nr, int M, int N, int chunk, bool fp64) {
   const size_t R = fp64 ? 8 : 4;
   const size_t cm = fp64 ? 32 : 20;
-  return cm * (size_t)chunk * nt + R * (3 * (size_t)chunk * nr + 2 * (size_t)chunk + nt + (size_t)nt * M) +
+  return cm * (size_t)chunk * nt + R * (3 * (size_t)chunk * nr + 2 * (size_t)chunk + nt) +
          2 * (size_t)chunk * N + 16;
 }
 

@@ -1,7 +1,7 @@
 // Sampler dispatch: picks the compiled instance for a shape (the kernel
 // templates live in sampler_impl.hpp, instantiated per proposal mode in
 // sampler_<mode>.hip so that they compile in parallel).
-#include "common.hpp"
+#include "sampler_impl.hpp"
 
 namespace dmala {
 
@@ -15,9 +15,34 @@ hipError_t launch_sampler_bf16x1(const Shape&, const SamplerArgs&, bool, hipStre
 size_t sampler_lds_bytes(const Shape& sh) {
   if (sh.fp64) {
     const int waves = sh.Cpad / 16 < 4 ? sh.Cpad / 16 : 4;
-    return sh.frag_bytes + (size_t)waves * 16 * sh.Npad * sizeof(double);
+    return sampler_cfg_lds(sh, sh.RT, 1, false, waves);
   }
-  return sh.RT > 4 ? sh.frag_bytes - 2 * (size_t)sh.Npad * 4 : sh.frag_bytes;
+  switch (sh.cfg) {
+    case 0: return sampler_cfg_lds(sh, 2, 1, false, 4);
+    case 1: return sampler_cfg_lds(sh, 4, 1, false, 4);
+    case 2: return sampler_cfg_lds(sh, 8, 1, false, 4);
+    case 3: return sampler_cfg_lds(sh, 4, 2, true, 2);
+    case 4: return sampler_cfg_lds(sh, 4, 4, true, 4);
+  }
+  return ~(size_t)0;
+}
+
+bool sampler_cfg_valid(const Shape& sh, int cfg) {
+  static const int rt_of[5] = {2, 4, 8, 8, 16};
+  if (cfg < 0 || cfg > 4 || rt_of[cfg] != sh.RT) return false;
+  Shape t = sh;
+  t.cfg = cfg;
+  return sampler_lds_bytes(t) <= 160 * 1024;
+}
+
+int sampler_default_cfg(const Shape& sh) {
+  switch (sh.RT) {
+    case 2: return 0;
+    case 4: return 1;
+    case 8: return sampler_cfg_valid(sh, 2) ? 2 : 3;
+    case 16: return 4;
+  }
+  return -1;
 }
 
 hipError_t launch_sampler(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {

@@ -158,11 +158,25 @@ __device__ __forceinline__ R bfly4(R v) {
   return v;
 }
 
-template <typename Real, int RT, int Q, int PM, bool EVAL, int WIN>
+// Cross-wave partial sums (dimension-split chain blocks).
+struct Red {
+  float x, y, z;
+  uint32_t h;
+};
+
+// Template parameters: RTW row tiles of 16 dimensions per wave, WD waves per
+// chain block splitting the dimensions (RT = RTW * WD tiles in all), MG = the
+// packed matrices are read from the instance block in global memory (L2) instead
+// of being staged in LDS.
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN>
 __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
   constexpr bool F64 = std::is_same<Real, double>::value;
-  constexpr int D = 4 * RT;
+  static_assert(!F64 || (WD == 1 && !MG), "the float64 path uses one wave per chain block and LDS matrices");
+  static_assert(WD == 1 || RTW % 2 == 0, "dimension-split waves own whole K blocks");
+  constexpr int RT = RTW * WD;
+  constexpr int D = 4 * RTW;
   constexpr int KB = RT / 2;
+  constexpr int KBW = RTW / 2;
   constexpr int NPP = p_passes(PM);
   constexpr int QM1 = Q - 1;
   constexpr int W = WIN > 0 ? WIN : Q - 1;
@@ -173,17 +187,23 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
   const unsigned char* blk = a.ws_inst + (size_t)inst * a.inst_stride;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int cl = lane & 15, h = lane >> 4;
-  const int chain = (blockIdx.y * nwaves + wave) * 16 + cl;
+  const int wd = WD > 1 ? wave : 0;                       // dimension slice of this wave
+  const int cblock = WD > 1 ? blockIdx.y : blockIdx.y * nwaves + wave;
+  const int chain = cblock * 16 + cl;
   const bool live = chain < a.C;
+  const int rt0 = wd * RTW;                               // first row tile owned
 
   // stage the instance's packed matrices and vectors in LDS
-  {
-    const int total = (!F64 && RT > 4) ? a.frag_bytes - 2 * Npad * 4 : a.frag_bytes;  // bytes staged in LDS
-    for (int o = threadIdx.x * 16; o < total; o += blockDim.x * 16)
-      *(uint4*)(smem + o) = *(const uint4*)(blk + kParamBytes + o);
-  }
+  const size_t mat_bytes = F64 ? 0 : (size_t)(NPP + kEPasses) * RT * KB * 1024;
+  size_t staged = 0;
+  if constexpr (F64) staged = a.frag_bytes;
+  else if constexpr (!MG) staged = (RT <= 4) ? (size_t)a.frag_bytes : mat_bytes;
+  for (size_t o = threadIdx.x * 16; o < staged; o += blockDim.x * 16)
+    *(uint4*)(smem + o) = *(const uint4*)(blk + kParamBytes + o);
   const InstParams ip = *(const InstParams*)blk;
   __syncthreads();
+  unsigned char* xbuf = smem + ((staged + 15) & ~(size_t)15);      // 2 x KB x 1 KiB (WD > 1)
+  Red* rbuf = (Red*)(xbuf + (WD > 1 ? 2 * KB * 1024 : 0));          // 2 x WD x 16
 
   const Real kL = (Real)ip.kL;
   const Real rho = (Real)ip.rho;
@@ -203,16 +223,36 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
     ezv = pbv + Npad;
     lvbuf = (double*)(smem + a.frag_bytes) + (size_t)wave * 16 * Npad;
   } else {
-    // the two per-dimension vectors follow the fragments; with 8 row tiles the
-    // fragments alone can fill the LDS, so the vectors are then read from the
-    // instance block (they stay in the L1/L2 caches)
-    const size_t mat = (size_t)(NPP + kEPasses) * RT * KB * 1024;
-    if constexpr (RT <= 4) pbv = (const Real*)(smem + mat);
-    else pbv = (const Real*)(blk + kParamBytes + mat);
+    // the two per-dimension vectors follow the fragments (in LDS only when small)
+    if (!MG && RT <= 4) pbv = (const Real*)(smem + mat_bytes);
+    else pbv = (const Real*)(blk + kParamBytes + mat_bytes);
     ezv = pbv + Npad;
   }
 
-  auto dim_of = [&](int d) { return 16 * (d >> 2) + 4 * h + (d & 3); };
+  auto dim_of = [&](int d) { return 16 * (rt0 + (d >> 2)) + 4 * h + (d & 3); };
+  int xphase = 0, rphase = 0;
+
+  // Sum of per-lane partials over the chain's 4 lanes and (WD > 1) its WD waves;
+  // every lane of the chain gets bitwise the same totals.
+  auto chain_sum = [&](Red v) {
+    v.x = bfly4(v.x); v.y = bfly4(v.y); v.z = bfly4(v.z);
+    v.h += __shfl_xor(v.h, 16);
+    v.h += __shfl_xor(v.h, 32);
+    if constexpr (WD > 1) {
+      Red* rb = rbuf + (rphase & 1) * WD * 16;
+      ++rphase;
+      if (h == 0) rb[wd * 16 + cl] = v;
+      __syncthreads();
+      Red t = rb[cl];
+#pragma unroll
+      for (int w2 = 1; w2 < WD; ++w2) {
+        const Red u = rb[w2 * 16 + cl];
+        t.x += u.x; t.y += u.y; t.z += u.z; t.h += u.h;
+      }
+      v = t;
+    }
+    return v;
+  };
 
   // [P; EG] x lv(k): accP/accE hold the lane's D outputs.
   auto contract = [&](const int (&k)[D], Real (&accP)[D], Real (&accE)[D]) {
@@ -237,29 +277,50 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
         accE[d] = se;
       }
     } else {
-      const uint32_t fo = opaque_zero() + (uint32_t)lane * 16;
+      // B operand: this wave's K blocks from its own registers
       half8 bh[KB];
       bf16x8 bb[KB];
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
+      for (int kb = 0; kb < KBW; ++kb) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int d = (2 * kb + (j >> 2)) * 4 + (j & 3);
           const int lv = (dim_of(d) < N) ? (2 * k[d] - QM1) : 0;
-          bh[kb][j] = (_Float16)(float)lv;
-          if constexpr (PM == PM_BF16X1) bb[kb][j] = (__bf16)(float)lv;
+          bh[wd * KBW + kb][j] = (_Float16)(float)lv;
+          if constexpr (PM == PM_BF16X1) bb[wd * KBW + kb][j] = (__bf16)(float)lv;
         }
       }
+      if constexpr (WD > 1) {
+        // exchange the K blocks of the other waves through LDS
+        unsigned char* xb = xbuf + (xphase & 1) * KB * 1024;
+        ++xphase;
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
+        for (int kb = 0; kb < KBW; ++kb) *(half8*)(xb + (size_t)(wd * KBW + kb) * 1024 + lane * 16) = bh[wd * KBW + kb];
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+          bh[kb] = *(const half8*)(xb + (size_t)kb * 1024 + lane * 16);
+          if constexpr (PM == PM_BF16X1) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) bb[kb][j] = (__bf16)(float)bh[kb][j];
+          }
+        }
+      }
+      const uint32_t fo = opaque_zero() + (uint32_t)lane * 16;
+      auto frag = [&](int p, int rtg, int kb) -> const unsigned char* {
+        const uint32_t off = fo + (uint32_t)((p * RT + rtg) * KB + kb) * 1024u;
+        if constexpr (MG) return blk + kParamBytes + off;
+        else return smem + off;
+      };
+#pragma unroll
+      for (int rt = 0; rt < RTW; ++rt) {
+        const int rtg = rt0 + rt;
         f32x4 e = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int p = 0; p < kEPasses; ++p)
 #pragma unroll
-          for (int kb = 0; kb < KB; ++kb) {
-            const half8 fa = *(const half8*)(smem + fo + (uint32_t)(((NPP + p) * RT + rt) * KB + kb) * 1024u);
-            e = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa, bh[kb], e, 0, 0, 0);
-          }
+          for (int kb = 0; kb < KB; ++kb)
+            e = __builtin_amdgcn_mfma_f32_16x16x32_f16(*(const half8*)frag(NPP + p, rtg, kb), bh[kb], e, 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < 4; ++i) accE[rt * 4 + i] = e[i];
         if constexpr (PM != PM_NAIVE) {
@@ -268,11 +329,10 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
           for (int p = 0; p < NPP; ++p)
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb) {
-              const unsigned char* src = smem + fo + (uint32_t)((p * RT + rt) * KB + kb) * 1024u;
               if constexpr (PM == PM_BF16X1)
-                q = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*(const bf16x8*)src, bb[kb], q, 0, 0, 0);
+                q = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*(const bf16x8*)frag(p, rtg, kb), bb[kb], q, 0, 0, 0);
               else
-                q = __builtin_amdgcn_mfma_f32_16x16x32_f16(*(const half8*)src, bh[kb], q, 0, 0, 0);
+                q = __builtin_amdgcn_mfma_f32_16x16x32_f16(*(const half8*)frag(p, rtg, kb), bh[kb], q, 0, 0, 0);
             }
 #pragma unroll
           for (int i = 0; i < 4; ++i) accP[rt * 4 + i] = q[i];
@@ -306,6 +366,9 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
 
   int kc[D];
   Real mu[D], lz[D], eg[D];
+  bool valid[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) valid[d] = dim_of(d) < N;
 
   if constexpr (EVAL) {
     // transition quantities for a given pair (x_from -> x_to)
@@ -314,25 +377,30 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int n = dim_of(d);
-      kc[d] = (live && n < N) ? (int)a.x_from[row + n] : 0;
-      kt[d] = (live && n < N) ? (int)a.x_to[row + n] : 0;
+      kc[d] = (live && valid[d]) ? (int)a.x_from[row + n] : 0;
+      kt[d] = (live && valid[d]) ? (int)a.x_to[row + n] : 0;
     }
     proposal_at(kc, mu, lz, eg);
     Real lqf = 0;
 #pragma unroll
     for (int d = 0; d < D; ++d)
-      if (dim_of(d) < N) lqf += lq(kt[d], mu[d], lz[d]);
+      if (valid[d]) lqf += lq(kt[d], mu[d], lz[d]);
     Real mup[D], lzp[D], egp[D];
     proposal_at(kt, mup, lzp, egp);
     Real lqr = 0, T2 = 0;
 #pragma unroll
     for (int d = 0; d < D; ++d)
-      if (dim_of(d) < N) {
+      if (valid[d]) {
         lqr += lq(kc[d], mup[d], lzp[d]);
         T2 -= Real(kt[d] - kc[d]) * (eg[d] + egp[d]);
       }
-    lqf = bfly4(lqf); lqr = bfly4(lqr); T2 = bfly4(T2);
-    if (live && h == 0) {
+    if constexpr (WD > 1) {
+      const Red r = chain_sum(Red{(float)lqf, (float)lqr, (float)T2, 0u});
+      lqf = r.x; lqr = r.y; T2 = r.z;
+    } else {
+      lqf = bfly4(lqf); lqr = bfly4(lqr); T2 = bfly4(T2);
+    }
+    if (live && h == 0 && wd == 0) {
       double* o = a.eval_out + ((size_t)inst * a.C + chain) * 4;
       const double ln2 = 1.0 / kLog2e;
       o[0] = (double)lqf * ln2;
@@ -343,13 +411,10 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
     return;
   } else {
     const uint32_t key0 = a.key0, key1 = a.key1;
-    bool valid[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) valid[d] = dim_of(d) < N;
     // initial state from the t = 0 words
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      uint32_t c[4] = {(uint32_t)(4 * rt + h), 0u, (uint32_t)chain, (uint32_t)inst};
+    for (int rt = 0; rt < RTW; ++rt) {
+      uint32_t c[4] = {(uint32_t)(4 * (rt0 + rt) + h), 0u, (uint32_t)chain, (uint32_t)inst};
       philox4x32_10(c, key0, key1);
 #pragma unroll
       for (int i = 0; i < 4; ++i) kc[rt * 4 + i] = (int)(((uint64_t)(c[i] >> 8) * Q) >> 24);
@@ -362,23 +427,24 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
       const int n = dim_of(d);
       ep += valid[d] ? Real(2 * kc[d] - QM1) * (eg[d] - ezv[n]) : Real(0);
     }
-    ep = bfly4(ep);
+    if constexpr (WD > 1) ep = chain_sum(Red{(float)ep, 0.f, 0.f, 0u}).x;
+    else ep = bfly4(ep);
     const Real eunit = (Real)ip.eunit;
     Real E = (Real)ip.yy + Real(0.5) * eunit * ep;
     Real Ebest = E;
-    uint32_t kbest[RT];
+    uint32_t kbest[RTW];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int rt = 0; rt < RTW; ++rt)
       kbest[rt] = (uint32_t)kc[rt * 4] | ((uint32_t)kc[rt * 4 + 1] << 8) | ((uint32_t)kc[rt * 4 + 2] << 16) | ((uint32_t)kc[rt * 4 + 3] << 24);
     int nacc = 0;
     uint32_t abits = 0;
     const size_t trow = (size_t)inst * a.C + (live ? chain : 0);
 
     for (int t = 1; t <= a.T; ++t) {
-      uint32_t w[RT][4];
+      uint32_t w[RTW][4];
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        w[rt][0] = (uint32_t)(4 * rt + h); w[rt][1] = (uint32_t)t; w[rt][2] = (uint32_t)chain; w[rt][3] = (uint32_t)inst;
+      for (int rt = 0; rt < RTW; ++rt) {
+        w[rt][0] = (uint32_t)(4 * (rt0 + rt) + h); w[rt][1] = (uint32_t)t; w[rt][2] = (uint32_t)chain; w[rt][3] = (uint32_t)inst;
         philox4x32_10(w[rt], key0, key1);
       }
       // 1. draw x' (padding dimensions never move) and -log q(x'|x)
@@ -405,16 +471,22 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
         T2 -= Real(kp[d] - kc[d]) * (eg[d] + egp[d]);
       }
       S += T2;
-      // 4. MH: accept iff  log ratio > log u  (eq. acc_prob: A > u); lanes h = 0 hold the MH word
+      // 4. MH: accept iff  log ratio > log u  (eq. acc_prob: A > u); the MH word
+      // is held by the lanes that own dimensions 0..3 (h = 0 of the first slice)
       {
         const uint32_t um = low_bytes24(w[0][0], w[0][1], w[0][2]);
         Real lu;
         if constexpr (F64) lu = lg2((double)um * 5.9604644775390625e-08);
         else lu = lg2((float)um * 5.9604644775390625e-08f);
-        S -= (h == 0) ? lu : Real(0);
+        S -= (h == 0 && wd == 0) ? lu : Real(0);
       }
-      S = bfly4(S);
-      T2 = bfly4(T2);
+      if constexpr (WD > 1) {
+        const Red r = chain_sum(Red{(float)S, (float)T2, 0.f, 0u});
+        S = r.x; T2 = r.y;
+      } else {
+        S = bfly4(S);
+        T2 = bfly4(T2);
+      }
       const bool acc = S > Real(0);
       // 5. select
 #pragma unroll
@@ -429,12 +501,12 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
       if (E < Ebest) {
         Ebest = E;
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
+        for (int rt = 0; rt < RTW; ++rt)
           kbest[rt] = (uint32_t)kc[rt * 4] | ((uint32_t)kc[rt * 4 + 1] << 8) | ((uint32_t)kc[rt * 4 + 2] << 16) | ((uint32_t)kc[rt * 4 + 3] << 24);
       }
       if (a.trace_accept) {
         abits |= (acc ? 1u : 0u) << ((t - 1) & 31);
-        if (((t & 31) == 0 || t == a.T) && live && h == 0) {
+        if (((t & 31) == 0 || t == a.T) && live && h == 0 && wd == 0) {
           a.trace_accept[trow * a.trace_words + ((t - 1) >> 5)] = abits;
         }
         if ((t & 31) == 0) abits = 0;
@@ -443,9 +515,13 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
         uint32_t hs = 0;
 #pragma unroll
         for (int d = 0; d < D; ++d) hs += valid[d] ? (uint32_t)(kc[d] + 1) * hash_mult(dim_of(d)) : 0u;
-        hs += __shfl_xor(hs, 16);
-        hs += __shfl_xor(hs, 32);
-        if (live && h == 0) a.trace_hash[trow * a.T + (t - 1)] = hs;
+        if constexpr (WD > 1) {
+          hs = chain_sum(Red{0.f, 0.f, 0.f, hs}).h;
+        } else {
+          hs += __shfl_xor(hs, 16);
+          hs += __shfl_xor(hs, 32);
+        }
+        if (live && h == 0 && wd == 0) a.trace_hash[trow * a.T + (t - 1)] = hs;
       }
     }
 
@@ -454,8 +530,8 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
       const StateOff so = state_offsets(a.Cpad, Npad);
       unsigned char* st = a.ws_state + (size_t)inst * a.state_stride;
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        const int n0 = 16 * rt + 4 * h;
+      for (int rt = 0; rt < RTW; ++rt) {
+        const int n0 = 16 * (rt0 + rt) + 4 * h;
         const uint32_t cur = (uint32_t)kc[rt * 4] | ((uint32_t)kc[rt * 4 + 1] << 8) | ((uint32_t)kc[rt * 4 + 2] << 16) | ((uint32_t)kc[rt * 4 + 3] << 24);
         *(uint32_t*)(st + so.k + (size_t)chain * Npad + n0) = cur;
         *(uint32_t*)(st + so.kbest + (size_t)chain * Npad + n0) = kbest[rt];
@@ -465,7 +541,7 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
             if (n0 + i < N) a.final_state[((size_t)inst * a.C + chain) * N + n0 + i] = (int8_t)kc[rt * 4 + i];
         }
       }
-      if (h == 0) {
+      if (h == 0 && wd == 0) {
         ((double*)(st + so.ebest))[chain] = (double)Ebest;
         ((int32_t*)(st + so.nacc))[chain] = nacc;
         if (a.accept_count) a.accept_count[(size_t)inst * a.C + chain] = nacc;
@@ -474,13 +550,26 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
   }
 }
 
-template <typename Real, int RT, int Q, int PM, int WIN>
+// LDS bytes of a configuration.
+inline size_t sampler_cfg_lds(const Shape& sh, int rtw, int wd, bool mg, int waves) {
+  if (sh.fp64) return sh.frag_bytes + (size_t)waves * 16 * sh.Npad * sizeof(double);
+  const int RT = rtw * wd, KB = RT / 2;
+  const size_t mat = (size_t)(p_passes(sh.pm) + kEPasses) * RT * KB * 1024;
+  size_t staged = mg ? 0 : (RT <= 4 ? sh.frag_bytes : mat);
+  staged = (staged + 15) & ~(size_t)15;
+  if (wd > 1) staged += 2 * (size_t)KB * 1024 + 2 * (size_t)wd * 16 * sizeof(Red);
+  return staged;
+}
+
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, int WIN>
 hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
   const int chain_blocks = sh.Cpad / 16;
-  const int waves = chain_blocks < 4 ? chain_blocks : 4;
-  const dim3 grid(a.n_inst, (chain_blocks + waves - 1) / waves);
-  const size_t lds = sampler_lds_bytes(sh);
-  auto k = eval ? sampler_kernel<Real, RT, Q, PM, true, WIN> : sampler_kernel<Real, RT, Q, PM, false, WIN>;
+  int waves, gy;
+  if (WD > 1) { waves = WD; gy = chain_blocks; }
+  else { waves = chain_blocks < 4 ? chain_blocks : 4; gy = (chain_blocks + waves - 1) / waves; }
+  const dim3 grid(a.n_inst, gy);
+  const size_t lds = sampler_cfg_lds(sh, RTW, WD, MG, waves);
+  auto k = eval ? sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN> : sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -489,27 +578,40 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
   return hipGetLastError();
 }
 
-template <typename Real, int RT, int PM>
+template <typename Real, int RTW, int WD, bool MG, int PM>
 hipError_t launch_q(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
   // the 3-level window is used only for Q >= 8 (it would not be smaller otherwise)
   const bool win = !std::is_same<Real, double>::value && sh.win == 3;
   switch (sh.Q) {
-    case 2: return launch_t<Real, RT, 2, PM, 0>(sh, a, eval, s);
-    case 4: return launch_t<Real, RT, 4, PM, 0>(sh, a, eval, s);
-    case 8: return win ? launch_t<Real, RT, 8, PM, 3>(sh, a, eval, s) : launch_t<Real, RT, 8, PM, 0>(sh, a, eval, s);
-    case 16: return win ? launch_t<Real, RT, 16, PM, 3>(sh, a, eval, s) : launch_t<Real, RT, 16, PM, 0>(sh, a, eval, s);
+    case 2: return launch_t<Real, RTW, WD, MG, 2, PM, 0>(sh, a, eval, s);
+    case 4: return launch_t<Real, RTW, WD, MG, 4, PM, 0>(sh, a, eval, s);
+    case 8: return win ? launch_t<Real, RTW, WD, MG, 8, PM, 3>(sh, a, eval, s) : launch_t<Real, RTW, WD, MG, 8, PM, 0>(sh, a, eval, s);
+    case 16: return win ? launch_t<Real, RTW, WD, MG, 16, PM, 3>(sh, a, eval, s) : launch_t<Real, RTW, WD, MG, 16, PM, 0>(sh, a, eval, s);
   }
   return hipErrorInvalidValue;
 }
 
+// Configurations (row tiles per wave, waves per chain block, matrices in L2):
+//   cfg 0: RT 2, 1 wave, LDS     cfg 1: RT 4, 1 wave, LDS     cfg 2: RT 8, 1 wave, LDS
+//   cfg 3: RT 8 as 2 waves x 4, L2     cfg 4: RT 16 as 4 waves x 4, L2
 template <typename Real, int PM>
 hipError_t launch_rt(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
-  switch (sh.RT) {
-    case 2: return launch_q<Real, 2, PM>(sh, a, eval, s);
-    case 4: return launch_q<Real, 4, PM>(sh, a, eval, s);
-    case 8: return launch_q<Real, 8, PM>(sh, a, eval, s);
+  if constexpr (std::is_same<Real, double>::value) {
+    switch (sh.RT) {
+      case 2: return launch_q<Real, 2, 1, false, PM>(sh, a, eval, s);
+      case 4: return launch_q<Real, 4, 1, false, PM>(sh, a, eval, s);
+    }
+    return hipErrorInvalidValue;
+  } else {
+    switch (sh.cfg) {
+      case 0: return launch_q<Real, 2, 1, false, PM>(sh, a, eval, s);
+      case 1: return launch_q<Real, 4, 1, false, PM>(sh, a, eval, s);
+      case 2: return launch_q<Real, 8, 1, false, PM>(sh, a, eval, s);
+      case 3: return launch_q<Real, 4, 2, true, PM>(sh, a, eval, s);
+      case 4: return launch_q<Real, 4, 4, true, PM>(sh, a, eval, s);
+    }
+    return hipErrorInvalidValue;
   }
-  return hipErrorInvalidValue;
 }
 
 }  // namespace dmala

@@ -104,7 +104,7 @@ __device__ void pack_dense(const cd* X, int ld, double c, int N, int Npad, doubl
   }
 }
 
-template <typename TIn>
+template <typename TIn, bool WGLOB>
 __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   const int b = blockIdx.x, tid = threadIdx.x, nt = a.nt, nr = a.nr, N = a.N, Npad = a.Npad;
   const int ld = nt + 1;  // padded leading dimension of the LDS matrices (no bank conflicts on columns)
@@ -112,8 +112,16 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   const TIn* y = (const TIn*)a.y + 2 * (size_t)b * nr;
   const double sigma2 = (double)((const TIn*)a.sigma2)[b];
   extern __shared__ double smem_setup[];
-  cd* W = (cd*)smem_setup;             // nt x ld
-  cd* z = W + nt * ld;
+  // nt x ld working matrix: in LDS, or (large nt) in this instance's slice of the workspace
+  cd* W;
+  cd* z;
+  if constexpr (WGLOB) {
+    W = (cd*)(a.wscratch + (size_t)b * a.wscratch_stride);
+    z = (cd*)smem_setup;
+  } else {
+    W = (cd*)smem_setup;
+    z = W + nt * ld;
+  }
   cd* bv = z + nt;
   cd* rowp = bv + nt;
   cd* colp = rowp + nt;
@@ -132,49 +140,51 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   // its (m, m2) entries (and entries of z) in registers across the chunks.
   double nonfinite = 0.0;
   {
-    constexpr int kIC = 32, kEPT = 17;  // (64*64 + 64) / 256 entries per thread at most
+    constexpr int kIC = 32, kEPT = 17;  // entries per thread per group
     typedef cd tc;
     tc* Ht = (tc*)(red + 256);          // kIC x (nt + 1)
     tc* yc = Ht + kIC * ld;              // kIC
     const int total = nt * nt + nt;
-    double are[kEPT], aim[kEPT];
+    for (int e0 = 0; e0 < total; e0 += kEPT * (int)blockDim.x) {  // groups of entries held in registers
+      double are[kEPT], aim[kEPT];
 #pragma unroll
-    for (int q = 0; q < kEPT; ++q) { are[q] = 0.0; aim[q] = 0.0; }
-    for (int i0 = 0; i0 < nr; i0 += kIC) {
-      const int ic = nr - i0 < kIC ? nr - i0 : kIC;
-      for (int e = tid; e < ic * nt; e += blockDim.x) {
-        const int m = e / ic, ii = e % ic;
-        Ht[ii * ld + m] = {(double)Hg[2 * ((size_t)m * nr + i0 + ii)], (double)Hg[2 * ((size_t)m * nr + i0 + ii) + 1]};
+      for (int q = 0; q < kEPT; ++q) { are[q] = 0.0; aim[q] = 0.0; }
+      for (int i0 = 0; i0 < nr; i0 += kIC) {
+        const int ic = nr - i0 < kIC ? nr - i0 : kIC;
+        for (int e = tid; e < ic * nt; e += blockDim.x) {
+          const int m = e / ic, ii = e % ic;
+          Ht[ii * ld + m] = {(double)Hg[2 * ((size_t)m * nr + i0 + ii)], (double)Hg[2 * ((size_t)m * nr + i0 + ii) + 1]};
+        }
+        for (int ii = tid; ii < ic; ii += blockDim.x) yc[ii] = {(double)y[2 * (i0 + ii)], (double)y[2 * (i0 + ii) + 1]};
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kEPT; ++q) {
+          const int e = e0 + tid + q * (int)blockDim.x;
+          if (e < total) {
+            const bool isz = e >= nt * nt;
+            const int m = isz ? e - nt * nt : e / nt, m2 = isz ? 0 : e % nt;
+            double re = are[q], im = aim[q];
+            for (int ii = 0; ii < ic; ++ii) {
+              const tc hv = Ht[ii * ld + m];
+              const tc bvv = isz ? yc[ii] : Ht[ii * ld + m2];
+              const double ar = hv.re, ai = hv.im, br = bvv.re, bi = bvv.im;
+              re += ar * br + ai * bi;
+              im += ar * bi - ai * br;
+            }
+            are[q] = re;
+            aim[q] = im;
+          }
+        }
+        __syncthreads();
       }
-      for (int ii = tid; ii < ic; ii += blockDim.x) yc[ii] = {(double)y[2 * (i0 + ii)], (double)y[2 * (i0 + ii) + 1]};
-      __syncthreads();
 #pragma unroll
       for (int q = 0; q < kEPT; ++q) {
-        const int e = tid + q * (int)blockDim.x;
+        const int e = e0 + tid + q * (int)blockDim.x;
         if (e < total) {
-          const bool isz = e >= nt * nt;
-          const int m = isz ? e - nt * nt : e / nt, m2 = isz ? 0 : e % nt;
-          double re = are[q], im = aim[q];
-          for (int ii = 0; ii < ic; ++ii) {
-            const tc hv = Ht[ii * ld + m];
-            const tc bvv = isz ? yc[ii] : Ht[ii * ld + m2];
-            const double ar = hv.re, ai = hv.im, br = bvv.re, bi = bvv.im;
-            re += ar * br + ai * bi;
-            im += ar * bi - ai * br;
-          }
-          are[q] = re;
-          aim[q] = im;
+          if (e >= nt * nt) z[e - nt * nt] = {are[q], aim[q]};
+          else W[(e / nt) * ld + e % nt] = {are[q], aim[q]};
+          if (!isfinite(are[q]) || !isfinite(aim[q])) nonfinite = 1.0;
         }
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < kEPT; ++q) {
-      const int e = tid + q * (int)blockDim.x;
-      if (e < total) {
-        if (e >= nt * nt) z[e - nt * nt] = {are[q], aim[q]};
-        else W[(e / nt) * ld + e % nt] = {are[q], aim[q]};
-        if (!isfinite(are[q]) || !isfinite(aim[q])) nonfinite = 1.0;
       }
     }
   }
@@ -291,10 +301,14 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   }
 }
 
+bool setup_w_global(int nt) { return nt > 64; }
+
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)(a.nt * (a.nt + 1) + 4 * a.nt) * sizeof(cd) + 256 * sizeof(double) +
+  const bool wg = setup_w_global(a.nt);
+  const size_t lds = (size_t)((wg ? 0 : a.nt * (a.nt + 1)) + 4 * a.nt) * sizeof(cd) + 256 * sizeof(double) +
                      (32 * (size_t)(a.nt + 1) + 32) * sizeof(cd);
-  auto k = a.fp64 ? setup_kernel<double> : setup_kernel<float>;
+  auto k = a.fp64 ? (wg ? setup_kernel<double, true> : setup_kernel<double, false>)
+                  : (wg ? setup_kernel<float, true> : setup_kernel<float, false>);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

@@ -29,7 +29,7 @@ def test_workspace_size_validation():
     p = dm.make_params(32, 100, 1)
     assert dm.workspace_size(8, 32, 32, 64, p) > 8 * 32 * 1024
     for args, msg in [((8, 32, 32, 8), "qam_order"), ((0, 32, 32, 64), "n_inst"), ((8, 0, 4, 16), "nt"),
-                      ((8, 65, 65, 16), "nt > 64"), ((8, 4, 5000, 16), "nr")]:
+                      ((8, 129, 129, 16), "nt > 128"), ((8, 4, 5000, 16), "nr")]:
         with pytest.raises(dm.DmalaError) as e:
             dm.workspace_size(*args, p)
         assert msg in str(e.value)
@@ -37,6 +37,13 @@ def test_workspace_size_validation():
         dm.workspace_size(8, 4, 4, 16, dm.make_params(0, 10, 1))
     with pytest.raises(dm.DmalaError):
         dm.workspace_size(8, 40, 40, 16, dm.make_params(16, 10, 1, precision="fp64"))
+    # every automatic layout exists for 1..128 antennas
+    for nt in (1, 3, 16, 17, 33, 48, 64, 65, 100, 128):
+        assert dm.workspace_size(2, nt, nt, 16, p) > 0
+    # explicit layouts: valid only for their dimension count
+    assert dm.workspace_size(2, 64, 64, 64, dm.make_params(16, 10, 1, tile_config=4)) > 0
+    with pytest.raises(dm.DmalaError):
+        dm.workspace_size(2, 32, 32, 64, dm.make_params(16, 10, 1, tile_config=4))
 
 
 def test_detect_rejects_bad_workspace_before_launch():

@@ -164,3 +164,51 @@ def test_device_kernel_detailed_balance(precision, nt, M):
     fo = prob.f(prob.x_of(K)) / prob.tau
     ftol = 1e-9 if precision == "fp64" else 1e-4
     np.testing.assert_allclose(DF, fo[None, :] - fo[:, None], atol=ftol * max(1.0, np.abs(fo).max()))
+
+
+@pytest.mark.parametrize("nt,M,rho,snr,C,T,tile", [
+    (48, 64, 0.0, 20.0, 32, 30, 0),      # 96 dims padded to 128, automatic layout
+    (64, 64, 0.0, 22.0, 32, 30, 3),      # one wave per 16 chains, matrices in LDS
+    (64, 64, 0.0, 22.0, 32, 30, 4),      # two waves per 16 chains, matrices from L2
+    (128, 256, 0.5, 30.0, 32, 20, 0),    # Kronecker-correlated 128x128 256-QAM, four waves per 16 chains
+])
+def test_large_shapes_fp32(nt, M, rho, snr, C, T, tile):
+    """Chain identity on the large layouts; estimators on a few antennas (oracle one by one)."""
+    batch = W.make_batch(nt, nt, M, snr, 2, seed=nt + M, rho=rho)
+    b, g = run_gpu(batch, C, T, 4242 + tile, "fp32", tile_config=tile)
+    for i in range(2):
+        o = run_oracle(b, i, C, T, 4242 + tile, estimators=False)
+        n_id, n_fd, bad = compare_chains(g["trace_hash"][i], o, *EPS32)
+        _print("large", nt=nt, M=M, tile=tile, inst=i, identical=n_id, flagged=n_fd, bad=bad[:3])
+        assert not bad
+        assert n_id >= C // 2
+        prob = odm.Problem(b.H[i], b.y[i], b.sigma2[i], M)
+        k = g["final_state"][i].astype(np.int64)
+        ants = [0, nt // 2, nt - 1]
+        m_or = odm.marginals_is(prob, k, antennas=ants)
+        l_or = odm.llr_is(prob, k, antennas=ants)
+        np.testing.assert_allclose(g["marginals"][i][ants], m_or[ants], atol=1e-3)
+        np.testing.assert_allclose(g["llrs"][i][ants], l_or[ants], atol=5e-3 * np.maximum(1.0, np.abs(l_or[ants])).max())
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+@pytest.mark.parametrize("nt,M", [(32, 64), (64, 64), (128, 256)])
+def test_reduced_precision_kernel_is_reversible(precision, nt, M):
+    """Reduced-precision proposals keep the exact target: device log-ratios are antisymmetric
+    and the energy term matches the float64 metric on random state pairs."""
+    import torch
+    import paper_2407_06042_amd as dm
+    b = W.make_batch(nt, nt, M, 25.0, 1, seed=nt).as_precision(np.float32)
+    prob = odm.Problem(b.H[0], b.y[0], b.sigma2[0], M)
+    rng = np.random.default_rng(nt)
+    P = 256
+    xf = rng.integers(0, prob.Q, size=(1, P, prob.N))
+    xt = np.where(rng.random((1, P, prob.N)) < 0.1, rng.integers(0, prob.Q, size=(1, P, prob.N)), xf)
+    Hcm, y, s2 = dm.device_inputs(b.H, b.y, b.sigma2, precision)
+    fwd = dm.debug_eval(Hcm, y, s2, M, torch.from_numpy(xf).cuda(), torch.from_numpy(xt).cuda(), precision=precision).cpu().numpy()[0]
+    rev = dm.debug_eval(Hcm, y, s2, M, torch.from_numpy(xt).cuda(), torch.from_numpy(xf).cuda(), precision=precision).cpu().numpy()[0]
+    # log q(x'|x) forward == log q(x'|x) seen as the reverse term of the swapped pair
+    np.testing.assert_allclose(fwd[:, 0], rev[:, 1], rtol=1e-6, atol=1e-5)
+    np.testing.assert_allclose(fwd[:, 3], -rev[:, 3], rtol=1e-5, atol=1e-4)
+    fo = prob.f(prob.x_of(xt[0])) / prob.tau - prob.f(prob.x_of(xf[0])) / prob.tau
+    np.testing.assert_allclose(fwd[:, 2], fo, atol=2e-4 * max(1.0, np.abs(fo).max()))
