@@ -82,8 +82,10 @@ typedef struct {
                                 2: 128 dims, 1 wave / 16 chains, LDS
                                 3: 128 dims, 2 waves / 16 chains, matrices read from L2
                                 4: 256 dims, 4 waves / 16 chains, L2
-                                (dims = 2 Nt rounded up to 32; a layout that does not match the
-                                shape returns DMALA_ERR_UNSUPPORTED) */
+                                (dims = 2 Nt rounded up to a power of two >= 32; a layout that does
+                                not match the shape returns DMALA_ERR_UNSUPPORTED) */
+  int32_t wg_chain_blocks;   /* layouts 0-2: 16-chain blocks sharing one workgroup (and one LDS copy
+                                of the matrices): 0 = automatic (up to 4), or 1, 2, 4 */
 } dmala_params;
 
 /* Device output buffers; any pointer may be NULL to skip that output. */
@@ -132,6 +134,51 @@ dmala_status dmala_debug_eval(const void* H, const void* y, const void* sigma2,
                               const dmala_params* params, const int8_t* x_from, const int8_t* x_to,
                               int32_t n_pairs, double* out, void* workspace, size_t workspace_bytes,
                               dmala_stream_t stream);
+
+/* ---- Uneven batches: instances of different Nt, Nr, M in one graph launch ----
+ * A plan groups the instances of a batch by shape class (Nt, Nr, M), orders the
+ * classes by decreasing work (longest processing time first) and runs them all
+ * as one HIP graph: per class a setup, a sampler and an estimator kernel, the
+ * classes on parallel branches.  Buffers are packed in instance order:
+ *   H of instance b at complex offset sum_{j<b} Nt_j Nr_j (column-major per instance),
+ *   y at sum_{j<b} Nr_j, sigma2[b]; symbols at sum Nt_j; marginals and marginals_mc at
+ *   sum Nt_j M_j; llrs at sum Nt_j log2 M_j; best_energy[b]; final_state at
+ *   sum n_chains 2 Nt_j; accept_count at b * n_chains.  Trace outputs are not
+ *   supported by plans (NULL required).
+ * The per-instance random counters use the instance index b, so a plan and a
+ * dmala_detect call over the same instances give identical chains.
+ * The plan owns a small device table (hipMalloc at creation, freed by
+ * dmala_plan_destroy) and its graph; the graph is rebuilt when execute is called
+ * with different buffers.  Params: as for dmala_detect (tile_config 0 lets each
+ * class use its tuned or default layout). */
+typedef struct dmala_plan_s* dmala_plan;
+typedef struct { int32_t nt, nr, qam_order; } dmala_shape;
+
+/* shapes: host array [n_inst].  On success *plan is set and *workspace_bytes
+ * receives the device workspace the plan needs. */
+dmala_status dmala_plan_create(dmala_plan* plan, const dmala_shape* shapes, int32_t n_inst,
+                               const dmala_params* params, size_t* workspace_bytes);
+
+/* Run every instance of the plan (enqueued on `stream` as one graph launch). */
+dmala_status dmala_plan_execute(dmala_plan plan, const void* H, const void* y, const void* sigma2,
+                                const dmala_outputs* out, void* workspace, size_t workspace_bytes,
+                                dmala_stream_t stream);
+
+/* Time every admissible (layout, workgroup chain blocks) candidate of every
+ * class on the given inputs and keep the fastest per class; when cache_path is
+ * non-NULL, read earlier results from it first (classes already present are not
+ * re-timed) and write the updated table back (JSON).  Synchronises `stream`. */
+dmala_status dmala_plan_autotune(dmala_plan plan, const void* H, const void* y, const void* sigma2,
+                                 void* workspace, size_t workspace_bytes, const char* cache_path,
+                                 dmala_stream_t stream);
+
+/* Number of shape classes; per class: its shape, instance count, chosen layout
+ * (tile_config value, >= 1), chain blocks per workgroup and tuned time (ms, 0 if untuned). */
+int32_t dmala_plan_num_classes(dmala_plan plan);
+dmala_status dmala_plan_class_info(dmala_plan plan, int32_t k, dmala_shape* shape, int32_t* n_inst,
+                                   int32_t* tile_config, int32_t* wg_chain_blocks, double* tuned_ms);
+
+void dmala_plan_destroy(dmala_plan plan);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* dmala_last_error(void);

@@ -24,7 +24,11 @@ class Params(ctypes.Structure):
     _fields_ = [("n_chains", ctypes.c_int32), ("n_iters", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("precision", ctypes.c_int), ("proposal", ctypes.c_int), ("tau", ctypes.c_double),
                 ("alpha_mult", ctypes.c_double), ("beta_mult", ctypes.c_double), ("gamma_mult", ctypes.c_double),
-                ("tile_config", ctypes.c_int32)]
+                ("tile_config", ctypes.c_int32), ("wg_chain_blocks", ctypes.c_int32)]
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("nt", ctypes.c_int32), ("nr", ctypes.c_int32), ("qam_order", ctypes.c_int32)]
 
 
 class Outputs(ctypes.Structure):
@@ -58,13 +62,29 @@ def lib():
                                    ctypes.POINTER(Outputs), vp, sz, vp]
         L.dmala_debug_eval.restype = ctypes.c_int
         L.dmala_debug_eval.argtypes = [vp, vp, vp, i32, i32, i32, i32, ctypes.POINTER(Params), vp, vp, i32, vp, vp, sz, vp]
+        L.dmala_plan_create.restype = ctypes.c_int
+        L.dmala_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Shape), i32, ctypes.POINTER(Params),
+                                        ctypes.POINTER(sz)]
+        L.dmala_plan_execute.restype = ctypes.c_int
+        L.dmala_plan_execute.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Outputs), vp, sz, vp]
+        L.dmala_plan_autotune.restype = ctypes.c_int
+        L.dmala_plan_autotune.argtypes = [vp, vp, vp, vp, vp, sz, ctypes.c_char_p, vp]
+        L.dmala_plan_num_classes.restype = i32
+        L.dmala_plan_num_classes.argtypes = [vp]
+        L.dmala_plan_class_info.restype = ctypes.c_int
+        L.dmala_plan_class_info.argtypes = [vp, i32, ctypes.POINTER(Shape), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                            ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+        L.dmala_plan_destroy.restype = None
+        L.dmala_plan_destroy.argtypes = [vp]
         L.dmala_last_error.restype = ctypes.c_char_p
         L.dmala_version.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
 
-EXPORTED = ["dmala_workspace_size", "dmala_detect", "dmala_debug_eval", "dmala_last_error", "dmala_version"]
+EXPORTED = ["dmala_workspace_size", "dmala_detect", "dmala_debug_eval", "dmala_plan_create", "dmala_plan_execute",
+            "dmala_plan_autotune", "dmala_plan_num_classes", "dmala_plan_class_info", "dmala_plan_destroy",
+            "dmala_last_error", "dmala_version"]
 
 
 def last_error():
@@ -75,7 +95,7 @@ def make_params(n_chains, n_iters, seed, precision="fp32", proposal="precond", t
                 alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, tile_config=0):
     return Params(int(n_chains), int(n_iters), int(seed) & ((1 << 64) - 1), PRECISIONS[precision],
                   PROPOSALS[proposal], float(tau), float(alpha_mult), float(beta_mult), float(gamma_mult),
-                  int(tile_config))
+                  int(tile_config), 0)
 
 
 def workspace_size(n_inst, nt, nr, M, params):
@@ -191,3 +211,84 @@ def debug_eval(Hcm, y, sigma2, M, x_from, x_to, precision="fp32", proposal="prec
     if st != 0:
         raise DmalaError(st, last_error())
     return out
+
+
+def pack_uneven(H_list, y_list, sigma2, precision="fp32", device="cuda"):
+    """Pack per-instance host arrays (H_b: (Nr_b, Nt_b), y_b: (Nr_b,)) into the plan layout."""
+    import torch
+    ct, rt = (np.complex128, np.float64) if precision == "fp64" else (np.complex64, np.float32)
+    Hp = np.concatenate([np.asarray(H).T.reshape(-1) for H in H_list]).astype(ct)   # column-major per instance
+    yp = np.concatenate([np.asarray(y).reshape(-1) for y in y_list]).astype(ct)
+    return (torch.from_numpy(Hp).to(device), torch.from_numpy(yp).to(device),
+            torch.from_numpy(np.asarray(sigma2).astype(rt)).to(device))
+
+
+class Plan:
+    """Uneven batch (instances of different Nt, Nr, M) run as one graph launch."""
+
+    def __init__(self, shapes, n_chains, n_iters, seed=0, precision="fp32", proposal="precond", tau=2.0,
+                 device="cuda", outputs=("symbols", "marginals", "llrs", "best_energy", "final_state", "accept_count")):
+        import torch
+        self.torch = torch
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        n = len(self.shapes)
+        arr = (Shape * n)(*[Shape(*s) for s in self.shapes])
+        self.params = make_params(n_chains, n_iters, seed, precision, proposal, tau)
+        self.precision = precision
+        h = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        st = lib().dmala_plan_create(ctypes.byref(h), arr, n, ctypes.byref(self.params), ctypes.byref(ws))
+        if st != 0:
+            raise DmalaError(st, last_error())
+        self.handle = h
+        self.ws_bytes = ws.value
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        nt_sum = sum(s[0] for s in self.shapes)
+        marg = sum(s[0] * s[2] for s in self.shapes)
+        llr = sum(s[0] * int(round(np.log2(s[2]))) for s in self.shapes)
+        sizes = dict(symbols=(nt_sum, torch.int32), marginals=(marg, torch.float32), llrs=(llr, torch.float32),
+                     best_energy=(n, torch.float32), final_state=(n_chains * 2 * nt_sum, torch.int8),
+                     accept_count=(n * n_chains, torch.int32), marginals_mc=(marg, torch.float32))
+        self.out = {k: torch.empty(sizes[k][0], dtype=sizes[k][1], device=device) for k in outputs}
+        o = Outputs()
+        for name, _ in Outputs._fields_[:-1]:
+            setattr(o, name, self.out[name].data_ptr() if name in self.out else None)
+        self._outs = o
+
+    def _ws_ptr(self):
+        return (self.ws.data_ptr() + 255) // 256 * 256
+
+    def __call__(self, H, y, sigma2, events=None):
+        s = self.torch.cuda.current_stream().cuda_stream
+        for i in range(4):
+            self._outs.stage_events[i] = events[i] if events is not None else None
+        st = lib().dmala_plan_execute(self.handle, H.data_ptr(), y.data_ptr(), sigma2.data_ptr(), ctypes.byref(self._outs),
+                                      self._ws_ptr(), self.ws_bytes, s)
+        if st != 0:
+            raise DmalaError(st, last_error())
+        return self.out
+
+    def autotune(self, H, y, sigma2, cache_path=None):
+        s = self.torch.cuda.current_stream().cuda_stream
+        st = lib().dmala_plan_autotune(self.handle, H.data_ptr(), y.data_ptr(), sigma2.data_ptr(), self._ws_ptr(),
+                                       self.ws_bytes, cache_path.encode() if cache_path else None, s)
+        if st != 0:
+            raise DmalaError(st, last_error())
+
+    def classes(self):
+        out = []
+        for k in range(lib().dmala_plan_num_classes(self.handle)):
+            sh, n, tc, cb, ms = Shape(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+            st = lib().dmala_plan_class_info(self.handle, k, ctypes.byref(sh), ctypes.byref(n), ctypes.byref(tc),
+                                             ctypes.byref(cb), ctypes.byref(ms))
+            if st != 0:
+                raise DmalaError(st, last_error())
+            out.append(dict(nt=sh.nt, nr=sh.nr, M=sh.qam_order, count=n.value, tile_config=tc.value,
+                            wg_chain_blocks=cb.value, tuned_ms=ms.value))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.dmala_plan_destroy(h)
+            self.handle = None

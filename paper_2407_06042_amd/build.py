@@ -24,7 +24,7 @@ FLAGS = [
 ]
 
 SOURCES = [
-    "api.cpp", "setup.hip", "estimate.hip", "sampler.hip",
+    "api.cpp", "plan.cpp", "setup.hip", "estimate.hip", "sampler.hip",
     "sampler_f64_naive.hip", "sampler_f64_pre.hip", "sampler_naive.hip",
     "sampler_f16x2.hip", "sampler_f16x1.hip", "sampler_bf16x1.hip",
 ]

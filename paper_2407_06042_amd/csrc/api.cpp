@@ -7,10 +7,10 @@
 
 #include "../../include/dmala.h"
 #include "common.hpp"
+#include "host.hpp"
 
-using namespace dmala;
-
-namespace {
+namespace dmala {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -26,13 +26,6 @@ dmala_status fail(dmala_status st, const char* fmt, ...) {
 }
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-struct Plan {
-  Shape sh;
-  size_t inst_off, state_off, wscratch_off, total;
-  double tau, am, bm, gm;
-  bool naive;
-};
 
 dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const dmala_params* p, Plan& pl) {
   if (!p) return fail(DMALA_ERR_ARG, "params is NULL");
@@ -76,6 +69,9 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
     sh.frag_bytes = (size_t)(p_passes(sh.pm) + kEPasses) * sh.RT * sh.KB * 1024 + 2 * (size_t)sh.Npad * 4;
   }
   if (p->tile_config < 0 || p->tile_config > 5) return fail(DMALA_ERR_ARG, "tile_config must be in [0, 5]");
+  if (p->wg_chain_blocks != 0 && p->wg_chain_blocks != 1 && p->wg_chain_blocks != 2 && p->wg_chain_blocks != 4)
+    return fail(DMALA_ERR_ARG, "wg_chain_blocks must be 0, 1, 2 or 4");
+  sh.cbw = p->wg_chain_blocks ? p->wg_chain_blocks : 4;
   if (fp64 || p->tile_config == 0) {
       sh.cfg = fp64 ? 0 : sampler_default_cfg(sh);
   } else {
@@ -113,17 +109,12 @@ dmala_status hip_fail(hipError_t e, const char* what) {
   return fail(DMALA_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-dmala_status run(const void* H, const void* y, const void* sigma2, int32_t n_inst, const Plan& pl,
-                 const dmala_params* p, const dmala_outputs* out, const int8_t* x_from, const int8_t* x_to,
-                 double* eval_out, void* ws, size_t ws_bytes, hipStream_t stream) {
-  if (!H || !y || !sigma2) return fail(DMALA_ERR_ARG, "H, y and sigma2 must be non-NULL");
-  if (!ws) return fail(DMALA_ERR_WORKSPACE, "workspace is NULL");
-  if (ws_bytes < pl.total) return fail(DMALA_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, pl.total);
-  if (((uintptr_t)ws & 255) != 0) return fail(DMALA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+dmala_status enqueue(const void* H, const void* y, const void* sigma2, int32_t n_inst, const Plan& pl,
+                     const dmala_params* p, const dmala_outputs* out, const InstDesc* desc, unsigned char* base,
+                     const int8_t* x_from, const int8_t* x_to, double* eval_out, hipStream_t stream) {
   const Shape& sh = pl.sh;
-  unsigned char* base = (unsigned char*)ws;
-
   SetupArgs sa{};
+  sa.desc = desc;
   sa.H = H; sa.y = y; sa.sigma2 = sigma2;
   sa.ws_inst = base + pl.inst_off; sa.inst_stride = sh.inst_bytes;
   sa.wscratch = base + pl.wscratch_off; sa.wscratch_stride = sh.wscratch_bytes;
@@ -138,6 +129,7 @@ dmala_status run(const void* H, const void* y, const void* sigma2, int32_t n_ins
   if (e != hipSuccess) return hip_fail(e, "setup launch");
 
   SamplerArgs ka{};
+  ka.desc = desc;
   ka.ws_inst = base + pl.inst_off; ka.inst_stride = sh.inst_bytes;
   ka.ws_state = base + pl.state_off; ka.state_stride = sh.state_bytes;
   ka.n_inst = n_inst; ka.N = sh.N; ka.Npad = sh.Npad; ka.C = sh.C; ka.Cpad = sh.Cpad; ka.T = sh.T;
@@ -159,6 +151,7 @@ dmala_status run(const void* H, const void* y, const void* sigma2, int32_t n_ins
 
   if (out->symbols || out->marginals || out->llrs || out->best_energy || out->marginals_mc) {
     EstArgs ea{};
+    ea.desc = desc;
     ea.H = H; ea.y = y; ea.sigma2 = sigma2;
     ea.ws_inst = base + pl.inst_off; ea.inst_stride = sh.inst_bytes;
     ea.ws_state = base + pl.state_off; ea.state_stride = sh.state_bytes;
@@ -174,7 +167,21 @@ dmala_status run(const void* H, const void* y, const void* sigma2, int32_t n_ins
   return DMALA_OK;
 }
 
-}  // namespace
+dmala_status run(const void* H, const void* y, const void* sigma2, int32_t n_inst, const Plan& pl,
+                 const dmala_params* p, const dmala_outputs* out, const int8_t* x_from, const int8_t* x_to,
+                 double* eval_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!H || !y || !sigma2) return fail(DMALA_ERR_ARG, "H, y and sigma2 must be non-NULL");
+  if (!ws) return fail(DMALA_ERR_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < pl.total) return fail(DMALA_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, pl.total);
+  if (((uintptr_t)ws & 255) != 0) return fail(DMALA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  return enqueue(H, y, sigma2, n_inst, pl, p, out, nullptr, (unsigned char*)ws, x_from, x_to, eval_out, stream);
+}
+
+}  // namespace host
+}  // namespace dmala
+
+using namespace dmala;
+using namespace dmala::host;
 
 extern "C" {
 

@@ -57,6 +57,7 @@ struct Shape {
   int pm;          // PMode (MFMA path)
   int win;         // proposal window half-width (0 = all levels), see the sampler
   int cfg;         // sampler work layout (see sampler_impl.hpp launch_rt)
+  int cbw;         // 16-chain blocks per workgroup for the one-wave layouts (1, 2 or 4)
   size_t inst_bytes;   // per-instance setup block
   size_t frag_bytes;   // MFMA fragments (MFMA path)
   size_t state_bytes;  // per-instance sampler->estimator block
@@ -77,7 +78,38 @@ __host__ __device__ inline StateOff state_offsets(int Cpad, int Npad) {
   return o;
 }
 
+// Where one instance's inputs and outputs live in the caller's buffers.  A
+// uniform batch uses no table (offsets follow from the instance index); an
+// uneven batch passes one entry per instance, grouped by shape class.
+struct InstDesc {
+  int64_t h_off;     // complex elements into H
+  int64_t y_off;     // complex elements into y
+  int64_t sym_off;   // antennas into symbols (sum of Nt over the preceding instances)
+  int64_t marg_off;  // floats into marginals / marginals_mc (sum of Nt * M)
+  int64_t llr_off;   // floats into llrs (sum of Nt * log2 M)
+  int64_t fs_off;    // bytes into final_state (sum of n_chains * 2 Nt)
+  int32_t orig;      // instance index in the caller's batch: sigma2, best_energy, accept_count, RNG counter
+  int32_t pad_;
+};
+
+__host__ __device__ inline InstDesc inst_desc(const InstDesc* d, int b, int nt, int nr, int M, int C) {
+  if (d) return d[b];
+  int nb = 0;
+  while ((1 << nb) < M) ++nb;
+  InstDesc r;
+  r.h_off = (int64_t)b * nt * nr;
+  r.y_off = (int64_t)b * nr;
+  r.sym_off = (int64_t)b * nt;
+  r.marg_off = (int64_t)b * nt * M;
+  r.llr_off = (int64_t)b * nt * nb;
+  r.fs_off = (int64_t)b * C * 2 * nt;
+  r.orig = b;
+  r.pad_ = 0;
+  return r;
+}
+
 struct SetupArgs {
+  const InstDesc* desc;
   const void* H; const void* y; const void* sigma2;
   unsigned char* ws_inst; size_t inst_stride;
   unsigned char* wscratch; size_t wscratch_stride;  // per-instance working matrix when nt > 64
@@ -86,6 +118,7 @@ struct SetupArgs {
 };
 
 struct SamplerArgs {
+  const InstDesc* desc;
   const unsigned char* ws_inst; size_t inst_stride;
   unsigned char* ws_state; size_t state_stride;
   int n_inst, N, Npad, C, Cpad, T;
@@ -98,6 +131,7 @@ struct SamplerArgs {
 };
 
 struct EstArgs {
+  const InstDesc* desc;
   const void* H; const void* y; const void* sigma2;
   const unsigned char* ws_inst; size_t inst_stride;
   const unsigned char* ws_state; size_t state_stride;

@@ -66,8 +66,9 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
   constexpr int NB = Q == 2 ? 1 : (Q == 4 ? 2 : (Q == 8 ? 3 : 4));
   const int b = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
   const int nt = a.nt, nr = a.nr, C = a.C, Npad = a.Npad, N = a.N, CH = a.chunk;
-  const R* Hg = (const R*)a.H + 2 * (size_t)b * nt * nr;
-  const R* y = (const R*)a.y + 2 * (size_t)b * nr;
+  const InstDesc dsc = inst_desc(a.desc, b, nt, nr, M, C);
+  const R* Hg = (const R*)a.H + 2 * dsc.h_off;
+  const R* y = (const R*)a.y + 2 * dsc.y_off;
   const InstParams ip = *(const InstParams*)(a.ws_inst + (size_t)b * a.inst_stride);
   const R s = (R)ip.s, tau = (R)ip.tau;
   const R inv_s2 = R(1) / (R)ip.sigma2, inv_tau = R(1) / tau;
@@ -265,11 +266,11 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
         const R inv = R(1) / sm;
         if (a.marginals) {
 #pragma unroll
-          for (int j = 0; j < Q; ++j) a.marginals[((size_t)b * nt + m) * M + kIt * Q + j] = (float)(fexp(lv[j] - mx) * inv);
+          for (int j = 0; j < Q; ++j) a.marginals[dsc.marg_off + (size_t)m * M + kIt * Q + j] = (float)(fexp(lv[j] - mx) * inv);
         }
         if (want_mc) {
 #pragma unroll
-          for (int j = 0; j < Q; ++j) a.marginals_mc[((size_t)b * nt + m) * M + kIt * Q + j] = (float)cnt[j] / (float)C;
+          for (int j = 0; j < Q; ++j) a.marginals_mc[dsc.marg_off + (size_t)m * M + kIt * Q + j] = (float)cnt[j] / (float)C;
         }
       }
     }
@@ -279,16 +280,16 @@ __global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
 #pragma unroll
     for (int q = 0; q < kLlrPerThread; ++q) {
       const int it = tid + q * nth;
-      if (it < n_llr) a.llrs[(size_t)b * n_llr + it] = (float)(lnum[q].value() - lden[q].value());
+      if (it < n_llr) a.llrs[dsc.llr_off + it] = (float)(lnum[q].value() - lden[q].value());
     }
   }
   // hard decision: smallest recomputed energy among the chains' best states
   if (tid == 0) {
     const int bc = best_c;
-    if (a.best_energy) a.best_energy[b] = (float)best_e;
+    if (a.best_energy) a.best_energy[dsc.orig] = (float)best_e;
     if (a.symbols)
       for (int m = 0; m < nt; ++m)
-        a.symbols[(size_t)b * nt + m] = Kb[(size_t)bc * Npad + 2 * m] * Q + Kb[(size_t)bc * Npad + 2 * m + 1];
+        a.symbols[dsc.sym_off + m] = Kb[(size_t)bc * Npad + 2 * m] * Q + Kb[(size_t)bc * Npad + 2 * m + 1];
   }
 }
 

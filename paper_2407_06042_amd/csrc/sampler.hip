@@ -14,7 +14,8 @@ hipError_t launch_sampler_bf16x1(const Shape&, const SamplerArgs&, bool, hipStre
 
 size_t sampler_lds_bytes(const Shape& sh) {
   if (sh.fp64) {
-    const int waves = sh.Cpad / 16 < 4 ? sh.Cpad / 16 : 4;
+    const int cb = sh.cbw > 0 ? sh.cbw : 4;
+    const int waves = sh.Cpad / 16 < cb ? sh.Cpad / 16 : cb;
     return sampler_cfg_lds(sh, sh.RT, 1, false, waves);
   }
   switch (sh.cfg) {

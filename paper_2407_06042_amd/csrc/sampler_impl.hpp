@@ -182,9 +182,12 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
   constexpr int W = WIN > 0 ? WIN : Q - 1;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
-  const int inst = blockIdx.x;
+  const int inst = blockIdx.x;                            // index within this launch (workspace slot)
   const int N = a.N, Npad = a.Npad;
   const unsigned char* blk = a.ws_inst + (size_t)inst * a.inst_stride;
+  // the caller's instance index (RNG counter, per-instance outputs) and final-state offset
+  const uint32_t rid = a.desc ? (uint32_t)a.desc[inst].orig : (uint32_t)inst;
+  const size_t fs_base = a.desc ? (size_t)a.desc[inst].fs_off : (size_t)inst * a.C * N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int cl = lane & 15, h = lane >> 4;
   const int wd = WD > 1 ? wave : 0;                       // dimension slice of this wave
@@ -414,7 +417,7 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
     // initial state from the t = 0 words
 #pragma unroll
     for (int rt = 0; rt < RTW; ++rt) {
-      uint32_t c[4] = {(uint32_t)(4 * (rt0 + rt) + h), 0u, (uint32_t)chain, (uint32_t)inst};
+      uint32_t c[4] = {(uint32_t)(4 * (rt0 + rt) + h), 0u, (uint32_t)chain, rid};
       philox4x32_10(c, key0, key1);
 #pragma unroll
       for (int i = 0; i < 4; ++i) kc[rt * 4 + i] = (int)(((uint64_t)(c[i] >> 8) * Q) >> 24);
@@ -438,13 +441,13 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
       kbest[rt] = (uint32_t)kc[rt * 4] | ((uint32_t)kc[rt * 4 + 1] << 8) | ((uint32_t)kc[rt * 4 + 2] << 16) | ((uint32_t)kc[rt * 4 + 3] << 24);
     int nacc = 0;
     uint32_t abits = 0;
-    const size_t trow = (size_t)inst * a.C + (live ? chain : 0);
+    const size_t trow = (size_t)rid * a.C + (live ? chain : 0);
 
     for (int t = 1; t <= a.T; ++t) {
       uint32_t w[RTW][4];
 #pragma unroll
       for (int rt = 0; rt < RTW; ++rt) {
-        w[rt][0] = (uint32_t)(4 * (rt0 + rt) + h); w[rt][1] = (uint32_t)t; w[rt][2] = (uint32_t)chain; w[rt][3] = (uint32_t)inst;
+        w[rt][0] = (uint32_t)(4 * (rt0 + rt) + h); w[rt][1] = (uint32_t)t; w[rt][2] = (uint32_t)chain; w[rt][3] = rid;
         philox4x32_10(w[rt], key0, key1);
       }
       // 1. draw x' (padding dimensions never move) and -log q(x'|x)
@@ -538,13 +541,13 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
         if (a.final_state) {
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if (n0 + i < N) a.final_state[((size_t)inst * a.C + chain) * N + n0 + i] = (int8_t)kc[rt * 4 + i];
+            if (n0 + i < N) a.final_state[fs_base + (size_t)chain * N + n0 + i] = (int8_t)kc[rt * 4 + i];
         }
       }
       if (h == 0 && wd == 0) {
         ((double*)(st + so.ebest))[chain] = (double)Ebest;
         ((int32_t*)(st + so.nacc))[chain] = nacc;
-        if (a.accept_count) a.accept_count[(size_t)inst * a.C + chain] = nacc;
+        if (a.accept_count) a.accept_count[(size_t)rid * a.C + chain] = nacc;
       }
     }
   }
@@ -566,7 +569,11 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
   const int chain_blocks = sh.Cpad / 16;
   int waves, gy;
   if (WD > 1) { waves = WD; gy = chain_blocks; }
-  else { waves = chain_blocks < 4 ? chain_blocks : 4; gy = (chain_blocks + waves - 1) / waves; }
+  else {
+    const int cb = sh.cbw > 0 ? sh.cbw : 4;
+    waves = chain_blocks < cb ? chain_blocks : cb;
+    gy = (chain_blocks + waves - 1) / waves;
+  }
   const dim3 grid(a.n_inst, gy);
   const size_t lds = sampler_cfg_lds(sh, RTW, WD, MG, waves);
   auto k = eval ? sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN> : sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN>;

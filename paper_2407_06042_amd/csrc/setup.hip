@@ -108,9 +108,10 @@ template <typename TIn, bool WGLOB>
 __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   const int b = blockIdx.x, tid = threadIdx.x, nt = a.nt, nr = a.nr, N = a.N, Npad = a.Npad;
   const int ld = nt + 1;  // padded leading dimension of the LDS matrices (no bank conflicts on columns)
-  const TIn* Hg = (const TIn*)a.H + 2 * (size_t)b * nt * nr;
-  const TIn* y = (const TIn*)a.y + 2 * (size_t)b * nr;
-  const double sigma2 = (double)((const TIn*)a.sigma2)[b];
+  const InstDesc dsc = inst_desc(a.desc, b, nt, nr, a.Q * a.Q, 1);
+  const TIn* Hg = (const TIn*)a.H + 2 * dsc.h_off;
+  const TIn* y = (const TIn*)a.y + 2 * dsc.y_off;
+  const double sigma2 = (double)((const TIn*)a.sigma2)[dsc.orig];
   extern __shared__ double smem_setup[];
   // nt x ld working matrix: in LDS, or (large nt) in this instance's slice of the workspace
   cd* W;
