@@ -133,6 +133,6 @@ def test_plan_autotune_and_cache(tmp_path):
     plan2 = dm.Plan(shapes, C, T, 5)
     plan2.autotune(H, y, sig, cache)
     info2 = plan2.classes()
-    assert [(c["tile_config"], c["wg_chain_blocks"], c["tuned_ms"]) for c in info2] == \
-           [(c["tile_config"], c["wg_chain_blocks"], c["tuned_ms"]) for c in info]
+    assert [(c["tile_config"], c["wg_chain_blocks"]) for c in info2] == [(c["tile_config"], c["wg_chain_blocks"]) for c in info]
+    np.testing.assert_allclose([c["tuned_ms"] for c in info2], [c["tuned_ms"] for c in info], rtol=1e-5, atol=1e-6)
     print("autotuned", info, flush=True)
