@@ -138,6 +138,46 @@ def run_form(dm, torch, b, precision, steps, warmup):
                 setup_ms=float(np.mean(setup_ms)), estimator_ms=float(np.mean(est_ms)), ser=ser)
 
 
+def bench_uneven(args):
+    """4096 uneven problems: Nt in {16,32,64,128}, Nr in {Nt,2Nt}, M in {4,16,64}, SNR U(10,30) dB,
+    32 chains x 100 transitions, BF16 gradient with fp32 acceptance, one plan (graph) launch per step."""
+    import torch
+    import paper_2407_06042_amd as dm
+    d = W.c3_uneven()
+    shapes = d["shapes"]
+    H, y, sig = dm.pack_uneven(d["H"], d["y"], d["sigma2"])
+    C, T = 32, 100
+    forms = [f for f in args.forms.split(",") if f] if args.forms != "fp32,bf16" else ["bf16", "fp32"]
+    truth = np.concatenate(d["x_idx"])
+    res = {}
+    for f in forms:
+        plan = dm.Plan(shapes, C, T, SEED, precision=f, outputs=("symbols",))
+        if args.autotune:
+            plan.autotune(H, y, sig, args.autotune)
+        ev = HipEvents(4 * args.steps)
+        for _ in range(args.warmup):
+            plan(H, y, sig)
+        torch.cuda.synchronize()
+        for k in range(args.steps):
+            out = plan(H, y, sig, events=[ev.ev[4 * k], None, None, ev.ev[4 * k + 3]])
+        torch.cuda.synchronize()
+        ms = float(np.mean([ev.elapsed_ms(4 * k, 4 * k + 3) for k in range(args.steps)]))
+        ser = float(np.mean(out["symbols"].cpu().numpy() != truth))
+        res[f] = dict(ms_per_step=ms, chain_iters_per_s=len(shapes) * C * T / (ms * 1e-3), ser=ser,
+                      classes=plan.classes())
+    r = res[forms[0]]
+    line = {"metric": METRIC, "value": r["chain_iters_per_s"], "unit": "chain-iterations/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": forms[0], "data": "synthetic",
+            "config": {"workload": "4096 uneven problems: Nt in {16,32,64,128}, Nr in {Nt,2Nt}, M in {4,16,64}, "
+                                   "SNR U(10,30) dB, 32 chains x 100 transitions, one graph launch",
+                       "instances": len(shapes)},
+            "vectors_per_s": len(shapes) / (r["ms_per_step"] * 1e-3), "ser": r["ser"],
+            "forms": {f: {k: v for k, v in res[f].items() if k != "classes"} for f in forms},
+            "classes": r["classes"]}
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +188,9 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16", help="comma list; the first is the reported value")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference kernel for HBM counters)")
+    ap.add_argument("--workload", default="c2", choices=("c2", "uneven"),
+                    help="c2: the default 32x32 64-QAM sweep; uneven: 4096 mixed-shape problems in one plan")
+    ap.add_argument("--autotune", default=None, help="uneven workload: autotune cache path (JSON)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the detector has no multi-GPU path to time "
@@ -163,6 +206,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_bytes=1 << 30, reps=3)))
         return
+
+    if args.workload == "uneven":
+        return bench_uneven(args)
 
     batch = W.c2_snr_sweep(n_per_snr=1024).as_precision(np.float32)
     cpu = None

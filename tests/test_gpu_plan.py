@@ -136,3 +136,44 @@ def test_plan_autotune_and_cache(tmp_path):
     assert [(c["tile_config"], c["wg_chain_blocks"]) for c in info2] == [(c["tile_config"], c["wg_chain_blocks"]) for c in info]
     np.testing.assert_allclose([c["tuned_ms"] for c in info2], [c["tuned_ms"] for c in info], rtol=1e-5, atol=1e-6)
     print("autotuned", info, flush=True)
+
+
+def test_uneven_full_size_sampled_parity():
+    """4096 uneven problems (Nt 16..128, Nr in {Nt, 2Nt}, 4/16/64-QAM, SNR 10..30 dB), 32 chains x 100
+    transitions in one plan launch: sampled instances (one per antenna count) follow the oracle's chains,
+    and the BF16-gradient form's symbol error rate matches the fp32 form's."""
+    import torch
+    import paper_2407_06042_amd as dm
+    d = W.c3_uneven()
+    shapes = d["shapes"]
+    Hs = [h.astype(np.complex64).astype(np.complex128) for h in d["H"]]
+    ys = [v.astype(np.complex64).astype(np.complex128) for v in d["y"]]
+    s2 = d["sigma2"].astype(np.float32).astype(np.float64)
+    H, y, sig = dm.pack_uneven(Hs, ys, s2)
+    C, T, seed = 32, 100, 0x2407060423
+    ser = {}
+    for prec in ("fp32", "bf16"):
+        plan = dm.Plan(shapes, C, T, seed, precision=prec, outputs=("symbols", "final_state", "accept_count"))
+        res = plan(H, y, sig)
+        torch.cuda.synchronize()
+        out = {k: v.cpu().numpy() for k, v in res.items()}
+        sym_off = np.concatenate([[0], np.cumsum([s[0] for s in shapes])])
+        truth = np.concatenate(d["x_idx"])
+        ser[prec] = float(np.mean(out["symbols"] != truth))
+        if prec != "fp32":
+            continue
+        off = _offsets(shapes, C)
+        picks = [next(i for i, s in enumerate(shapes) if s[0] == nt) for nt in (16, 32, 64, 128)]
+        for b in picks:
+            nt, nr, M = shapes[b]
+            o = odm.detect(Hs[b], ys[b], s2[b], M, C, T, seed, instance=b, trace=True, estimators=False)
+            tr = o["trace"]
+            clean = ~np.any((tr["cat_margin"] < EPS32[0]) | (tr["mh_margin"] < EPS32[1]), axis=0)
+            fs = out["final_state"][off["fs"][b]:off["fs"][b + 1]].reshape(C, 2 * nt)
+            print("uneven sample", b, shapes[b], "clean chains", int(clean.sum()), flush=True)
+            np.testing.assert_array_equal(fs[clean], o["k"][clean])
+            np.testing.assert_array_equal(out["accept_count"][b * C:(b + 1) * C][clean], o["n_acc"][clean])
+    n_sym = sum(s[0] for s in shapes)
+    sd = np.sqrt(ser["fp32"] * (1 - ser["fp32"]) / n_sym)
+    print("uneven SER", ser, flush=True)
+    assert abs(ser["bf16"] - ser["fp32"]) < 4 * np.sqrt(2) * sd + 1e-3

@@ -128,18 +128,22 @@ def c5_learned_eval(n_per_snr=2048, seed=5, snrs=(20, 22, 24, 26)):
 def c3_uneven(n_inst=4096, seed=3):
     """Uneven batch: Nt in {16,32,64,128}, Nr in {Nt,2Nt}, M in {4,16,64}, SNR U(10,30) dB.
 
-    Returns a list of (instance ids, Batch) groups, one per (Nt, Nr, M) shape,
-    plus the per-instance shape table, all drawn from one seeded stream.
+    Returns a dict of per-instance lists in batch order: shapes (Nt, Nr, M), H
+    (Nr, Nt), y, sigma2, x_idx, snr_db.  Each instance draws x, H, n from its own
+    seeded stream (i.i.d. Rayleigh CN(0, 1/Nr)).
     """
     rng = np.random.default_rng(np.random.SeedSequence([3, int(seed)]))
     nts = rng.choice([16, 32, 64, 128], size=n_inst)
     nrs = nts * rng.choice([1, 2], size=n_inst)
     Ms = rng.choice([4, 16, 64], size=n_inst)
     snrs = rng.uniform(10.0, 30.0, size=n_inst)
-    groups = []
-    keys = sorted(set(zip(nts.tolist(), nrs.tolist(), Ms.tolist())))
-    for gi, (nt, nr, M) in enumerate(keys):
-        ids = np.nonzero((nts == nt) & (nrs == nr) & (Ms == M))[0]
-        b = make_batch(nt, nr, M, snrs[ids], len(ids), seed * 1000 + gi, cfg_id=3)
-        groups.append((ids, b))
-    return groups, dict(nt=nts, nr=nrs, M=Ms, snr_db=snrs)
+    out = dict(shapes=[], H=[], y=[], sigma2=[], x_idx=[], snr_db=snrs)
+    for i in range(n_inst):
+        b = make_batch(int(nts[i]), int(nrs[i]), int(Ms[i]), snrs[i], 1, seed * 100000 + i, cfg_id=3)
+        out["shapes"].append((int(nts[i]), int(nrs[i]), int(Ms[i])))
+        out["H"].append(b.H[0])
+        out["y"].append(b.y[0])
+        out["sigma2"].append(b.sigma2[0])
+        out["x_idx"].append(b.x_idx[0])
+    out["sigma2"] = np.array(out["sigma2"])
+    return out
