@@ -8,6 +8,8 @@ imports it.  Modules:
 * philox -- Philox4x32-10 (Salmon et al., SC'11) and the random-word layout;
 * dmala  -- system model, proposal, Algorithm 1, estimators, Algorithm 2;
 * exact  -- enumeration over A^N: posterior, exact LLRs/marginals, MAP,
-            transition matrix, convergence rate, TV distance.
+            transition matrix, convergence rate, TV distance;
+* learned -- learned proposal (network, features), its mixture with the plain
+            kernel, exact mixture kernels, training loss, gradients and Adam.
 """
-from . import philox, dmala, exact  # noqa: F401
+from . import philox, dmala, exact, learned  # noqa: F401
