@@ -63,8 +63,34 @@ typedef enum {
 typedef enum { DMALA_FP64 = 0, DMALA_FP32 = 1, DMALA_BF16 = 2, DMALA_FP16 = 3 } dmala_precision;
 
 /* Proposal: PRECOND = the preconditioned discrete Langevin proposal (the
- * paper's evaluated variant); NAIVE = eq. exp_fac with the plain gradient. */
-typedef enum { DMALA_PRECOND = 0, DMALA_NAIVE = 1 } dmala_proposal;
+ * paper's evaluated variant); NAIVE = eq. exp_fac with the plain gradient;
+ * LEARNED = per transition and chain, the PRECOND kernel with probability
+ * mix_eps and otherwise the learned kernel: the same per-dimension discretised
+ * Gaussian over the levels, with its centre and precision set by a small
+ * per-antenna network (dmala_mlp_forward) from features of the current state.
+ * Each kernel is a full MH step with its own forward and reverse proposal, so
+ * pi_a stays invariant (the paper names such data-driven additions as future
+ * work, Section VI; admissibility follows from eq. acc_prob).  The kernel
+ * choice uses the 24-bit uniform from the low bytes of words 4, 5, 6 of the
+ * transition's random stream (plain iff u < mix_eps).  Not with DMALA_FP64. */
+typedef enum { DMALA_PRECOND = 0, DMALA_NAIVE = 1, DMALA_LEARNED = 2 } dmala_proposal;
+
+/* The learned proposal's network: 7 features per antenna -> 64 -> 64 -> 4
+ * (ReLU), parameters as one float32 array, row-major blocks in this order:
+ *   W1[64][7], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]   (4932 floats).
+ * Features of antenna m at state x (c = (Q-1)/2, h = Q/2, index units):
+ *   (mu_re - c)/h, (mu_im - c)/h, (k_re - c)/h, (k_im - c)/h,
+ *   log2(sigma^2 M_mm / (8 s^2)) / 8, log2(sigma^2 / (8 s^2 G_mm)) / 8, log2(Q) / 4
+ * with k the level indices of x_m, mu the centre of the PRECOND proposal at x
+ * in index units, G = H^H H, M = (G + gamma I)^-1.  Outputs (D_re, D_im,
+ * b_re, b_im): the learned proposal of axis p has centre mu_p + D_p and
+ * precision kappa * 2^clamp(b_p, -4, 4), kappa the PRECOND precision.
+ * In the sampler the network runs in bfloat16 (parameters, inputs, hidden
+ * activations rounded to nearest even) with fp32 sums. */
+#define DMALA_MLP_PARAMS 4932
+/* Floats per exported training row: 7 features, mu_re, mu_im, kappa (natural
+ * log units), Q, 0. */
+#define DMALA_TRAIN_ROW 12
 
 typedef struct {
   int32_t n_chains;          /* parallel samplers per instance, 1..1024 */
@@ -86,6 +112,9 @@ typedef struct {
                                 not match the shape returns DMALA_ERR_UNSUPPORTED) */
   int32_t wg_chain_blocks;   /* layouts 0-2: 16-chain blocks sharing one workgroup (and one LDS copy
                                 of the matrices): 0 = automatic (up to 4), or 1, 2, 4 */
+  const float* mlp_weights;  /* LEARNED: device float32 [DMALA_MLP_PARAMS]; otherwise ignored.
+                                LEARNED excludes layout 2 (128 dims use layout 3) */
+  double mix_eps;            /* LEARNED: probability of the PRECOND kernel per transition, in [0, 1] */
 } dmala_params;
 
 /* Device output buffers; any pointer may be NULL to skip that output. */
@@ -100,6 +129,9 @@ typedef struct {
   uint32_t* trace_accept;    /* [n_inst][n_chains][ceil(n_iters/32)] accept bit of transition t at bit t%32 */
   uint32_t* trace_hash;      /* [n_inst][n_chains][n_iters] state fingerprint after transition t:
                                 sum_n (k_n + 1) * ((2n + 1) * 0x9E3779B1) mod 2^32 */
+  float* train_rows;         /* [n_inst][n_chains][Nt][DMALA_TRAIN_ROW] network training rows at the final
+                                state (PRECOND or LEARNED only); plans index rows as
+                                (sum_{j<b} Nt_j) * n_chains + chain * Nt_b + m */
   void* stage_events[4];     /* optional hipEvent_t handles recorded on `stream` before the setup,
                                 sampler and estimator kernels and after the last one (profiling);
                                 NULL entries are skipped */
@@ -179,6 +211,31 @@ dmala_status dmala_plan_class_info(dmala_plan plan, int32_t k, dmala_shape* shap
                                    int32_t* tile_config, int32_t* wg_chain_blocks, double* tuned_ms);
 
 void dmala_plan_destroy(dmala_plan plan);
+
+/* ---- The learned proposal's network ----
+ * Forward pass in the sampler's precision (bfloat16 operands, fp32 sums, the
+ * same device code): rows = device float32 [n_rows][row_stride] whose first 7
+ * entries are the features; out = device float32 [n_rows][4]. */
+dmala_status dmala_mlp_forward(const float* weights, const float* rows, int32_t n_rows, int32_t row_stride,
+                               float* out, dmala_stream_t stream);
+
+/* Bytes of device workspace dmala_mlp_train_step needs for n_rows rows. */
+size_t dmala_mlp_train_workspace_size(int32_t n_rows);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; `step`
+ * counts from 1) on the mean over rows of the cross-entropy
+ *   -log q_re(t_re) - log q_im(t_im)
+ * of the learned proposal (float32, unrounded network) at target levels.
+ *   weights, adam_m, adam_v: device float32 [DMALA_MLP_PARAMS], updated in place;
+ *   rows: device float32 [n_rows][DMALA_TRAIN_ROW] as exported by the sampler;
+ *   targets: device int32 [n_rows][2] level indices (Re, Im) in [0, Q);
+ *   loss (optional): device float32 [1], the mean loss before the step;
+ *   grad (optional): device float32 [DMALA_MLP_PARAMS], the gradient of that loss.
+ * Deterministic (fixed summation order). */
+dmala_status dmala_mlp_train_step(float* weights, float* adam_m, float* adam_v, int32_t step, float lr,
+                                  const float* rows, const int32_t* targets, int32_t n_rows,
+                                  float* loss, float* grad, void* workspace, size_t workspace_bytes,
+                                  dmala_stream_t stream);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* dmala_last_error(void);

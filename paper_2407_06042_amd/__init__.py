@@ -14,9 +14,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmala.so")
 
 FP64, FP32, BF16, FP16 = 0, 1, 2, 3
-PRECOND, NAIVE = 0, 1
+PRECOND, NAIVE, LEARNED = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp16": FP16}
-PROPOSALS = {"precond": PRECOND, "naive": NAIVE}
+PROPOSALS = {"precond": PRECOND, "naive": NAIVE, "learned": LEARNED}
+MLP_PARAMS = 4932     # DMALA_MLP_PARAMS
+TRAIN_ROW = 12        # DMALA_TRAIN_ROW
 STATUS = {0: "DMALA_OK", -1: "DMALA_ERR_ARG", -2: "DMALA_ERR_UNSUPPORTED", -4: "DMALA_ERR_WORKSPACE", -5: "DMALA_ERR_HIP"}
 
 
@@ -24,7 +26,8 @@ class Params(ctypes.Structure):
     _fields_ = [("n_chains", ctypes.c_int32), ("n_iters", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("precision", ctypes.c_int), ("proposal", ctypes.c_int), ("tau", ctypes.c_double),
                 ("alpha_mult", ctypes.c_double), ("beta_mult", ctypes.c_double), ("gamma_mult", ctypes.c_double),
-                ("tile_config", ctypes.c_int32), ("wg_chain_blocks", ctypes.c_int32)]
+                ("tile_config", ctypes.c_int32), ("wg_chain_blocks", ctypes.c_int32),
+                ("mlp_weights", ctypes.c_void_p), ("mix_eps", ctypes.c_double)]
 
 
 class Shape(ctypes.Structure):
@@ -35,7 +38,7 @@ class Outputs(ctypes.Structure):
     _fields_ = [("symbols", ctypes.c_void_p), ("marginals", ctypes.c_void_p), ("llrs", ctypes.c_void_p),
                 ("best_energy", ctypes.c_void_p), ("final_state", ctypes.c_void_p), ("accept_count", ctypes.c_void_p),
                 ("marginals_mc", ctypes.c_void_p), ("trace_accept", ctypes.c_void_p), ("trace_hash", ctypes.c_void_p),
-                ("stage_events", ctypes.c_void_p * 4)]
+                ("train_rows", ctypes.c_void_p), ("stage_events", ctypes.c_void_p * 4)]
 
 
 class DmalaError(RuntimeError):
@@ -76,6 +79,12 @@ def lib():
                                             ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
         L.dmala_plan_destroy.restype = None
         L.dmala_plan_destroy.argtypes = [vp]
+        L.dmala_mlp_forward.restype = ctypes.c_int
+        L.dmala_mlp_forward.argtypes = [vp, vp, i32, i32, vp, vp]
+        L.dmala_mlp_train_workspace_size.restype = sz
+        L.dmala_mlp_train_workspace_size.argtypes = [i32]
+        L.dmala_mlp_train_step.restype = ctypes.c_int
+        L.dmala_mlp_train_step.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp, i32, vp, vp, vp, sz, vp]
         L.dmala_last_error.restype = ctypes.c_char_p
         L.dmala_version.restype = ctypes.c_char_p
         _lib = L
@@ -84,6 +93,7 @@ def lib():
 
 EXPORTED = ["dmala_workspace_size", "dmala_detect", "dmala_debug_eval", "dmala_plan_create", "dmala_plan_execute",
             "dmala_plan_autotune", "dmala_plan_num_classes", "dmala_plan_class_info", "dmala_plan_destroy",
+            "dmala_mlp_forward", "dmala_mlp_train_workspace_size", "dmala_mlp_train_step",
             "dmala_last_error", "dmala_version"]
 
 
@@ -92,10 +102,22 @@ def last_error():
 
 
 def make_params(n_chains, n_iters, seed, precision="fp32", proposal="precond", tau=2.0,
-                alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, tile_config=0):
+                alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, tile_config=0, mlp_weights=None, mix_eps=0.0):
+    """mlp_weights: device float32 tensor of MLP_PARAMS values (learned proposal only)."""
+    w = None
+    if mlp_weights is not None:
+        _check_weights(mlp_weights)
+        w = mlp_weights.data_ptr()
     return Params(int(n_chains), int(n_iters), int(seed) & ((1 << 64) - 1), PRECISIONS[precision],
                   PROPOSALS[proposal], float(tau), float(alpha_mult), float(beta_mult), float(gamma_mult),
-                  int(tile_config), 0)
+                  int(tile_config), 0, w, float(mix_eps))
+
+
+def _check_weights(w):
+    import torch
+    if not (isinstance(w, torch.Tensor) and w.is_cuda and w.dtype == torch.float32 and w.is_contiguous()
+            and w.numel() == MLP_PARAMS):
+        raise ValueError("mlp weights must be a contiguous float32 device tensor of %d values" % MLP_PARAMS)
 
 
 def workspace_size(n_inst, nt, nr, M, params):
@@ -123,13 +145,15 @@ class Detector:
 
     def __init__(self, n_inst, nt, nr, M, n_chains, n_iters, seed=0, precision="fp32", proposal="precond",
                  tau=2.0, alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, device="cuda",
-                 outputs=("symbols", "marginals", "llrs", "best_energy"), trace=False, tile_config=0):
+                 outputs=("symbols", "marginals", "llrs", "best_energy"), trace=False, tile_config=0,
+                 mlp_weights=None, mix_eps=0.0):
         import torch
         self.torch = torch
         self.n_inst, self.nt, self.nr, self.M = n_inst, nt, nr, M
         self.precision = precision
+        self.mlp_weights = mlp_weights  # keeps the tensor alive while the detector holds its pointer
         self.params = make_params(n_chains, n_iters, seed, precision, proposal, tau, alpha_mult, beta_mult,
-                                  gamma_mult, tile_config)
+                                  gamma_mult, tile_config, mlp_weights, mix_eps)
         self.ws_bytes = workspace_size(n_inst, nt, nr, M, self.params)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
         nb = int(round(np.log2(M)))
@@ -137,7 +161,8 @@ class Detector:
                       llrs=((n_inst, nt, nb), torch.float32), best_energy=((n_inst,), torch.float32),
                       final_state=((n_inst, n_chains, 2 * nt), torch.int8),
                       accept_count=((n_inst, n_chains), torch.int32),
-                      marginals_mc=((n_inst, nt, M), torch.float32))
+                      marginals_mc=((n_inst, nt, M), torch.float32),
+                      train_rows=((n_inst, n_chains, nt, TRAIN_ROW), torch.float32))
         want = set(outputs)
         if trace:
             want |= {"final_state", "accept_count"}
@@ -193,12 +218,15 @@ def detect(Hcm, y, sigma2, M, n_chains, n_iters, seed, **kw):
 
 
 def debug_eval(Hcm, y, sigma2, M, x_from, x_to, precision="fp32", proposal="precond", tau=2.0,
-               alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, tile_config=0):
-    """Transition quantities of the device chain for state pairs (see dmala_debug_eval)."""
+               alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, tile_config=0, mlp_weights=None):
+    """Transition quantities of the device chain for state pairs (see dmala_debug_eval).
+
+    With proposal="learned" the quantities are those of the learned kernel alone."""
     import torch
     n_inst, nt, nr = Hcm.shape
     n_pairs = x_from.shape[1]
-    p = make_params(n_pairs, 0, 0, precision, proposal, tau, alpha_mult, beta_mult, gamma_mult, tile_config)
+    p = make_params(n_pairs, 0, 0, precision, proposal, tau, alpha_mult, beta_mult, gamma_mult, tile_config,
+                    mlp_weights, 0.0)
     ws_bytes = workspace_size(n_inst, nt, nr, M, p)
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=Hcm.device)
     wp = (ws.data_ptr() + 255) // 256 * 256
@@ -227,13 +255,16 @@ class Plan:
     """Uneven batch (instances of different Nt, Nr, M) run as one graph launch."""
 
     def __init__(self, shapes, n_chains, n_iters, seed=0, precision="fp32", proposal="precond", tau=2.0,
-                 device="cuda", outputs=("symbols", "marginals", "llrs", "best_energy", "final_state", "accept_count")):
+                 device="cuda", outputs=("symbols", "marginals", "llrs", "best_energy", "final_state", "accept_count"),
+                 mlp_weights=None, mix_eps=0.0):
         import torch
         self.torch = torch
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
         n = len(self.shapes)
         arr = (Shape * n)(*[Shape(*s) for s in self.shapes])
-        self.params = make_params(n_chains, n_iters, seed, precision, proposal, tau)
+        self.mlp_weights = mlp_weights
+        self.params = make_params(n_chains, n_iters, seed, precision, proposal, tau, mlp_weights=mlp_weights,
+                                  mix_eps=mix_eps)
         self.precision = precision
         h = ctypes.c_void_p()
         ws = ctypes.c_size_t()
@@ -248,7 +279,8 @@ class Plan:
         llr = sum(s[0] * int(round(np.log2(s[2]))) for s in self.shapes)
         sizes = dict(symbols=(nt_sum, torch.int32), marginals=(marg, torch.float32), llrs=(llr, torch.float32),
                      best_energy=(n, torch.float32), final_state=(n_chains * 2 * nt_sum, torch.int8),
-                     accept_count=(n * n_chains, torch.int32), marginals_mc=(marg, torch.float32))
+                     accept_count=(n * n_chains, torch.int32), marginals_mc=(marg, torch.float32),
+                     train_rows=(n_chains * nt_sum * TRAIN_ROW, torch.float32))
         self.out = {k: torch.empty(sizes[k][0], dtype=sizes[k][1], device=device) for k in outputs}
         o = Outputs()
         for name, _ in Outputs._fields_[:-1]:
@@ -292,3 +324,62 @@ class Plan:
         if h is not None and h.value and _lib is not None:
             _lib.dmala_plan_destroy(h)
             self.handle = None
+
+
+# ---------------------------------------------------------------- the learned proposal's network
+
+def mlp_forward(weights, rows, row_stride=None):
+    """Network outputs (R, 4) in the sampler's bf16 precision; rows: (R, >= 7) float32 device tensor."""
+    import torch
+    _check_weights(weights)
+    rows = rows.contiguous()
+    if rows.dtype != torch.float32 or not rows.is_cuda or rows.dim() != 2:
+        raise ValueError("rows must be a 2-D float32 device tensor")
+    R = rows.shape[0]
+    out = torch.empty((R, 4), dtype=torch.float32, device=rows.device)
+    st = lib().dmala_mlp_forward(weights.data_ptr(), rows.data_ptr(), R, rows.shape[1] if row_stride is None else row_stride,
+                                 out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    if st != 0:
+        raise DmalaError(st, last_error())
+    return out
+
+
+class MlpTrainer:
+    """Adam on the learned proposal's network with the library's training kernels.
+
+    weights: float32 device tensor (updated in place).  Each step takes training
+    rows (R, TRAIN_ROW) as exported by the sampler and int32 targets (R, 2)."""
+
+    def __init__(self, weights, lr=1e-3):
+        import torch
+        _check_weights(weights)
+        self.torch = torch
+        self.w = weights
+        self.m = torch.zeros_like(weights)
+        self.v = torch.zeros_like(weights)
+        self.lr = float(lr)
+        self.t = 0
+        self.ws = None
+        self.ws_rows = 0
+        self.loss = torch.zeros(1, dtype=torch.float32, device=weights.device)
+        self.grad = torch.zeros_like(weights)
+
+    def step(self, rows, targets, lr=None):
+        torch = self.torch
+        R = rows.shape[0]
+        if tuple(rows.shape) != (R, TRAIN_ROW) or rows.dtype != torch.float32 or not rows.is_contiguous():
+            raise ValueError("rows must be contiguous float32 (R, %d)" % TRAIN_ROW)
+        if tuple(targets.shape) != (R, 2) or targets.dtype != torch.int32 or not targets.is_contiguous():
+            raise ValueError("targets must be contiguous int32 (R, 2)")
+        need = lib().dmala_mlp_train_workspace_size(R)
+        if self.ws is None or self.ws.numel() < need + 256:
+            self.ws = torch.empty(need + 256, dtype=torch.uint8, device=self.w.device)
+        wp = (self.ws.data_ptr() + 255) // 256 * 256
+        self.t += 1
+        st = lib().dmala_mlp_train_step(self.w.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), self.t,
+                                        float(self.lr if lr is None else lr), rows.data_ptr(), targets.data_ptr(), R,
+                                        self.loss.data_ptr(), self.grad.data_ptr(), wp, need,
+                                        torch.cuda.current_stream().cuda_stream)
+        if st != 0:
+            raise DmalaError(st, last_error())
+        return self.loss

@@ -34,7 +34,14 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
   if (p->n_chains < 1 || p->n_chains > 1024) return fail(DMALA_ERR_ARG, "n_chains must be in [1, 1024] (got %d)", p->n_chains);
   if (p->n_iters < 0 || p->n_iters > 65535) return fail(DMALA_ERR_ARG, "n_iters must be in [0, 65535] (got %d)", p->n_iters);
   if (p->precision < DMALA_FP64 || p->precision > DMALA_FP16) return fail(DMALA_ERR_ARG, "unknown precision %d", (int)p->precision);
-  if (p->proposal != DMALA_PRECOND && p->proposal != DMALA_NAIVE) return fail(DMALA_ERR_ARG, "unknown proposal %d", (int)p->proposal);
+  if (p->proposal != DMALA_PRECOND && p->proposal != DMALA_NAIVE && p->proposal != DMALA_LEARNED)
+    return fail(DMALA_ERR_ARG, "unknown proposal %d", (int)p->proposal);
+  const bool lrn = p->proposal == DMALA_LEARNED;
+  if (lrn) {
+    if (p->precision == DMALA_FP64) return fail(DMALA_ERR_UNSUPPORTED, "DMALA_LEARNED is not available with DMALA_FP64");
+    if (!p->mlp_weights) return fail(DMALA_ERR_ARG, "DMALA_LEARNED needs mlp_weights");
+    if (!(p->mix_eps >= 0.0 && p->mix_eps <= 1.0)) return fail(DMALA_ERR_ARG, "mix_eps must be in [0, 1]");
+  }
   if (!(std::isfinite(p->tau) && std::isfinite(p->alpha_mult) && std::isfinite(p->beta_mult) && std::isfinite(p->gamma_mult)))
     return fail(DMALA_ERR_ARG, "non-finite tau/alpha/beta/gamma multiplier");
   int Q = 0;
@@ -51,6 +58,7 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
   sh.RT = sh.Npad / 16; sh.KB = sh.RT / 2;
   sh.C = p->n_chains; sh.Cpad = 16 * ((sh.C + 15) / 16); sh.T = p->n_iters;
   sh.fp64 = fp64 ? 1 : 0;
+  sh.lrn = lrn ? 1 : 0;
   pl.naive = p->proposal == DMALA_NAIVE;
   if (pl.naive) sh.pm = PM_NAIVE;
   else if (p->precision == DMALA_BF16) sh.pm = PM_BF16X1;
@@ -61,12 +69,13 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
   {
     const double am = p->alpha_mult > 0 ? p->alpha_mult : 1.0, bm = p->beta_mult > 0 ? p->beta_mult : 1.0;
     const double kL = 2.0 * 1.4426950408889634 / (am * bm);
-    sh.win = (!fp64 && !pl.naive && Q >= 8 && kL * 12.0 >= 30.0) ? 3 : 0;
+    sh.win = (!fp64 && !pl.naive && !lrn && Q >= 8 && kL * 12.0 >= 30.0) ? 3 : 0;
   }
   if (fp64) {
     sh.frag_bytes = round_up((2 * (size_t)sh.Npad * sh.Npad + 2 * (size_t)sh.Npad) * 8, 16);
   } else {
-    sh.frag_bytes = (size_t)(p_passes(sh.pm) + kEPasses) * sh.RT * sh.KB * 1024 + 2 * (size_t)sh.Npad * 4;
+    // fragments, then the vectors pb, ez and the per-antenna network features
+    sh.frag_bytes = (size_t)(p_passes(sh.pm) + kEPasses) * sh.RT * sh.KB * 1024 + 3 * (size_t)sh.Npad * 4;
   }
   if (p->tile_config < 0 || p->tile_config > 5) return fail(DMALA_ERR_ARG, "tile_config must be in [0, 5]");
   if (p->wg_chain_blocks != 0 && p->wg_chain_blocks != 1 && p->wg_chain_blocks != 2 && p->wg_chain_blocks != 4)
@@ -92,6 +101,11 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
   pl.am = p->alpha_mult > 0 ? p->alpha_mult : 1.0;
   pl.bm = p->beta_mult > 0 ? p->beta_mult : 1.0;
   pl.gm = p->gamma_mult > 0 ? p->gamma_mult : 1.0;
+  pl.mix_thr = 0;
+  if (lrn) {
+    const double t = std::ceil(p->mix_eps * 16777216.0);
+    pl.mix_thr = (uint32_t)(t < 0 ? 0 : (t > 16777216.0 ? 16777216.0 : t));
+  }
   return DMALA_OK;
 }
 
@@ -142,7 +156,10 @@ dmala_status enqueue(const void* H, const void* y, const void* sigma2, int32_t n
     ka.final_state = out->final_state; ka.accept_count = out->accept_count;
     ka.trace_accept = out->trace_accept; ka.trace_hash = out->trace_hash;
     ka.trace_words = (sh.T + 31) / 32;
+    ka.train_rows = out->train_rows;
   }
+  ka.mlp = sh.lrn ? p->mlp_weights : nullptr;
+  ka.mix_thr = pl.mix_thr;
   mark(1);
   e = launch_sampler(sh, ka, eval, stream);
   if (e != hipSuccess) return hip_fail(e, "sampler launch");
@@ -174,6 +191,8 @@ dmala_status run(const void* H, const void* y, const void* sigma2, int32_t n_ins
   if (!ws) return fail(DMALA_ERR_WORKSPACE, "workspace is NULL");
   if (ws_bytes < pl.total) return fail(DMALA_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, pl.total);
   if (((uintptr_t)ws & 255) != 0) return fail(DMALA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (out && out->train_rows && (pl.naive || pl.sh.fp64))
+    return fail(DMALA_ERR_UNSUPPORTED, "train_rows needs the PRECOND or LEARNED proposal without DMALA_FP64");
   return enqueue(H, y, sigma2, n_inst, pl, p, out, nullptr, (unsigned char*)ws, x_from, x_to, eval_out, stream);
 }
 

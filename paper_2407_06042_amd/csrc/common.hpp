@@ -44,6 +44,10 @@ struct InstParams {
 static_assert(sizeof(InstParams) <= 256, "params block");
 constexpr int kParamBytes = 256;
 
+// Floats per exported training row: 7 network features, the plain centre (Re, Im),
+// the plain precision (natural-log units), Q, 0.
+constexpr int kTrainRow = 12;
+
 // Packing modes of the proposal matrix in the MFMA path.
 enum PMode : int { PM_NAIVE = 0, PM_F16X2 = 1, PM_F16X1 = 2, PM_BF16X1 = 3 };
 constexpr int kEPasses = 3;  // energy matrix: hi/mid/lo fp16 split
@@ -58,6 +62,7 @@ struct Shape {
   int win;         // proposal window half-width (0 = all levels), see the sampler
   int cfg;         // sampler work layout (see sampler_impl.hpp launch_rt)
   int cbw;         // 16-chain blocks per workgroup for the one-wave layouts (1, 2 or 4)
+  int lrn;         // 1: plain/learned kernel mixture (learned proposal network in the sampler)
   size_t inst_bytes;   // per-instance setup block
   size_t frag_bytes;   // MFMA fragments (MFMA path)
   size_t state_bytes;  // per-instance sampler->estimator block
@@ -126,6 +131,10 @@ struct SamplerArgs {
   int frag_bytes;
   int8_t* final_state; int32_t* accept_count; uint32_t* trace_accept; uint32_t* trace_hash;
   int trace_words;
+  // learned-proposal mixture and training-row export
+  const float* mlp;       // network parameters (flat float32, see mlp_device.hpp)
+  uint32_t mix_thr;       // plain kernel iff the 24-bit mixture uniform < mix_thr (= ceil(eps 2^24))
+  float* train_rows;      // [sum Nt][n_chains] rows of kTrainRow floats at the final state
   // debug-eval mode
   const int8_t* x_from; const int8_t* x_to; double* eval_out;
 };

@@ -15,6 +15,7 @@ struct Plan {
   size_t inst_off, state_off, wscratch_off, total;
   double tau, am, bm, gm;
   bool naive;
+  uint32_t mix_thr;   // learned mixture: plain kernel iff the 24-bit uniform < mix_thr
 };
 
 extern thread_local std::string g_err;

@@ -1,0 +1,143 @@
+// The learned proposal's per-antenna network on MFMA (device side).
+//
+// Network: 8 inputs (7 features and a constant 1 that carries the first
+// layer's bias) -> 64 -> 64 -> 4, ReLU after both hidden layers.  Inference
+// precision: parameters, inputs and hidden activations rounded to bfloat16,
+// products summed in fp32 by v_mfma_f32_16x16x32_bf16, second and third layer
+// biases added in fp32 (their bf16-rounded values).
+//
+// Lane layout.  A wavefront evaluates the network for 16 columns (chains) x 4
+// rows of antennas at once: lane l = 16 h + c holds the 8 inputs of "its"
+// antenna a_h for column c, and receives that antenna's 4 outputs.  No data
+// moves between lanes:
+//   * layer 1 for the antenna of lane group g is one MFMA per 16 hidden units
+//     whose A operand (W1) is non-zero only in the K slice 8g..8g+7 -- exactly
+//     the inputs that group g supplies in its B registers;
+//   * layers 2 and 3 take their B operand from the lane's own accumulator
+//     registers; the K order of the packed weights follows the accumulator
+//     layout (lane group h holds hidden units 16 t + 4 h + i);
+//   * the output layer of antenna a_g writes rows 4g..4g+3 of one shared
+//     accumulator tile, so lane group g ends up with the outputs of a_g.
+// 56 MFMAs per 4 x 16 network evaluations.
+#pragma once
+#include "common.hpp"
+
+namespace dmala {
+
+typedef __bf16 mlp_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float mlp_f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMlpIn = 7;
+constexpr int kMlpHid = 64;
+constexpr int kMlpOut = 4;
+constexpr int kMlpParams = kMlpHid * kMlpIn + kMlpHid + kMlpHid * kMlpHid + kMlpHid + kMlpOut * kMlpHid + kMlpOut;
+// offsets of the parameter blocks in the flat float32 array
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kMlpHid * kMlpIn;
+constexpr int kOffW2 = kOffB1 + kMlpHid;
+constexpr int kOffB2 = kOffW2 + kMlpHid * kMlpHid;
+constexpr int kOffW3 = kOffB2 + kMlpHid;
+constexpr int kOffB3 = kOffW3 + kMlpOut * kMlpHid;
+// LDS image: W1 fragments [4], W2 fragments [4 out tiles][2 K steps], W3 fragments [2], b2 [64], b3 [4]
+constexpr int kMlpFragW1 = 0;
+constexpr int kMlpFragW2 = 4;
+constexpr int kMlpFragW3 = 12;
+constexpr int kMlpFrags = 14;
+constexpr size_t kMlpLdsBytes = (size_t)kMlpFrags * 1024 + 64 * 4 + 4 * 4;
+
+// Hidden unit that K element j of lane group h feeds in K step s (layers 2, 3).
+__device__ __forceinline__ int mlp_kidx(int s, int h, int j) { return 16 * (2 * s + (j >> 2)) + 4 * h + (j & 3); }
+
+__device__ __forceinline__ float bf16_round(float v) { return (float)(__bf16)v; }
+
+// Build the LDS image of the network from the flat float32 parameters (all
+// threads of the block take part; the caller synchronises afterwards).
+__device__ inline void mlp_stage(const float* __restrict__ w, unsigned char* lds) {
+  for (int it = threadIdx.x; it < kMlpFrags * 64; it += blockDim.x) {
+    const int f = it >> 6, l = it & 63, r = l & 15, h = l >> 4;
+    mlp_bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      float x;
+      if (f < kMlpFragW2) {
+        const int u = 16 * f + r;
+        x = j < kMlpIn ? w[kOffW1 + u * kMlpIn + j] : w[kOffB1 + u];
+      } else if (f < kMlpFragW3) {
+        const int ot = (f - kMlpFragW2) >> 1, s = (f - kMlpFragW2) & 1;
+        x = w[kOffW2 + (16 * ot + r) * kMlpHid + mlp_kidx(s, h, j)];
+      } else {
+        const int s = f - kMlpFragW3;
+        x = w[kOffW3 + (r & 3) * kMlpHid + mlp_kidx(s, h, j)];
+      }
+      v[j] = (__bf16)x;
+    }
+    *(mlp_bf16x8*)(lds + (size_t)f * 1024 + l * 16) = v;
+  }
+  float* bias = (float*)(lds + (size_t)kMlpFrags * 1024);
+  for (int i = threadIdx.x; i < 64 + 4; i += blockDim.x)
+    bias[i] = bf16_round(i < 64 ? w[kOffB2 + i] : w[kOffB3 + i - 64]);
+}
+
+// Inputs of one antenna for this lane (7 features and the constant 1), rounded to bf16.
+__device__ __forceinline__ mlp_bf16x8 mlp_inputs(float f0, float f1, float f2, float f3, float f4, float f5, float f6) {
+  mlp_bf16x8 x;
+  x[0] = (__bf16)f0; x[1] = (__bf16)f1; x[2] = (__bf16)f2; x[3] = (__bf16)f3;
+  x[4] = (__bf16)f4; x[5] = (__bf16)f5; x[6] = (__bf16)f6; x[7] = (__bf16)1.0f;
+  return x;
+}
+
+// Evaluate the network for the 4 antennas x 16 columns held by the wave; the
+// lane receives the 4 outputs of its own antenna.  All 64 lanes must call it.
+// `lds_off` must be an LDS byte offset hidden from the optimiser (so that the
+// fragments are reloaded per call instead of being pinned in registers).
+__device__ __forceinline__ mlp_f32x4 mlp_eval4(const unsigned char* lds, uint32_t lds_off, mlp_bf16x8 x) {
+  const int lane = threadIdx.x & 63, h = lane >> 4, r = lane & 15;
+  const unsigned char* base = lds + lds_off + (uint32_t)lane * 16;
+  const float* bias = (const float*)(lds + lds_off + (size_t)kMlpFrags * 1024);
+  mlp_bf16x8 w1[4], w2[4][2], w3[2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) w1[t] = *(const mlp_bf16x8*)(base + (kMlpFragW1 + t) * 1024);
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) w2[t][s] = *(const mlp_bf16x8*)(base + (kMlpFragW2 + 2 * t + s) * 1024);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) w3[s] = *(const mlp_bf16x8*)(base + (kMlpFragW3 + s) * 1024);
+  mlp_f32x4 b2[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) b2[t] = *(const mlp_f32x4*)(bias + 16 * t + 4 * h);
+  mlp_f32x4 out = *(const mlp_f32x4*)(bias + 64);
+  const mlp_bf16x8 zero8 = {};
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    mlp_f32x4 z1[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const mlp_f32x4 c0 = {0.f, 0.f, 0.f, 0.f};
+      z1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h == g ? w1[t] : zero8, x, c0, 0, 0, 0);
+    }
+    mlp_bf16x8 a1[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a1[s][j] = (__bf16)fmaxf(z1[2 * s + (j >> 2)][j & 3], 0.0f);
+    mlp_f32x4 z2[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      z2[t] = b2[t];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) z2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[t][s], a1[s], z2[t], 0, 0, 0);
+    }
+    mlp_bf16x8 a2[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a2[s][j] = (__bf16)fmaxf(z2[2 * s + (j >> 2)][j & 3], 0.0f);
+    const bool mine = (r >> 2) == g;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mine ? w3[s] : zero8, a2[s], out, 0, 0, 0);
+  }
+  return out;
+}
+
+}  // namespace dmala

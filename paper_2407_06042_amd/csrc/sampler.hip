@@ -11,6 +11,9 @@ hipError_t launch_sampler_naive(const Shape&, const SamplerArgs&, bool, hipStrea
 hipError_t launch_sampler_f16x2(const Shape&, const SamplerArgs&, bool, hipStream_t);
 hipError_t launch_sampler_f16x1(const Shape&, const SamplerArgs&, bool, hipStream_t);
 hipError_t launch_sampler_bf16x1(const Shape&, const SamplerArgs&, bool, hipStream_t);
+hipError_t launch_sampler_lrn_f16x2(const Shape&, const SamplerArgs&, bool, hipStream_t);
+hipError_t launch_sampler_lrn_f16x1(const Shape&, const SamplerArgs&, bool, hipStream_t);
+hipError_t launch_sampler_lrn_bf16x1(const Shape&, const SamplerArgs&, bool, hipStream_t);
 
 size_t sampler_lds_bytes(const Shape& sh) {
   if (sh.fp64) {
@@ -31,6 +34,7 @@ size_t sampler_lds_bytes(const Shape& sh) {
 bool sampler_cfg_valid(const Shape& sh, int cfg) {
   static const int rt_of[5] = {2, 4, 8, 8, 16};
   if (cfg < 0 || cfg > 4 || rt_of[cfg] != sh.RT) return false;
+  if (sh.lrn && cfg == 2) return false;  // the learned variant keeps at most 4 row tiles per wave
   Shape t = sh;
   t.cfg = cfg;
   return sampler_lds_bytes(t) <= 160 * 1024;
@@ -40,7 +44,7 @@ int sampler_default_cfg(const Shape& sh) {
   switch (sh.RT) {
     case 2: return 0;
     case 4: return 1;
-    case 8: return sampler_cfg_valid(sh, 2) ? 2 : 3;
+    case 8: return !sh.lrn && sampler_cfg_valid(sh, 2) ? 2 : 3;
     case 16: return 4;
   }
   return -1;
@@ -48,6 +52,14 @@ int sampler_default_cfg(const Shape& sh) {
 
 hipError_t launch_sampler(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
   if (sh.fp64) return sh.pm == PM_NAIVE ? launch_sampler_f64_naive(sh, a, eval, s) : launch_sampler_f64_pre(sh, a, eval, s);
+  if (sh.lrn) {
+    switch (sh.pm) {
+      case PM_F16X2: return launch_sampler_lrn_f16x2(sh, a, eval, s);
+      case PM_F16X1: return launch_sampler_lrn_f16x1(sh, a, eval, s);
+      case PM_BF16X1: return launch_sampler_lrn_bf16x1(sh, a, eval, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (sh.pm) {
     case PM_NAIVE: return launch_sampler_naive(sh, a, eval, s);
     case PM_F16X2: return launch_sampler_f16x2(sh, a, eval, s);

@@ -19,10 +19,22 @@
 //   5. select, energy bookkeeping for the minimum-residual hard decision.
 // The float64 path keeps the same structure with dense double matrices in LDS
 // and VALU dot products instead of MFMA.
+//
+// Learned variant (LRN = 1).  Every transition of every chain uses the plain
+// preconditioned kernel with probability eps and otherwise the learned kernel,
+// whose proposal is the same discretised Gaussian with the centre and the
+// precision of each dimension set by the per-antenna network of
+// mlp_device.hpp (features of the antenna at the current state).  Each kernel
+// is a complete MH step with its own forward and reverse proposal; the choice
+// comes from the chain's random stream (low bytes of words 4, 5, 6), not from
+// the state, so the mixture keeps pi_a invariant.  The network runs at every
+// proposed state (its output becomes the cached learned proposal when the
+// move is accepted), and all Q levels are weighted directly (no window).
 #pragma once
 #include <type_traits>
 
 #include "common.hpp"
+#include "mlp_device.hpp"
 
 namespace dmala {
 
@@ -142,6 +154,27 @@ __device__ __forceinline__ int draw_level(R mu, R kL, const R (&c)[W + 1], R u) 
   }
 }
 
+// Inverse-CDF draw over all Q levels that also returns the log2 normaliser
+// (the same arithmetic as log2_norm<Q, 0, .>).
+template <int Q>
+__device__ __forceinline__ int draw_level_lz(float mu, float kL, float u, float& lz) {
+  float e[Q], base;
+  level_weights<Q>(mu, kL, e, base);
+  float Z = 0.f;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) Z += e[j];
+  const float target = u * Z;
+  float cum = 0.f;
+  int cnt = 0;
+#pragma unroll
+  for (int j = 0; j < Q - 1; ++j) {
+    cum += e[j];
+    cnt += (cum <= target) ? 1 : 0;
+  }
+  lz = lg2(Z) - kL * base;
+  return cnt;
+}
+
 // An opaque zero: added to LDS offsets inside the loop so that the optimiser
 // cannot hoist the loop-invariant A-operand fragment loads out of the loop
 // (that would pin every fragment in registers and halve the occupancy).
@@ -168,10 +201,11 @@ struct Red {
 // chain block splitting the dimensions (RT = RTW * WD tiles in all), MG = the
 // packed matrices are read from the instance block in global memory (L2) instead
 // of being staged in LDS.
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN>
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int LRN>
 __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
   constexpr bool F64 = std::is_same<Real, double>::value;
   static_assert(!F64 || (WD == 1 && !MG), "the float64 path uses one wave per chain block and LDS matrices");
+  static_assert(!LRN || (!F64 && PM != PM_NAIVE && WIN == 0 && RTW <= 4), "learned variant: float, preconditioned, no window");
   static_assert(WD == 1 || RTW % 2 == 0, "dimension-split waves own whole K blocks");
   constexpr int RT = RTW * WD;
   constexpr int D = 4 * RTW;
@@ -204,9 +238,11 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
   for (size_t o = threadIdx.x * 16; o < staged; o += blockDim.x * 16)
     *(uint4*)(smem + o) = *(const uint4*)(blk + kParamBytes + o);
   const InstParams ip = *(const InstParams*)blk;
-  __syncthreads();
   unsigned char* xbuf = smem + ((staged + 15) & ~(size_t)15);      // 2 x KB x 1 KiB (WD > 1)
   Red* rbuf = (Red*)(xbuf + (WD > 1 ? 2 * KB * 1024 : 0));          // 2 x WD x 16
+  unsigned char* mlp_lds = (unsigned char*)(rbuf + (WD > 1 ? 2 * WD * 16 : 0));   // network image (LRN)
+  if constexpr (LRN) mlp_stage(a.mlp, mlp_lds);
+  __syncthreads();
 
   const Real kL = (Real)ip.kL;
   const Real rho = (Real)ip.rho;
@@ -231,6 +267,8 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
     else pbv = (const Real*)(blk + kParamBytes + mat_bytes);
     ezv = pbv + Npad;
   }
+  // per-antenna network features (dimension 2m: LS variance, 2m+1: conditional variance)
+  const float* afv = (const float*)ezv + Npad;
 
   auto dim_of = [&](int d) { return 16 * (rt0 + (d >> 2)) + 4 * h + (d & 3); };
   int xphase = 0, rphase = 0;
@@ -344,8 +382,8 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
     }
   };
 
-  // Proposal parameters and energy gradient at state k from the contraction.
-  auto proposal_at = [&](const int (&k)[D], Real (&mu)[D], Real (&lz)[D], Real (&eg)[D]) {
+  // Proposal centre and energy gradient at state k from the contraction.
+  auto grad_at = [&](const int (&k)[D], Real (&mu)[D], Real (&eg)[D]) {
     Real accP[D], accE[D];
     contract(k, accP, accE);
 #pragma unroll
@@ -357,8 +395,71 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
       else shift = accP[d] * sP - pbv[n];
       eg[d] = g;
       mu[d] = Real(k[d]) - shift;
-      lz[d] = log2_norm<Q, WIN, W>(mu[d], kL, cw);
     }
+  };
+  // ... and the log2 normalisers.
+  auto proposal_at = [&](const int (&k)[D], Real (&mu)[D], Real (&lz)[D], Real (&eg)[D]) {
+    grad_at(k, mu, eg);
+#pragma unroll
+    for (int d = 0; d < D; ++d) lz[d] = log2_norm<Q, WIN, W>(mu[d], kL, cw);
+  };
+
+  // Network features of the lane's antenna in slot (rt, i2) at state k with plain centre mu.
+  constexpr float kCq = 0.5f * (Q - 1), kIhq = 2.0f / Q;
+  const float lq4 = 0.25f * (Q == 2 ? 1.f : Q == 4 ? 2.f : Q == 8 ? 3.f : 4.f);
+  auto feats = [&](const int (&k)[D], const Real (&m)[D], int rt, int i2, float (&f)[kMlpIn]) {
+    const int d0 = rt * 4 + 2 * i2;
+    const int n0 = dim_of(d0);
+    f[0] = ((float)m[d0] - kCq) * kIhq;
+    f[1] = ((float)m[d0 + 1] - kCq) * kIhq;
+    f[2] = ((float)k[d0] - kCq) * kIhq;
+    f[3] = ((float)k[d0 + 1] - kCq) * kIhq;
+    f[4] = afv[n0];
+    f[5] = afv[n0 + 1];
+    f[6] = lq4;
+  };
+  // Learned proposal (centre muL, log2 precision kLL) at state k with plain centre m.
+  auto learned_at = [&](const int (&k)[D], const Real (&m)[D], Real (&muL)[D], Real (&kLL)[D]) {
+    const uint32_t mo = opaque_zero();
+#pragma unroll
+    for (int rt = 0; rt < RTW; ++rt)
+#pragma unroll
+      for (int i2 = 0; i2 < 2; ++i2) {
+        float f[kMlpIn];
+        feats(k, m, rt, i2, f);
+        const mlp_f32x4 o = mlp_eval4(mlp_lds, mo, mlp_inputs(f[0], f[1], f[2], f[3], f[4], f[5], f[6]));
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const int d = rt * 4 + 2 * i2 + p;
+          const float b = fminf(fmaxf(o[2 + p], -4.0f), 4.0f);
+          muL[d] = m[d] + o[p];
+          kLL[d] = kL * ex2(b);
+        }
+      }
+  };
+  // Training rows (features, plain centre, natural-log precision, Q) of the lane's antennas at k.
+  auto write_rows = [&](const int (&k)[D], const Real (&m)[D]) {
+    const int Nt = N >> 1;
+    const int64_t sym0 = a.desc ? a.desc[inst].sym_off : (int64_t)inst * Nt;
+#pragma unroll
+    for (int rt = 0; rt < RTW; ++rt)
+#pragma unroll
+      for (int i2 = 0; i2 < 2; ++i2) {
+        const int d0 = rt * 4 + 2 * i2;
+        const int ant = dim_of(d0) >> 1;
+        if (ant < Nt) {
+          float f[kMlpIn];
+          feats(k, m, rt, i2, f);
+          float* row = a.train_rows + ((size_t)sym0 * a.C + (size_t)chain * Nt + ant) * kTrainRow;
+#pragma unroll
+          for (int i = 0; i < kMlpIn; ++i) row[i] = f[i];
+          row[7] = (float)m[d0];
+          row[8] = (float)m[d0 + 1];
+          row[9] = (float)(kL / Real(kLog2e));
+          row[10] = (float)Q;
+          row[11] = 0.f;
+        }
+      }
   };
 
   // log2 q_n(j | .) for a level j given the cached mode and normaliser
@@ -383,20 +484,36 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
       kc[d] = (live && valid[d]) ? (int)a.x_from[row + n] : 0;
       kt[d] = (live && valid[d]) ? (int)a.x_to[row + n] : 0;
     }
-    proposal_at(kc, mu, lz, eg);
-    Real lqf = 0;
-#pragma unroll
-    for (int d = 0; d < D; ++d)
-      if (valid[d]) lqf += lq(kt[d], mu[d], lz[d]);
+    Real lqf = 0, lqr = 0, T2 = 0;
     Real mup[D], lzp[D], egp[D];
-    proposal_at(kt, mup, lzp, egp);
-    Real lqr = 0, T2 = 0;
+    if constexpr (LRN) {
+      // the learned kernel alone (the mixture's other component is the plain kernel)
+      Real muL[D], kLL[D], muLp[D], kLLp[D];
+      grad_at(kc, mu, eg);
+      learned_at(kc, mu, muL, kLL);
+      grad_at(kt, mup, egp);
+      learned_at(kt, mup, muLp, kLLp);
 #pragma unroll
-    for (int d = 0; d < D; ++d)
-      if (valid[d]) {
-        lqr += lq(kc[d], mup[d], lzp[d]);
-        T2 -= Real(kt[d] - kc[d]) * (eg[d] + egp[d]);
-      }
+      for (int d = 0; d < D; ++d)
+        if (valid[d]) {
+          const Real tf = Real(kt[d]) - muL[d], tr = Real(kc[d]) - muLp[d];
+          lqf += -kLL[d] * tf * tf - log2_norm<Q, 0, W>(muL[d], kLL[d], cw);
+          lqr += -kLLp[d] * tr * tr - log2_norm<Q, 0, W>(muLp[d], kLLp[d], cw);
+          T2 -= Real(kt[d] - kc[d]) * (eg[d] + egp[d]);
+        }
+    } else {
+      proposal_at(kc, mu, lz, eg);
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+        if (valid[d]) lqf += lq(kt[d], mu[d], lz[d]);
+      proposal_at(kt, mup, lzp, egp);
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+        if (valid[d]) {
+          lqr += lq(kc[d], mup[d], lzp[d]);
+          T2 -= Real(kt[d] - kc[d]) * (eg[d] + egp[d]);
+        }
+    }
     if constexpr (WD > 1) {
       const Red r = chain_sum(Red{(float)lqf, (float)lqr, (float)T2, 0u});
       lqf = r.x; lqr = r.y; T2 = r.z;
@@ -422,7 +539,13 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) kc[rt * 4 + i] = (int)(((uint64_t)(c[i] >> 8) * Q) >> 24);
     }
-    proposal_at(kc, mu, lz, eg);
+    Real muL[D], kLL[D];  // cached learned proposal (LRN)
+    if constexpr (LRN) {
+      grad_at(kc, mu, eg);
+      learned_at(kc, mu, muL, kLL);
+    } else {
+      proposal_at(kc, mu, lz, eg);
+    }
     // E(x) = ||y||^2 + x^T g - z^T x = ||y||^2 + (eunit/2) sum_n lv_n (eg_n - ez_n)
     Real ep = 0;
 #pragma unroll
@@ -450,6 +573,15 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
         w[rt][0] = (uint32_t)(4 * (rt0 + rt) + h); w[rt][1] = (uint32_t)t; w[rt][2] = (uint32_t)chain; w[rt][3] = rid;
         philox4x32_10(w[rt], key0, key1);
       }
+      // kernel choice of the mixture (LRN): learned unless the uniform from the
+      // low bytes of words 4, 5, 6 falls below eps; every lane of the chain
+      // regenerates block 1 of the stream, so no lane has to broadcast it
+      bool useL = false;
+      if constexpr (LRN) {
+        uint32_t wm[4] = {1u, (uint32_t)t, (uint32_t)chain, rid};
+        philox4x32_10(wm, key0, key1);
+        useL = low_bytes24(wm[0], wm[1], wm[2]) >= a.mix_thr;
+      }
       // 1. draw x' (padding dimensions never move) and -log q(x'|x)
       int kp[D];
       Real S = 0;
@@ -458,20 +590,43 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
         Real u;
         if constexpr (F64) u = u24d(w[d >> 2][d & 3]);
         else u = u24f(w[d >> 2][d & 3]);
-        const int kd = draw_level<Q, WIN, W>(mu[d], kL, cw, u);
-        kp[d] = valid[d] ? kd : kc[d];
-        S -= lq(kp[d], mu[d], lz[d]);
+        if constexpr (LRN) {
+          const float ms = useL ? muL[d] : mu[d], ks = useL ? kLL[d] : (float)kL;
+          float lzf;
+          const int kd = draw_level_lz<Q>(ms, ks, u, lzf);
+          kp[d] = valid[d] ? kd : kc[d];
+          const float t0 = float(kp[d]) - ms;
+          S -= valid[d] ? (-ks * t0 * t0 - lzf) : 0.f;
+        } else {
+          const int kd = draw_level<Q, WIN, W>(mu[d], kL, cw, u);
+          kp[d] = valid[d] ? kd : kc[d];
+          S -= lq(kp[d], mu[d], lz[d]);
+        }
       }
       // 2-3. gradient at x', proposal at x', + log q(x|x'), energy term.
       // A padding dimension contributes exactly zero: its contraction rows are
       // zero, so mu' = mu, lz' = lz and the two log q terms cancel.
       Real mup[D], lzp[D], egp[D];
-      proposal_at(kp, mup, lzp, egp);
+      Real muLp[D], kLLp[D];
       Real T2 = 0;
+      if constexpr (LRN) {
+        grad_at(kp, mup, egp);
+        learned_at(kp, mup, muLp, kLLp);
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        S += lq(kc[d], mup[d], lzp[d]);
-        T2 -= Real(kp[d] - kc[d]) * (eg[d] + egp[d]);
+        for (int d = 0; d < D; ++d) {
+          const float mr = useL ? muLp[d] : mup[d], kr = useL ? kLLp[d] : (float)kL;
+          const float lzr = log2_norm<Q, 0, W>(mr, kr, cw);
+          const float t0 = float(kc[d]) - mr;
+          S += valid[d] ? (-kr * t0 * t0 - lzr) : 0.f;
+          T2 -= Real(kp[d] - kc[d]) * (eg[d] + egp[d]);
+        }
+      } else {
+        proposal_at(kp, mup, lzp, egp);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          S += lq(kc[d], mup[d], lzp[d]);
+          T2 -= Real(kp[d] - kc[d]) * (eg[d] + egp[d]);
+        }
       }
       S += T2;
       // 4. MH: accept iff  log ratio > log u  (eq. acc_prob: A > u); the MH word
@@ -496,8 +651,13 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
       for (int d = 0; d < D; ++d) {
         kc[d] = acc ? kp[d] : kc[d];
         mu[d] = acc ? mup[d] : mu[d];
-        lz[d] = acc ? lzp[d] : lz[d];
         eg[d] = acc ? egp[d] : eg[d];
+        if constexpr (LRN) {
+          muL[d] = acc ? muLp[d] : muL[d];
+          kLL[d] = acc ? kLLp[d] : kLL[d];
+        } else {
+          lz[d] = acc ? lzp[d] : lz[d];
+        }
       }
       E = acc ? E - T2 * eunit : E;
       nacc += acc ? 1 : 0;
@@ -529,6 +689,9 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
     }
 
     // results for the estimator and the optional outputs
+    if constexpr (!F64 && PM != PM_NAIVE) {
+      if (a.train_rows && live) write_rows(kc, mu);
+    }
     if (live) {
       const StateOff so = state_offsets(a.Cpad, Npad);
       unsigned char* st = a.ws_state + (size_t)inst * a.state_stride;
@@ -561,10 +724,11 @@ inline size_t sampler_cfg_lds(const Shape& sh, int rtw, int wd, bool mg, int wav
   size_t staged = mg ? 0 : (RT <= 4 ? sh.frag_bytes : mat);
   staged = (staged + 15) & ~(size_t)15;
   if (wd > 1) staged += 2 * (size_t)KB * 1024 + 2 * (size_t)wd * 16 * sizeof(Red);
+  if (sh.lrn) staged += kMlpLdsBytes;
   return staged;
 }
 
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, int WIN>
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, int WIN, int LRN = 0>
 hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
   const int chain_blocks = sh.Cpad / 16;
   int waves, gy;
@@ -576,7 +740,7 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
   }
   const dim3 grid(a.n_inst, gy);
   const size_t lds = sampler_cfg_lds(sh, RTW, WD, MG, waves);
-  auto k = eval ? sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN> : sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN>;
+  auto k = eval ? sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN, LRN> : sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -619,6 +783,29 @@ hipError_t launch_rt(const Shape& sh, const SamplerArgs& a, bool eval, hipStream
     }
     return hipErrorInvalidValue;
   }
+}
+
+// Learned-mixture instances: layouts with at most 4 row tiles per wave (cfg 0, 1, 3, 4).
+template <int RTW, int WD, bool MG, int PM>
+hipError_t launch_q_lrn(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+  switch (sh.Q) {
+    case 2: return launch_t<float, RTW, WD, MG, 2, PM, 0, 1>(sh, a, eval, s);
+    case 4: return launch_t<float, RTW, WD, MG, 4, PM, 0, 1>(sh, a, eval, s);
+    case 8: return launch_t<float, RTW, WD, MG, 8, PM, 0, 1>(sh, a, eval, s);
+    case 16: return launch_t<float, RTW, WD, MG, 16, PM, 0, 1>(sh, a, eval, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int PM>
+hipError_t launch_rt_lrn(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+  switch (sh.cfg) {
+    case 0: return launch_q_lrn<2, 1, false, PM>(sh, a, eval, s);
+    case 1: return launch_q_lrn<4, 1, false, PM>(sh, a, eval, s);
+    case 3: return launch_q_lrn<4, 2, true, PM>(sh, a, eval, s);
+    case 4: return launch_q_lrn<4, 4, true, PM>(sh, a, eval, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace dmala

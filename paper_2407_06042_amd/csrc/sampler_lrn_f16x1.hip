@@ -1,0 +1,8 @@
+// Sampler instances: plain/learned kernel mixture, proposal mode PM_F16X1.
+#include "sampler_impl.hpp"
+
+namespace dmala {
+hipError_t launch_sampler_lrn_f16x1(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+  return launch_rt_lrn<PM_F16X1>(sh, a, eval, s);
+}
+}  // namespace dmala

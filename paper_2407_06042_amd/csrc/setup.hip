@@ -10,7 +10,11 @@
 // and writes, scaled to the index units of the sampler (see common.hpp),
 //   energy matrix  EG = 2 s^2 log2(e)/(tau sigma^2) * R(G),  ez = 2 s log2(e)/(tau sigma^2) * R(z)
 //   proposal matrix P = alpha/(2 tau sigma^2) * R(A),       pb = alpha/(2 tau sigma^2 s) * R(b)
-// where R(.) is the Re/Im-interleaved real-equivalent.  On the MFMA path each
+// where R(.) is the Re/Im-interleaved real-equivalent.  The MFMA path also
+// stores two per-antenna features of the learned proposal's network, in index
+// units (level step 2 s): af_{2m} = log2(sigma^2 M_mm / (8 s^2)) / 8 (variance
+// of the damped LS estimate) and af_{2m+1} = log2(sigma^2 / (8 s^2 G_mm)) / 8
+// (variance of one axis given the others).  On the MFMA path each
 // matrix is scaled by a power of two and split into fp16 (or bf16) terms laid
 // out as 16x16x32 MFMA A-operand fragments; on the float64 path it is stored
 // as a dense row-major array.
@@ -217,6 +221,11 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
     scaleE = pack_fragments(W, ld, cE, nt, N, a.RT, a.KB, kEPasses, 0, frag + (size_t)npP * a.RT * a.KB * 1024, red);
     float* ezf = (float*)(frag + (size_t)(npP + kEPasses) * a.RT * a.KB * 1024) + Npad;
     for (int n = tid; n < Npad; n += blockDim.x) ezf[n] = n < N ? (float)(cz * realeq_vec(z, n)) : 0.0f;
+    float* afv = ezf + Npad;
+    for (int n = tid; n < Npad; n += blockDim.x) {
+      const int m = n >> 1;
+      afv[n] = (n < N && (n & 1)) ? (float)(log2(sigma2 / (8.0 * s * s * W[m * ld + m].re)) / 8.0) : 0.0f;
+    }
   }
   __syncthreads();
 
@@ -256,6 +265,11 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
         if (j >= nt) { j -= nt; ++i; }
       }
       __syncthreads();
+    }
+    if (!a.fp64) {
+      float* afv = (float*)(frag + (size_t)(npP + kEPasses) * a.RT * a.KB * 1024) + 2 * Npad;
+      for (int m = tid; m < nt; m += blockDim.x)
+        afv[2 * m] = (float)(log2(sigma2 * W[m * ld + m].re / (8.0 * s * s)) / 8.0);
     }
     // b = M z, then W <- A = I - gamma M
     for (int m = tid; m < nt; m += blockDim.x) {

@@ -61,3 +61,52 @@ def test_detect_rejects_bad_workspace_before_launch():
     bad = (ctypes.c_float * 32)(*([0.5] * 32))
     st = L.dmala_detect(fake, fake, fake, 2, 4, 4, 16, bad, ctypes.byref(p), ctypes.byref(o), ctypes.c_void_p(0x10000), need, None)
     assert st == -2 and "constellation" in dm.last_error()
+
+
+def _lparams(**kw):
+    p = dm.make_params(16, 10, 1, proposal="learned")
+    p.mlp_weights = 0x2000
+    p.mix_eps = 0.1
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_learned_proposal_validation():
+    assert dm.workspace_size(2, 8, 8, 16, _lparams()) > 0
+    assert dm.workspace_size(2, 64, 64, 64, _lparams()) > 0            # 128 dims: layout 3
+    for kw, msg in [(dict(mlp_weights=None), "mlp_weights"), (dict(mix_eps=1.5), "mix_eps"),
+                    (dict(mix_eps=-0.1), "mix_eps"), (dict(precision=dm.FP64), "FP64")]:
+        with pytest.raises(dm.DmalaError) as e:
+            dm.workspace_size(2, 8, 8, 16, _lparams(**kw))
+        assert msg in str(e.value)
+    with pytest.raises(dm.DmalaError) as e:       # layout 2 (128 dims in one wave) is not built for it
+        dm.workspace_size(2, 64, 64, 64, _lparams(tile_config=3))
+    assert "tile_config" in str(e.value)
+
+
+def test_train_rows_need_the_preconditioned_proposal():
+    L = dm.lib()
+    p = dm.make_params(16, 10, 1, proposal="naive")
+    o = dm.Outputs()
+    o.train_rows = 0x3000
+    fake = ctypes.c_void_p(0x1000)
+    need = dm.workspace_size(2, 4, 4, 16, p)
+    st = L.dmala_detect(fake, fake, fake, 2, 4, 4, 16, None, ctypes.byref(p), ctypes.byref(o), ctypes.c_void_p(0x10000), need, None)
+    assert st == -2 and "train_rows" in dm.last_error()
+
+
+def test_mlp_entry_points_validate_on_the_host():
+    L = dm.lib()
+    f = ctypes.c_void_p(0x1000)
+    assert L.dmala_mlp_forward(f, f, 10, 5, f, None) == -1 and "row_stride" in dm.last_error()
+    assert L.dmala_mlp_forward(None, f, 10, 12, f, None) == -1
+    assert L.dmala_mlp_train_workspace_size(0) == 0
+    need = L.dmala_mlp_train_workspace_size(1000)
+    assert need >= 1000 * 4 * 64
+    ws = ctypes.c_void_p(0x10000)
+    assert L.dmala_mlp_train_step(f, f, f, 1, 1e-3, f, f, 0, None, None, ws, need, None) == -1
+    assert L.dmala_mlp_train_step(f, f, f, 0, 1e-3, f, f, 1000, None, None, ws, need, None) == -1
+    assert L.dmala_mlp_train_step(f, f, f, 1, -1.0, f, f, 1000, None, None, ws, need, None) == -1
+    assert L.dmala_mlp_train_step(f, f, f, 1, 1e-3, f, f, 1000, None, None, ws, need - 1, None) == -4
+    assert L.dmala_mlp_train_step(f, f, f, 1, 1e-3, f, f, 1000, None, None, ctypes.c_void_p(0x10010), need, None) == -4
