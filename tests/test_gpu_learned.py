@@ -233,3 +233,38 @@ def test_mixture_chains_follow_the_oracle(nt, M, eps):
     # float64 oracle; they are rare
     assert n_ok >= 0.9 * n_tot
     assert n_id >= 0.5 * n_tot
+
+
+def test_trained_network_gains_over_the_plain_kernel():
+    """Train on the method's own 32x32 64-QAM and 128x128 256-QAM chains, evaluate on 64x64 64-QAM at 20..26 dB:
+    the mixture with the trained network reaches a lower symbol error rate than the plain
+    kernel at the same number of transitions, and at 25 transitions a lower one than the
+    plain kernel at 50."""
+    import torch
+    import paper_2407_06042_amd as dm
+    from paper_2407_06042_amd import learned as L
+    b = W.c2_snr_sweep(n_per_snr=128, seed=202).as_precision(np.float32)
+    H, y, s2 = dm.device_inputs(b.H, b.y, b.sigma2)
+    rows, tg = L.collect(H, y, s2, 32, 32, 64, 32, [0, 5, 10, 20, 40, 80], 20, 11)
+    b4 = W.c4_correlated(n_inst=48, seed=204).as_precision(np.float32)
+    H4, y4, s4 = dm.device_inputs(b4.H, b4.y, b4.sigma2)
+    r4, t4 = L.collect(H4, y4, s4, 128, 128, 256, 32, [0, 10, 40], 20, 12)
+    rows, tg = torch.cat([rows, r4]), torch.cat([tg, t4])
+    w = L.init_weights(1)
+    hist = L.train(w, rows, tg, 400, batch=65536, lr=3e-3, lr_final=2e-4, log_every=50)
+    print("training rows", tuple(rows.shape), "loss", hist, flush=True)
+    assert hist[-1][1] < 0.5 * hist[0][1]
+    ev = W.c5_learned_eval(n_per_snr=128, seed=205).as_precision(np.float32)
+    He, ye, se = dm.device_inputs(ev.H, ev.y, ev.sigma2)
+    B = len(ev.sigma2)
+
+    def ser(T, prop):
+        kw = dict(mlp_weights=w, mix_eps=0.1) if prop == "learned" else {}
+        det = dm.Detector(B, 64, 64, 64, 32, T, 5, "bf16", prop, outputs=("symbols",), **kw)
+        sym = det(He, ye, se)["symbols"].cpu().numpy()
+        return float(np.mean(sym != ev.x_idx))
+
+    p25, p50, l25 = ser(25, "precond"), ser(50, "precond"), ser(25, "learned")
+    print("SER plain T=25 %.4f, plain T=50 %.4f, learned T=25 %.4f" % (p25, p50, l25), flush=True)
+    assert l25 < p25 - 0.015
+    assert l25 < p50
