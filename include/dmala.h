@@ -108,12 +108,14 @@ typedef struct {
                                 2: 128 dims, 1 wave / 16 chains, LDS
                                 3: 128 dims, 2 waves / 16 chains, matrices read from L2
                                 4: 256 dims, 4 waves / 16 chains, L2
+                                5: 64 dims, 2 waves / 16 chains, LDS   (LEARNED only)
+                                6: 128 dims, 4 waves / 16 chains, L2   (LEARNED only)
                                 (dims = 2 Nt rounded up to a power of two >= 32; a layout that does
                                 not match the shape returns DMALA_ERR_UNSUPPORTED) */
   int32_t wg_chain_blocks;   /* layouts 0-2: 16-chain blocks sharing one workgroup (and one LDS copy
                                 of the matrices): 0 = automatic (up to 4), or 1, 2, 4 */
   const float* mlp_weights;  /* LEARNED: device float32 [DMALA_MLP_PARAMS]; otherwise ignored.
-                                LEARNED excludes layout 2 (128 dims use layout 3) */
+                                LEARNED excludes layout 2; its defaults are layouts 0, 5, 6, 4 */
   double mix_eps;            /* LEARNED: probability of the PRECOND kernel per transition, in [0, 1] */
 } dmala_params;
 

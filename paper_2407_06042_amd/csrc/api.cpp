@@ -77,7 +77,7 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
     // fragments, then the vectors pb, ez and the per-antenna network features
     sh.frag_bytes = (size_t)(p_passes(sh.pm) + kEPasses) * sh.RT * sh.KB * 1024 + 3 * (size_t)sh.Npad * 4;
   }
-  if (p->tile_config < 0 || p->tile_config > 5) return fail(DMALA_ERR_ARG, "tile_config must be in [0, 5]");
+  if (p->tile_config < 0 || p->tile_config > 7) return fail(DMALA_ERR_ARG, "tile_config must be in [0, 7]");
   if (p->wg_chain_blocks != 0 && p->wg_chain_blocks != 1 && p->wg_chain_blocks != 2 && p->wg_chain_blocks != 4)
     return fail(DMALA_ERR_ARG, "wg_chain_blocks must be 0, 1, 2 or 4");
   sh.cbw = p->wg_chain_blocks ? p->wg_chain_blocks : 4;

@@ -50,6 +50,13 @@ __device__ __forceinline__ int mlp_kidx(int s, int h, int j) { return 16 * (2 * 
 
 __device__ __forceinline__ float bf16_round(float v) { return (float)(__bf16)v; }
 
+// An opaque zero offset (see the sampler's opaque_zero).
+__device__ __forceinline__ uint32_t opaque_zero_u32() {
+  uint32_t z = 0;
+  asm volatile("" : "+s"(z));
+  return z;
+}
+
 // Build the LDS image of the network from the flat float32 parameters (all
 // threads of the block take part; the caller synchronises afterwards).
 __device__ inline void mlp_stage(const float* __restrict__ w, unsigned char* lds) {
@@ -92,29 +99,20 @@ __device__ __forceinline__ mlp_bf16x8 mlp_inputs(float f0, float f1, float f2, f
 // fragments are reloaded per call instead of being pinned in registers).
 __device__ __forceinline__ mlp_f32x4 mlp_eval4(const unsigned char* lds, uint32_t lds_off, mlp_bf16x8 x) {
   const int lane = threadIdx.x & 63, h = lane >> 4, r = lane & 15;
-  const unsigned char* base = lds + lds_off + (uint32_t)lane * 16;
   const float* bias = (const float*)(lds + lds_off + (size_t)kMlpFrags * 1024);
-  mlp_bf16x8 w1[4], w2[4][2], w3[2];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) w1[t] = *(const mlp_bf16x8*)(base + (kMlpFragW1 + t) * 1024);
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int s = 0; s < 2; ++s) w2[t][s] = *(const mlp_bf16x8*)(base + (kMlpFragW2 + 2 * t + s) * 1024);
-#pragma unroll
-  for (int s = 0; s < 2; ++s) w3[s] = *(const mlp_bf16x8*)(base + (kMlpFragW3 + s) * 1024);
-  mlp_f32x4 b2[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) b2[t] = *(const mlp_f32x4*)(bias + 16 * t + 4 * h);
   mlp_f32x4 out = *(const mlp_f32x4*)(bias + 64);
   const mlp_bf16x8 zero8 = {};
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
+    // fragments are re-read for every antenna group (an opaque offset keeps the
+    // compiler from holding all 14 of them in registers across the groups)
+    const unsigned char* base = lds + lds_off + opaque_zero_u32() + (uint32_t)lane * 16;
     mlp_f32x4 z1[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const mlp_f32x4 c0 = {0.f, 0.f, 0.f, 0.f};
-      z1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h == g ? w1[t] : zero8, x, c0, 0, 0, 0);
+      const mlp_bf16x8 w1 = *(const mlp_bf16x8*)(base + (kMlpFragW1 + t) * 1024);
+      z1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h == g ? w1 : zero8, x, c0, 0, 0, 0);
     }
     mlp_bf16x8 a1[2];
 #pragma unroll
@@ -124,9 +122,12 @@ __device__ __forceinline__ mlp_f32x4 mlp_eval4(const unsigned char* lds, uint32_
     mlp_f32x4 z2[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      z2[t] = b2[t];
+      z2[t] = *(const mlp_f32x4*)(bias + 16 * t + 4 * h);
 #pragma unroll
-      for (int s = 0; s < 2; ++s) z2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[t][s], a1[s], z2[t], 0, 0, 0);
+      for (int s = 0; s < 2; ++s) {
+        const mlp_bf16x8 w2 = *(const mlp_bf16x8*)(base + (kMlpFragW2 + 2 * t + s) * 1024);
+        z2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2, a1[s], z2[t], 0, 0, 0);
+      }
     }
     mlp_bf16x8 a2[2];
 #pragma unroll
@@ -135,7 +136,10 @@ __device__ __forceinline__ mlp_f32x4 mlp_eval4(const unsigned char* lds, uint32_
       for (int j = 0; j < 8; ++j) a2[s][j] = (__bf16)fmaxf(z2[2 * s + (j >> 2)][j & 3], 0.0f);
     const bool mine = (r >> 2) == g;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mine ? w3[s] : zero8, a2[s], out, 0, 0, 0);
+    for (int s = 0; s < 2; ++s) {
+      const mlp_bf16x8 w3 = *(const mlp_bf16x8*)(base + (kMlpFragW3 + s) * 1024);
+      out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mine ? w3 : zero8, a2[s], out, 0, 0, 0);
+    }
   }
   return out;
 }

@@ -27,14 +27,17 @@ size_t sampler_lds_bytes(const Shape& sh) {
     case 2: return sampler_cfg_lds(sh, 8, 1, false, 4);
     case 3: return sampler_cfg_lds(sh, 4, 2, true, 2);
     case 4: return sampler_cfg_lds(sh, 4, 4, true, 4);
+    case 5: return sampler_cfg_lds(sh, 2, 2, false, 2);
+    case 6: return sampler_cfg_lds(sh, 2, 4, true, 4);
   }
   return ~(size_t)0;
 }
 
 bool sampler_cfg_valid(const Shape& sh, int cfg) {
-  static const int rt_of[5] = {2, 4, 8, 8, 16};
-  if (cfg < 0 || cfg > 4 || rt_of[cfg] != sh.RT) return false;
-  if (sh.lrn && cfg == 2) return false;  // the learned variant keeps at most 4 row tiles per wave
+  static const int rt_of[7] = {2, 4, 8, 8, 16, 4, 8};
+  if (cfg < 0 || cfg > 6 || rt_of[cfg] != sh.RT) return false;
+  if (sh.lrn && cfg == 2) return false;   // the learned variant keeps at most 4 row tiles per wave
+  if (!sh.lrn && cfg >= 5) return false;  // layouts 5, 6 are built for the learned variant only
   Shape t = sh;
   t.cfg = cfg;
   return sampler_lds_bytes(t) <= 160 * 1024;
@@ -43,8 +46,8 @@ bool sampler_cfg_valid(const Shape& sh, int cfg) {
 int sampler_default_cfg(const Shape& sh) {
   switch (sh.RT) {
     case 2: return 0;
-    case 4: return 1;
-    case 8: return !sh.lrn && sampler_cfg_valid(sh, 2) ? 2 : 3;
+    case 4: return sh.lrn ? 5 : 1;
+    case 8: return sh.lrn ? 6 : (sampler_cfg_valid(sh, 2) ? 2 : 3);
     case 16: return 4;
   }
   return -1;

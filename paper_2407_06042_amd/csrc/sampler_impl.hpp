@@ -202,7 +202,7 @@ struct Red {
 // packed matrices are read from the instance block in global memory (L2) instead
 // of being staged in LDS.
 template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int LRN>
-__global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
+__device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   constexpr bool F64 = std::is_same<Real, double>::value;
   static_assert(!F64 || (WD == 1 && !MG), "the float64 path uses one wave per chain block and LDS matrices");
   static_assert(!LRN || (!F64 && PM != PM_NAIVE && WIN == 0 && RTW <= 4), "learned variant: float, preconditioned, no window");
@@ -716,6 +716,18 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
   }
 }
 
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int LRN>
+__global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
+  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, LRN>(a);
+}
+
+// The same kernel held to two waves per SIMD (at most 256 registers): the
+// learned variant with two row tiles per wave fits without spilling.
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int LRN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sampler_kernel_w2(SamplerArgs a) {
+  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, LRN>(a);
+}
+
 // LDS bytes of a configuration.
 inline size_t sampler_cfg_lds(const Shape& sh, int rtw, int wd, bool mg, int waves) {
   if (sh.fp64) return sh.frag_bytes + (size_t)waves * 16 * sh.Npad * sizeof(double);
@@ -740,7 +752,11 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
   }
   const dim3 grid(a.n_inst, gy);
   const size_t lds = sampler_cfg_lds(sh, RTW, WD, MG, waves);
-  auto k = eval ? sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN, LRN> : sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>;
+  void (*k)(SamplerArgs);
+  if constexpr (LRN && RTW == 2)
+    k = eval ? sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, true, WIN, LRN> : sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>;
+  else
+    k = eval ? sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN, LRN> : sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -785,7 +801,9 @@ hipError_t launch_rt(const Shape& sh, const SamplerArgs& a, bool eval, hipStream
   }
 }
 
-// Learned-mixture instances: layouts with at most 4 row tiles per wave (cfg 0, 1, 3, 4).
+// Learned-mixture instances: layouts with at most 4 row tiles per wave (cfg 0, 1, 3, 4) and the
+// two-tile dimension splits 5 (64 dims, 2 waves, LDS matrices) and 6 (128 dims, 4 waves, L2), which
+// keep the network, the two cached proposals and the state within 256 registers.
 template <int RTW, int WD, bool MG, int PM>
 hipError_t launch_q_lrn(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
   switch (sh.Q) {
@@ -804,6 +822,8 @@ hipError_t launch_rt_lrn(const Shape& sh, const SamplerArgs& a, bool eval, hipSt
     case 1: return launch_q_lrn<4, 1, false, PM>(sh, a, eval, s);
     case 3: return launch_q_lrn<4, 2, true, PM>(sh, a, eval, s);
     case 4: return launch_q_lrn<4, 4, true, PM>(sh, a, eval, s);
+    case 5: return launch_q_lrn<2, 2, false, PM>(sh, a, eval, s);
+    case 6: return launch_q_lrn<2, 4, true, PM>(sh, a, eval, s);
   }
   return hipErrorInvalidValue;
 }

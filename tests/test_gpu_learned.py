@@ -179,12 +179,13 @@ def test_device_learned_kernel_is_reversible(nt, M):
     assert np.abs(LQp - LQo).max() > 20 * np.median(err)
 
 
-def _mixture_run(b, P, eps, C, T, seed, precision="fp32"):
+def _mixture_run(b, P, eps, C, T, seed, precision="fp32", tile_config=0):
     import torch
     import paper_2407_06042_amd as dm
     Hcm, y, s2 = dm.device_inputs(b.H, b.y, b.sigma2, precision)
     det = dm.Detector(len(b.sigma2), b.nt, b.nr, b.M, C, T, seed, precision, "learned",
-                      outputs=("final_state", "accept_count"), trace=True, mlp_weights=_dev(P), mix_eps=eps)
+                      outputs=("final_state", "accept_count"), trace=True, mlp_weights=_dev(P), mix_eps=eps,
+                      tile_config=tile_config)
     out = det(Hcm, y, s2)
     torch.cuda.synchronize()
     res = {k: v.cpu().numpy() for k, v in out.items()}
@@ -209,12 +210,16 @@ def test_zero_output_layer_mixture_is_the_plain_chain(nt, M, eps):
     assert n_id >= 0.8 * n_tot
 
 
-@pytest.mark.parametrize("nt,M,eps", [(2, 16, 0.3), (4, 64, 0.2), (8, 16, 0.5), (16, 64, 0.1)])
-def test_mixture_chains_follow_the_oracle(nt, M, eps):
+@pytest.mark.parametrize("nt,M,eps,tile", [(2, 16, 0.3, 0), (4, 64, 0.2, 0), (8, 16, 0.5, 0), (16, 64, 0.1, 0),
+                                           (24, 16, 0.2, 0), (24, 64, 0.3, 2), (40, 64, 0.2, 0), (40, 16, 0.2, 4),
+                                           (100, 64, 0.2, 0)])
+def test_mixture_chains_follow_the_oracle(nt, M, eps, tile):
+    """Default layouts 0, 5 (64 dims), 6 (128 dims), 4 (256 dims) and the explicit
+    four-tile layouts 1 (64 dims) and 3 (128 dims, matrices from L2)."""
     P = _params(7 + nt, scale=2.0)
     b = W.make_batch(nt, nt + 2, M, 15.0, 3, seed=50 + nt).as_precision(np.float32)
     C, T, seed = 16, 20, 4242
-    g = _mixture_run(b, P, eps, C, T, seed)
+    g = _mixture_run(b, P, eps, C, T, seed, tile_config=tile)
     n_ok = n_id = n_tot = 0
     used = 0.0
     for i in range(3):
