@@ -107,6 +107,11 @@ class HipEvents:
                 raise RuntimeError("hipEventCreate failed")
             self.ev.append(e.value)
 
+    def record(self, i):
+        import torch
+        if self.hip.hipEventRecord(ctypes.c_void_p(self.ev[i]), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)) != 0:
+            raise RuntimeError("hipEventRecord failed")
+
     def elapsed_ms(self, a, b):
         ms = ctypes.c_float()
         if self.hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(self.ev[a]), ctypes.c_void_p(self.ev[b])) != 0:
@@ -136,6 +141,66 @@ def run_form(dm, torch, b, precision, steps, warmup):
     ser = {str(s): float(err[k * 1024:(k + 1) * 1024].mean()) for k, s in enumerate(SNRS)}
     return dict(wall_ms=wall * 1e3 / steps, step_ms=float(np.mean(step_ms)), sampler_ms=float(np.mean(samp_ms)),
                 setup_ms=float(np.mean(setup_ms)), estimator_ms=float(np.mean(est_ms)), ser=ser)
+
+
+def learned_comparison(dm, torch, reps=3):
+    """64x64 64-QAM at 20..26 dB (2048 problems per SNR), 32 chains: symbol error rate and time of
+    the plain fp32 form, the BF16 form and the BF16 form with the learned proposal (mixture, eps 0.1)
+    over a sweep of transitions; the network is first trained on the GPU on the method's own
+    32x32 64-QAM and 128x128 256-QAM chains (training time reported separately)."""
+    from paper_2407_06042_amd import learned as L
+    ev0 = HipEvents(2)
+    hip_t0 = time.perf_counter()
+    ev0.record(0)
+    b = W.c2_snr_sweep(n_per_snr=128, seed=102).as_precision(np.float32)
+    H, y, s2 = dm.device_inputs(b.H, b.y, b.sigma2)
+    rows, tg = L.collect(H, y, s2, 32, 32, 64, 32, [0, 5, 10, 20, 40, 80], 20, 11)
+    b4 = W.c4_correlated(n_inst=48, seed=104).as_precision(np.float32)
+    H4, y4, s4 = dm.device_inputs(b4.H, b4.y, b4.sigma2)
+    r4, t4 = L.collect(H4, y4, s4, 128, 128, 256, 32, [0, 10, 40], 20, 12)
+    rows, tg = torch.cat([rows, r4]), torch.cat([tg, t4])
+    w = L.init_weights(1)
+    hist = L.train(w, rows, tg, 400, batch=65536, lr=3e-3, lr_final=2e-4, log_every=399)
+    ev0.record(1)
+    torch.cuda.synchronize()
+    train_ms = ev0.elapsed_ms(0, 1)
+    ev = W.c5_learned_eval().as_precision(np.float32)
+    He, ye, se = dm.device_inputs(ev.H, ev.y, ev.sigma2)
+    B = len(ev.sigma2)
+    runs = []
+    sweep = [("fp32", "precond", (25, 50, 100, 200)), ("bf16", "precond", (25, 50, 100, 200)),
+             ("bf16", "learned", (10, 25, 50, 100))]
+    for prec, prop, Ts in sweep:
+        for T in Ts:
+            kw = dict(mlp_weights=w, mix_eps=0.1) if prop == "learned" else {}
+            det = dm.Detector(B, 64, 64, 64, 32, T, SEED, prec, prop, outputs=("symbols", "accept_count"), **kw)
+            det(He, ye, se)
+            e = HipEvents(4 * reps)
+            for k in range(reps):
+                out = det(He, ye, se, events=e.ev[4 * k: 4 * k + 4])
+            torch.cuda.synchronize()
+            ms = float(np.mean([e.elapsed_ms(4 * k, 4 * k + 3) for k in range(reps)]))
+            sym = out["symbols"].cpu().numpy()
+            runs.append(dict(form=prec + ("+learned" if prop == "learned" else ""), T=T, ms=ms,
+                             ser=float(np.mean(sym != ev.x_idx)),
+                             accept=float(out["accept_count"].float().mean().item()) / T,
+                             chain_iters_per_s=B * 32 * T / (ms * 1e-3)))
+    ref = next(r for r in runs if r["form"] == "fp32" and r["T"] == 100)
+    matched = {}
+    for form in ("fp32", "bf16", "bf16+learned"):
+        ok = [r for r in runs if r["form"] == form and r["ser"] <= ref["ser"]]
+        if ok:
+            best = min(ok, key=lambda r: r["ms"])
+            matched[form] = dict(T=best["T"], ms=best["ms"], ser=best["ser"], speedup_vs_fp32_T100=ref["ms"] / best["ms"])
+        else:
+            matched[form] = None
+    return dict(workload="64x64 64-QAM i.i.d. Rayleigh CN(0,1/Nr), SNR 20:2:26 dB x 2048 (8192 problems), "
+                         "32 chains, swept transitions; learned = BF16 with the trained network, plain kernel "
+                         "with probability 0.1 per transition",
+                training=dict(ms=train_ms, rows=int(rows.shape[0]), steps=400, final_loss=hist[-1][1],
+                              data="32x32 64-QAM (896 problems) and 128x128 256-QAM rho=0.5 (48 problems) "
+                                   "chains, targets = the same chain 20 transitions later"),
+                runs=runs, reference="fp32 plain, 100 transitions", matched_ser=matched)
 
 
 def bench_uneven(args):
@@ -191,6 +256,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=("c2", "uneven"),
                     help="c2: the default 32x32 64-QAM sweep; uneven: 4096 mixed-shape problems in one plan")
     ap.add_argument("--autotune", default=None, help="uneven workload: autotune cache path (JSON)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the 64x64 64-QAM plain / BF16 / learned-proposal comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the detector has no multi-GPU path to time "
@@ -222,6 +289,8 @@ def main():
     res = {}
     for f in forms:
         res[f] = run_form(dm, torch, batch, f, args.steps, args.warmup)
+
+    learned = None if args.no_learned else learned_comparison(dm, torch)
 
     main_form = forms[0]
     r = res[main_form]
@@ -261,6 +330,7 @@ def main():
                      "gx_mfma_tflops": gx_flops_per_chain_iter(NT) * ci / (r["sampler_ms"] * 1e-3) / 1e12,
                      "ops_per_chain_iter": algorithmic_ops_per_chain_iter(NT, NR, M)},
         "cpu_baseline": cpu,
+        "learned_c5": learned,
         "forms": {f: {"chain_iters_per_s": ci / (res[f]["step_ms"] * 1e-3), "ms_per_step": res[f]["step_ms"],
                       "sampler_ms": res[f]["sampler_ms"], "ser": res[f]["ser"]} for f in forms},
     }
