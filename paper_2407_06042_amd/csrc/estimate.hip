@@ -52,6 +52,8 @@ __device__ __forceinline__ int ungray(int g) {
 }
 
 constexpr int kLlrPerThread = 4;  // bits per instance <= 128 antennas x 8 bits = 4 x 256 threads
+// Workgroups of 1024 threads serve instances with more than 256 (antenna, kI) rows: fewer row
+// blocks, so the chain chunks are staged (residuals, H^H r) fewer times, and 16 waves per CU.
 
 // Per (chain, antenna) values staged in LDS.
 template <typename R>
@@ -60,8 +62,8 @@ struct CM {
   int kI, kQ;
 };
 
-template <typename R, int Q, bool SH>
-__global__ __launch_bounds__(256) void estimate_kernel(EstArgs a) {
+template <typename R, int Q, bool SH, int BS>
+__global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
   constexpr int M = Q * Q;
   constexpr int NB = Q == 2 ? 1 : (Q == 4 ? 2 : (Q == 8 ? 3 : 4));
   const int b = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
@@ -309,18 +311,24 @@ int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64) {
   return ch;
 }
 
-template <typename R, int Q>
-static hipError_t launch_e(const EstArgs& a, hipStream_t s) {
+template <typename R, int Q, int BS>
+static hipError_t launch_eb(const EstArgs& a, hipStream_t s) {
   const size_t hbytes = 2 * (size_t)(a.nt + 1) * a.nr * sizeof(R);
-  const bool sh = hbytes <= 32768;
+  const bool sh = hbytes <= 65536;
   const size_t lds = estimate_lds_bytes(a.nt, a.nr, Q * Q, a.N, a.chunk, a.fp64) + (sh ? hbytes + 16 : 0);
-  auto k = sh ? estimate_kernel<R, Q, true> : estimate_kernel<R, Q, false>;
+  auto k = sh ? estimate_kernel<R, Q, true, BS> : estimate_kernel<R, Q, false, BS>;
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k, dim3(a.n_inst), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(k, dim3(a.n_inst), dim3(BS), lds, s, a);
   return hipGetLastError();
+}
+
+template <typename R, int Q>
+static hipError_t launch_e(const EstArgs& a, hipStream_t s) {
+  if constexpr (sizeof(R) == 8) return launch_eb<R, Q, 256>(a, s);  // the float64 path (nt <= 32) keeps 256
+  else return a.nt * Q > 256 ? launch_eb<R, Q, 1024>(a, s) : launch_eb<R, Q, 256>(a, s);
 }
 
 template <typename R>

@@ -108,8 +108,8 @@ __device__ void pack_dense(const cd* X, int ld, double c, int N, int Npad, doubl
   }
 }
 
-template <typename TIn, bool WGLOB>
-__global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
+template <typename TIn, bool WGLOB, int BS>
+__global__ __launch_bounds__(BS) void setup_kernel(SetupArgs a) {
   const int b = blockIdx.x, tid = threadIdx.x, nt = a.nt, nr = a.nr, N = a.N, Npad = a.Npad;
   const int ld = nt + 1;  // padded leading dimension of the LDS matrices (no bank conflicts on columns)
   const InstDesc dsc = inst_desc(a.desc, b, nt, nr, a.Q * a.Q, 1);
@@ -145,9 +145,9 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   // its (m, m2) entries (and entries of z) in registers across the chunks.
   double nonfinite = 0.0;
   {
-    constexpr int kIC = 32, kEPT = 17;  // entries per thread per group
+    constexpr int kIC = 32, kEPT = BS >= 1024 ? 5 : 17;  // entries per thread per group
     typedef cd tc;
-    tc* Ht = (tc*)(red + 256);          // kIC x (nt + 1)
+    tc* Ht = (tc*)(red + BS);           // kIC x (nt + 1)
     tc* yc = Ht + kIC * ld;              // kIC
     const int total = nt * nt + nt;
     for (int e0 = 0; e0 < total; e0 += kEPT * (int)blockDim.x) {  // groups of entries held in registers
@@ -318,18 +318,25 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
 
 bool setup_w_global(int nt) { return nt > 64; }
 
-hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
+template <int BS>
+hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s) {
   const bool wg = setup_w_global(a.nt);
-  const size_t lds = (size_t)((wg ? 0 : a.nt * (a.nt + 1)) + 4 * a.nt) * sizeof(cd) + 256 * sizeof(double) +
+  const size_t lds = (size_t)((wg ? 0 : a.nt * (a.nt + 1)) + 4 * a.nt) * sizeof(cd) + BS * sizeof(double) +
                      (32 * (size_t)(a.nt + 1) + 32) * sizeof(cd);
-  auto k = a.fp64 ? (wg ? setup_kernel<double, true> : setup_kernel<double, false>)
-                  : (wg ? setup_kernel<float, true> : setup_kernel<float, false>);
+  auto k = a.fp64 ? (wg ? setup_kernel<double, true, BS> : setup_kernel<double, false, BS>)
+                  : (wg ? setup_kernel<float, true, BS> : setup_kernel<float, false, BS>);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k, dim3(a.n_inst), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(k, dim3(a.n_inst), dim3(BS), lds, s, a);
   return hipGetLastError();
+}
+
+// Large instances leave one workgroup per CU (LDS), so they get 16 waves instead of 4 to hide
+// the latency of the double-precision LDS traffic of the Gauss-Jordan sweep.
+hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
+  return a.nt > 32 ? launch_setup_bs<1024>(a, s) : launch_setup_bs<256>(a, s);
 }
 
 }  // namespace dmala
