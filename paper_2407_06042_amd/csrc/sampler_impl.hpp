@@ -357,6 +357,46 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
       for (int rt = 0; rt < RTW; ++rt) {
         const int rtg = rt0 + rt;
         f32x4 e = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (MG && RT >= 8) {
+          // matrices from L2 at one wave per SIMD: issue every fragment load of the row tile
+          // before the first product, so the loads overlap instead of waiting one by one
+          uint4 fr[kEPasses + NPP][KB];
+#pragma unroll
+          for (int p = 0; p < kEPasses + NPP; ++p)
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+              fr[p][kb] = *(const uint4*)frag(p < kEPasses ? NPP + p : p - kEPasses, rtg, kb);
+#pragma unroll
+          for (int p = 0; p < kEPasses; ++p)
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+              half8 av;
+              __builtin_memcpy(&av, &fr[p][kb], 16);
+              e = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bh[kb], e, 0, 0, 0);
+            }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) accE[rt * 4 + i] = e[i];
+          if constexpr (PM != PM_NAIVE) {
+            f32x4 q = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int p = 0; p < NPP; ++p)
+#pragma unroll
+              for (int kb = 0; kb < KB; ++kb) {
+                if constexpr (PM == PM_BF16X1) {
+                  bf16x8 av;
+                  __builtin_memcpy(&av, &fr[kEPasses + p][kb], 16);
+                  q = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bb[kb], q, 0, 0, 0);
+                } else {
+                  half8 av;
+                  __builtin_memcpy(&av, &fr[kEPasses + p][kb], 16);
+                  q = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bh[kb], q, 0, 0, 0);
+                }
+              }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) accP[rt * 4 + i] = q[i];
+          }
+          continue;
+        }
 #pragma unroll
         for (int p = 0; p < kEPasses; ++p)
 #pragma unroll
