@@ -110,3 +110,15 @@ def test_mlp_entry_points_validate_on_the_host():
     assert L.dmala_mlp_train_step(f, f, f, 1, -1.0, f, f, 1000, None, None, ws, need, None) == -1
     assert L.dmala_mlp_train_step(f, f, f, 1, 1e-3, f, f, 1000, None, None, ws, need - 1, None) == -4
     assert L.dmala_mlp_train_step(f, f, f, 1, 1e-3, f, f, 1000, None, None, ctypes.c_void_p(0x10010), need, None) == -4
+
+
+def test_learned_only_layouts():
+    # layouts 5 and 6 (tile_config 6, 7) exist for the learned mixture only
+    assert dm.workspace_size(2, 32, 32, 64, _lparams(tile_config=6)) > 0
+    assert dm.workspace_size(2, 64, 64, 64, _lparams(tile_config=7)) > 0
+    with pytest.raises(dm.DmalaError):
+        dm.workspace_size(2, 32, 32, 64, dm.make_params(16, 10, 1, tile_config=6))
+    with pytest.raises(dm.DmalaError):
+        dm.workspace_size(2, 32, 32, 64, _lparams(tile_config=7))      # 64 dims, not 128
+    with pytest.raises(dm.DmalaError):
+        dm.workspace_size(2, 32, 32, 64, dm.make_params(16, 10, 1, tile_config=8))
