@@ -128,9 +128,9 @@ __global__ __launch_bounds__(BS) void setup_kernel(SetupArgs a) {
     z = W + nt * ld;
   }
   cd* bv = z + nt;
-  cd* rowp = bv + nt;
-  cd* colp = rowp + nt;
-  double* red = (double*)(colp + nt);
+  cd* rowp = bv + nt;       // 2 x nt (alternating Gauss-Jordan steps)
+  cd* colp = rowp + 2 * nt; // 2 x nt
+  double* red = (double*)(colp + 2 * nt);
   unsigned char* blk = a.ws_inst + (size_t)b * a.inst_stride;
 
   const int Q = a.Q, M = Q * Q;
@@ -233,39 +233,68 @@ __global__ __launch_bounds__(BS) void setup_kernel(SetupArgs a) {
     // W <- (G + gamma I)^-1 by in-place Gauss-Jordan
     for (int m = tid; m < nt; m += blockDim.x) W[m * ld + m].re += gamma;
     __syncthreads();
-    // Gauss-Jordan step p: row p is scaled by the pivot inverse (sr), every
-    // other row i subtracts col[i] * sr, where column p is treated as zero so
-    // that it receives -col[i] * inv.  Entries are visited in row-major order
-    // with incremental indices (no integer division in the loop).
-    const int di = (int)blockDim.x / nt, dj = (int)blockDim.x % nt;
-    const int i_start = tid / nt, j_start = tid % nt;
+    // Gauss-Jordan with the working matrix in registers: thread t keeps row
+    // t / TPR, columns t % TPR + TPR k (k < KMAX), for the whole sweep.  Step p:
+    // the owners of column p publish it (colp), the owners of row p publish the row
+    // scaled by the pivot inverse (rowp, with the inverse itself in column p), and
+    // every other row i subtracts colp[i] * rowp, column p counting as zero so that
+    // it receives -colp[i] * inv.  The two vectors alternate between steps, so two
+    // barriers per step order all reads and writes.
+    constexpr int RMAX = WGLOB ? 128 : (BS >= 1024 ? 64 : 32);  // rows covered (nt <= RMAX)
+    constexpr int TPR = BS / RMAX;                               // threads per row
+    constexpr int KMAX = RMAX / TPR;                             // columns per thread
+    const int gi = tid / TPR, gj = tid % TPR;
+    cd w[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int j = gj + TPR * k;
+      w[k] = (gi < nt && j < nt) ? W[gi * ld + j] : cd{0.0, 0.0};
+    }
     for (int p = 0; p < nt; ++p) {
-      for (int j = tid; j < nt; j += blockDim.x) {
-        const cd piv = W[p * ld + p];
+      cd* rp = rowp + (p & 1) * nt;
+      cd* cp = colp + (p & 1) * nt;
+      const int kp = p / TPR;
+      if (gi < nt && gj == p % TPR) {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+          if (k == kp) cp[gi] = w[k];
+      }
+      __syncthreads();
+      if (gi == p) {
+        const cd piv = cp[p];
         const double den = piv.re * piv.re + piv.im * piv.im;
         const cd inv = {piv.re / den, -piv.im / den};
-        rowp[j] = (j == p) ? inv : cmul(W[p * ld + j], inv);
-        colp[j] = W[j * ld + p];
-      }
-      __syncthreads();
-      int i = i_start, j = j_start;
-      for (int e = tid; e < nt * nt; e += blockDim.x) {
-        const cd sr = rowp[j];
-        cd v;
-        if (i == p) {
-          v = sr;
-        } else {
-          const cd t = cmul(colp[i], sr);
-          const cd w = (j == p) ? cd{0.0, 0.0} : W[i * ld + j];
-          v = {w.re - t.re, w.im - t.im};
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+          const int j = gj + TPR * k;
+          if (j < nt) rp[j] = (j == p) ? inv : cmul(w[k], inv);
         }
-        W[i * ld + j] = v;
-        i += di;
-        j += dj;
-        if (j >= nt) { j -= nt; ++i; }
       }
       __syncthreads();
+      if (gi < nt) {
+        const cd ci = cp[gi];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+          const int j = gj + TPR * k;
+          if (j < nt) {
+            const cd sr = rp[j];
+            if (gi == p) {
+              w[k] = sr;
+            } else {
+              const cd t = cmul(ci, sr);
+              const cd w0 = (j == p) ? cd{0.0, 0.0} : w[k];
+              w[k] = {w0.re - t.re, w0.im - t.im};
+            }
+          }
+        }
+      }
     }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int j = gj + TPR * k;
+      if (gi < nt && j < nt) W[gi * ld + j] = w[k];
+    }
+    __syncthreads();
     if (!a.fp64) {
       float* afv = (float*)(frag + (size_t)(npP + kEPasses) * a.RT * a.KB * 1024) + 2 * Npad;
       for (int m = tid; m < nt; m += blockDim.x)
@@ -321,10 +350,14 @@ bool setup_w_global(int nt) { return nt > 64; }
 template <int BS>
 hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s) {
   const bool wg = setup_w_global(a.nt);
-  const size_t lds = (size_t)((wg ? 0 : a.nt * (a.nt + 1)) + 4 * a.nt) * sizeof(cd) + BS * sizeof(double) +
+  const size_t lds = (size_t)((wg ? 0 : a.nt * (a.nt + 1)) + 6 * a.nt) * sizeof(cd) + BS * sizeof(double) +
                      (32 * (size_t)(a.nt + 1) + 32) * sizeof(cd);
-  auto k = a.fp64 ? (wg ? setup_kernel<double, true, BS> : setup_kernel<double, false, BS>)
-                  : (wg ? setup_kernel<float, true, BS> : setup_kernel<float, false, BS>);
+  void (*k)(SetupArgs);
+  if constexpr (BS >= 1024)   // the working matrix goes to the workspace only for nt > 64 (1024 threads)
+    k = a.fp64 ? (wg ? setup_kernel<double, true, BS> : setup_kernel<double, false, BS>)
+               : (wg ? setup_kernel<float, true, BS> : setup_kernel<float, false, BS>);
+  else
+    k = a.fp64 ? setup_kernel<double, false, BS> : setup_kernel<float, false, BS>;
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
