@@ -316,3 +316,13 @@ def test_trace_consistency():
     # rejection keeps the hash
     prev = np.concatenate([tr["init_hash"][None], tr["hash"][:-1]])
     assert np.all((tr["hash"] == prev) | tr["accept"])
+
+
+def test_imperfect_csi_has_the_requested_nmse():
+    b = W.make_batch(16, 16, 16, 16.5, 400, seed=91)
+    for nmse in (-20.0, -10.0):
+        e = W.imperfect_csi(b, nmse, seed=1)
+        ratio = np.sum(np.abs(e.H - b.H) ** 2) / np.sum(np.abs(b.H) ** 2)
+        assert abs(10 * np.log10(ratio) - nmse) < 0.1
+        np.testing.assert_array_equal(e.y, b.y)
+        np.testing.assert_array_equal(e.meta["H_true"], b.H)

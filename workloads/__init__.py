@@ -147,3 +147,18 @@ def c3_uneven(n_inst=4096, seed=3):
         out["x_idx"].append(b.x_idx[0])
     out["sigma2"] = np.array(out["sigma2"])
     return out
+
+
+def imperfect_csi(batch, nmse_db, seed=0):
+    """The same problems seen through an estimated channel H_hat = H + E (Section V-F).
+
+    E has i.i.d. CN(0, sigma_e^2) entries with sigma_e^2 = NMSE * E|h_ij|^2, so that
+    E||E||_F^2 / E||H||_F^2 = NMSE.  y, sigma^2 and the transmitted symbols are
+    unchanged (y was generated with the true H, kept in meta["H_true"]).
+    """
+    var_h = batch.meta.get("var_h", 1.0 / batch.nr)
+    s2e = 10.0 ** (nmse_db / 10.0) * var_h
+    rng = np.random.default_rng(np.random.SeedSequence([6, int(seed), int(round((nmse_db + 200.0) * 100))]))
+    E = (rng.standard_normal(batch.H.shape) + 1j * rng.standard_normal(batch.H.shape)) * np.sqrt(s2e / 2.0)
+    meta = dict(batch.meta, H_true=batch.H, nmse_db=nmse_db)
+    return Batch(batch.H + E, batch.y, batch.sigma2, batch.x_idx, batch.M, meta)
