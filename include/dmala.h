@@ -75,6 +75,15 @@ typedef enum { DMALA_FP64 = 0, DMALA_FP32 = 1, DMALA_BF16 = 2, DMALA_FP16 = 3 } 
  * transition's random stream (plain iff u < mix_eps).  Not with DMALA_FP64. */
 typedef enum { DMALA_PRECOND = 0, DMALA_NAIVE = 1, DMALA_LEARNED = 2 } dmala_proposal;
 
+/* Bit LLR estimator from the final samples (one per chain):
+ *   IS   -- eq. llr_is in the log-sum-exp form of eq. llr_simple (the default);
+ *   LIST -- eq. llr_approx_app: APP sums over the distinct samples only, each sample
+ *           on the side of its own bit; a side without samples gives +-20;
+ *   MC   -- eq. mc on the bit indicators: log(#samples with b = +1 / # with b = -1),
+ *           duplicates counted, +-20 when one side is empty (meaningful with tau = 1,
+ *           i.e. samples of pi).  LIST and MC are clipped to [-20, 20]. */
+typedef enum { DMALA_LLR_IS = 0, DMALA_LLR_LIST = 1, DMALA_LLR_MC = 2 } dmala_llr_mode;
+
 /* The learned proposal's network: 7 features per antenna -> 64 -> 64 -> 4
  * (ReLU), parameters as one float32 array, row-major blocks in this order:
  *   W1[64][7], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]   (4932 floats).
@@ -117,6 +126,7 @@ typedef struct {
   const float* mlp_weights;  /* LEARNED: device float32 [DMALA_MLP_PARAMS]; otherwise ignored.
                                 LEARNED excludes layout 2; its defaults are layouts 0, 5, 6, 4 */
   double mix_eps;            /* LEARNED: probability of the PRECOND kernel per transition, in [0, 1] */
+  dmala_llr_mode llr_mode;   /* bit LLR estimator (default IS) */
 } dmala_params;
 
 /* Device output buffers; any pointer may be NULL to skip that output. */

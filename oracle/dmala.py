@@ -310,6 +310,49 @@ def llr_is(prob, k_samples, log_w=None, antennas=None):
     return out
 
 
+LLR_CLIP = 20.0
+
+
+def llr_list(prob, k_samples, clip=LLR_CLIP):
+    """List-based LLRs (eq. llr_approx_app): the APP sums of eq. exact_llr restricted
+    to the distinct samples of the list, log sum over the list's x with b_k = +1 of
+    exp f(x) minus the same over b_k = -1.  A side with no sample gives +-clip (the
+    paper leaves the empty case open; the result is also clipped to [-clip, clip])."""
+    k = np.unique(np.asarray(k_samples), axis=0)             # the list: distinct samples
+    nb = prob.nbits_axis
+    f = prob.f(prob.x_of(k))
+    labels = gray_bits(k, nb)                                # (L, N, nb)
+    out = np.zeros((prob.Nt, 2 * nb))
+    for n in range(prob.N):
+        for b in range(nb):
+            plus = labels[:, n, b] == 0
+            if not plus.any():
+                v = -clip
+            elif plus.all():
+                v = clip
+            else:
+                v = _lse(f[plus], axis=0) - _lse(f[~plus], axis=0)
+            out[n // 2, (n % 2) * nb + b] = np.clip(v, -clip, clip)
+    return out
+
+
+def llr_mc(prob, k_samples, clip=LLR_CLIP):
+    """Plain Monte Carlo LLRs (eq. mc on the bit indicators): log of the number of
+    samples with b_k = +1 over the number with b_k = -1, duplicates counted; with
+    samples from pi (tau = 1) this tends to eq. exact_llr.  Clipped to [-clip, clip]."""
+    k = np.asarray(k_samples)
+    nb = prob.nbits_axis
+    labels = gray_bits(k, nb)
+    out = np.zeros((prob.Nt, 2 * nb))
+    for n in range(prob.N):
+        for b in range(nb):
+            npl = int(np.sum(labels[:, n, b] == 0))
+            nmi = len(k) - npl
+            v = clip if nmi == 0 else (-clip if npl == 0 else np.log(npl) - np.log(nmi))
+            out[n // 2, (n % 2) * nb + b] = np.clip(v, -clip, clip)
+    return out
+
+
 def marginals_is(prob, k_samples, log_w=None, antennas=None):
     """Symbol posterior marginals, IS estimator at symbol level (see module doc).
 

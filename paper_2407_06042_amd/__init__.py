@@ -27,7 +27,7 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int), ("proposal", ctypes.c_int), ("tau", ctypes.c_double),
                 ("alpha_mult", ctypes.c_double), ("beta_mult", ctypes.c_double), ("gamma_mult", ctypes.c_double),
                 ("tile_config", ctypes.c_int32), ("wg_chain_blocks", ctypes.c_int32),
-                ("mlp_weights", ctypes.c_void_p), ("mix_eps", ctypes.c_double)]
+                ("mlp_weights", ctypes.c_void_p), ("mix_eps", ctypes.c_double), ("llr_mode", ctypes.c_int)]
 
 
 class Shape(ctypes.Structure):
@@ -101,8 +101,12 @@ def last_error():
     return lib().dmala_last_error().decode()
 
 
+LLR_MODES = {"is": 0, "list": 1, "mc": 2}
+
+
 def make_params(n_chains, n_iters, seed, precision="fp32", proposal="precond", tau=2.0,
-                alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, tile_config=0, mlp_weights=None, mix_eps=0.0):
+                alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, tile_config=0, mlp_weights=None, mix_eps=0.0,
+                llr_mode="is"):
     """mlp_weights: device float32 tensor of MLP_PARAMS values (learned proposal only)."""
     w = None
     if mlp_weights is not None:
@@ -110,7 +114,7 @@ def make_params(n_chains, n_iters, seed, precision="fp32", proposal="precond", t
         w = mlp_weights.data_ptr()
     return Params(int(n_chains), int(n_iters), int(seed) & ((1 << 64) - 1), PRECISIONS[precision],
                   PROPOSALS[proposal], float(tau), float(alpha_mult), float(beta_mult), float(gamma_mult),
-                  int(tile_config), 0, w, float(mix_eps))
+                  int(tile_config), 0, w, float(mix_eps), LLR_MODES[llr_mode])
 
 
 def _check_weights(w):
@@ -146,14 +150,14 @@ class Detector:
     def __init__(self, n_inst, nt, nr, M, n_chains, n_iters, seed=0, precision="fp32", proposal="precond",
                  tau=2.0, alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, device="cuda",
                  outputs=("symbols", "marginals", "llrs", "best_energy"), trace=False, tile_config=0,
-                 mlp_weights=None, mix_eps=0.0):
+                 mlp_weights=None, mix_eps=0.0, llr_mode="is"):
         import torch
         self.torch = torch
         self.n_inst, self.nt, self.nr, self.M = n_inst, nt, nr, M
         self.precision = precision
         self.mlp_weights = mlp_weights  # keeps the tensor alive while the detector holds its pointer
         self.params = make_params(n_chains, n_iters, seed, precision, proposal, tau, alpha_mult, beta_mult,
-                                  gamma_mult, tile_config, mlp_weights, mix_eps)
+                                  gamma_mult, tile_config, mlp_weights, mix_eps, llr_mode)
         self.ws_bytes = workspace_size(n_inst, nt, nr, M, self.params)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
         nb = int(round(np.log2(M)))

@@ -37,6 +37,7 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
   if (p->proposal != DMALA_PRECOND && p->proposal != DMALA_NAIVE && p->proposal != DMALA_LEARNED)
     return fail(DMALA_ERR_ARG, "unknown proposal %d", (int)p->proposal);
   const bool lrn = p->proposal == DMALA_LEARNED;
+  if (p->llr_mode < DMALA_LLR_IS || p->llr_mode > DMALA_LLR_MC) return fail(DMALA_ERR_ARG, "unknown llr_mode %d", (int)p->llr_mode);
   if (lrn) {
     if (p->precision == DMALA_FP64) return fail(DMALA_ERR_UNSUPPORTED, "DMALA_LEARNED is not available with DMALA_FP64");
     if (!p->mlp_weights) return fail(DMALA_ERR_ARG, "DMALA_LEARNED needs mlp_weights");
@@ -175,6 +176,8 @@ dmala_status enqueue(const void* H, const void* y, const void* sigma2, int32_t n
     ea.n_inst = n_inst; ea.nt = sh.nt; ea.nr = sh.nr; ea.Q = sh.Q; ea.N = sh.N; ea.Npad = sh.Npad;
     ea.C = sh.C; ea.Cpad = sh.Cpad; ea.fp64 = sh.fp64;
     ea.chunk = estimate_chunk(sh.nt, sh.nr, sh.M, sh.N, sh.C, sh.fp64 != 0);
+    ea.llr_mode = (int)p->llr_mode;
+    ea.llr_clip = 20.0f;
     ea.symbols = out->symbols; ea.marginals = out->marginals; ea.llrs = out->llrs;
     ea.best_energy = out->best_energy; ea.marginals_mc = out->marginals_mc;
     e = launch_estimate(ea, stream);

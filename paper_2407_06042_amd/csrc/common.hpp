@@ -147,6 +147,8 @@ struct EstArgs {
   int n_inst, nt, nr, Q, N, Npad, C, Cpad, fp64;
   int chunk;       // chains staged in LDS at a time
   int32_t* symbols; float* marginals; float* llrs; float* best_energy; float* marginals_mc;
+  int llr_mode;    // 0: IS (eq. llr_is), 1: list (eq. llr_approx_app), 2: Monte Carlo bit frequencies (eq. mc)
+  float llr_clip;  // |LLR| limit of the list and Monte Carlo forms
 };
 
 // Host launchers (defined in the .hip translation units).

@@ -91,6 +91,7 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
   int8_t* Kbs = Ks + (size_t)CH * N;                 // CH x N
   __shared__ R best_e;
   __shared__ int best_c;
+  __shared__ unsigned char dupf[1024];   // list LLRs: chain repeats an earlier chain's final state
   // H is read many times per element: stage it in LDS when it fits, transposed
   // with a padded row (Ht[i][m], leading dimension nt + 1) so that both the
   // row-wise (residual) and the column-wise (H^H r) sweeps are conflict-free.
@@ -118,6 +119,26 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
     a2[m] = R(4) * s * s * g * inv_s2;
   }
   if (tid == 0) { best_e = R(INFINITY); best_c = 0; }
+  const int mode = a.llr_mode;
+  if (mode == 1 && a.llrs) {
+    // the list holds distinct samples: flag every chain whose first N levels equal an earlier chain's
+    const int nw = (N + 3) >> 2;
+    for (int c = tid; c < C; c += nth) {
+      const uint32_t* kc = (const uint32_t*)(K + (size_t)c * Npad);
+      bool dup = false;
+      for (int c2 = 0; c2 < c && !dup; ++c2) {
+        const uint32_t* k2 = (const uint32_t*)(K + (size_t)c2 * Npad);
+        bool same = true;
+        for (int w = 0; w < nw; ++w) {
+          const int valid = N - 4 * w;
+          const uint32_t msk = valid >= 4 ? 0xFFFFFFFFu : ((1u << (8 * valid)) - 1u);
+          same = same && ((kc[w] ^ k2[w]) & msk) == 0u;
+        }
+        dup = same;
+      }
+      dupf[c] = dup ? 1 : 0;
+    }
+  }
 
   // ownership: marginal rows (m, kI), in blocks of one row per thread, and bits (m, ax, bit)
   const int n_rows = nt * Q, n_llr = nt * 2 * NB;
@@ -125,6 +146,9 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
   const bool single_chunk = CH >= C;
   const bool want_mc = a.marginals_mc != nullptr;
   OnlineLse<R> lnum[kLlrPerThread], lden[kLlrPerThread];
+  int cplus[kLlrPerThread];
+#pragma unroll
+  for (int q = 0; q < kLlrPerThread; ++q) cplus[q] = 0;
 
   for (int rb = 0; rb < n_rb; ++rb) {
     const int row = rb * nth + tid;
@@ -236,14 +260,26 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
             for (int c = 0; c < ch; ++c) {
               const CM<R> v = cm[c * nt + m];
               const int k = ax ? v.kQ : v.kI;
-              const R av = ax ? v.aQ : v.aI;
               const int g = k ^ (k >> 1);
-              const R ep = R(ungray(g & ~mask) - k), em = R(ungray(g | mask) - k);
-              const R Fp = fs[c] + ep * (av - q2 * ep);
-              const R Fm = fs[c] + em * (av - q2 * em);
-              const R gm = (Fp - Fm) * inv_tau;
-              lnum[q].add(cw * Fp - softplus(-gm));
-              lden[q].add(cw * Fm - softplus(gm));
+              if (mode == 0) {
+                const R av = ax ? v.aQ : v.aI;
+                const R ep = R(ungray(g & ~mask) - k), em = R(ungray(g | mask) - k);
+                const R Fp = fs[c] + ep * (av - q2 * ep);
+                const R Fm = fs[c] + em * (av - q2 * em);
+                const R gm = (Fp - Fm) * inv_tau;
+                lnum[q].add(cw * Fp - softplus(-gm));
+                lden[q].add(cw * Fm - softplus(gm));
+              } else {
+                const bool plus = (g & mask) == 0;   // label bit 0 <-> b = +1
+                if (mode == 1) {
+                  if (!dupf[c0 + c]) {
+                    if (plus) lnum[q].add(fs[c]);
+                    else lden[q].add(fs[c]);
+                  }
+                } else {
+                  cplus[q] += plus ? 1 : 0;
+                }
+              }
             }
           }
         }
@@ -282,7 +318,22 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
 #pragma unroll
     for (int q = 0; q < kLlrPerThread; ++q) {
       const int it = tid + q * nth;
-      if (it < n_llr) a.llrs[dsc.llr_off + it] = (float)(lnum[q].value() - lden[q].value());
+      if (it < n_llr) {
+        R v;
+        const R clip = (R)a.llr_clip;
+        if (mode == 0) {
+          v = lnum[q].value() - lden[q].value();
+        } else if (mode == 1) {
+          const bool hp = lnum[q].mx > R(-INFINITY), hm = lden[q].mx > R(-INFINITY);
+          v = !hp ? -clip : (!hm ? clip : lnum[q].value() - lden[q].value());
+          v = v > clip ? clip : (v < -clip ? -clip : v);
+        } else {
+          const int cm_ = C - cplus[q];
+          v = cm_ == 0 ? clip : (cplus[q] == 0 ? -clip : flog(R(cplus[q])) - flog(R(cm_)));
+          v = v > clip ? clip : (v < -clip ? -clip : v);
+        }
+        a.llrs[dsc.llr_off + it] = (float)v;
+      }
     }
   }
   // hard decision: smallest recomputed energy among the chains' best states

@@ -122,3 +122,12 @@ def test_learned_only_layouts():
         dm.workspace_size(2, 32, 32, 64, _lparams(tile_config=7))      # 64 dims, not 128
     with pytest.raises(dm.DmalaError):
         dm.workspace_size(2, 32, 32, 64, dm.make_params(16, 10, 1, tile_config=8))
+
+
+def test_llr_mode_validation():
+    p = dm.make_params(16, 10, 1, llr_mode="list")
+    assert dm.workspace_size(2, 4, 4, 16, p) > 0
+    p.llr_mode = 3
+    with pytest.raises(dm.DmalaError) as e:
+        dm.workspace_size(2, 4, 4, 16, p)
+    assert "llr_mode" in str(e.value)

@@ -326,3 +326,33 @@ def test_imperfect_csi_has_the_requested_nmse():
         assert abs(10 * np.log10(ratio) - nmse) < 0.1
         np.testing.assert_array_equal(e.y, b.y)
         np.testing.assert_array_equal(e.meta["H_true"], b.H)
+
+
+def test_list_llr_over_the_whole_lattice_is_exact():
+    """eq. llr_approx_app with the list equal to A^N is eq. exact_llr."""
+    b = W.make_batch(2, 2, 16, 12.0, 3, seed=44)
+    for i in range(3):
+        prob = dmala.Problem(b.H[i], b.y[i], b.sigma2[i], 16)
+        K = exact.all_states(prob.N, prob.Q)
+        np.testing.assert_allclose(dmala.llr_list(prob, K, clip=1e9), exact.exact_llr(prob, K), atol=1e-9)
+        # duplicates do not count; a one-sided list clips
+        dup = np.concatenate([K, K[:7]])
+        np.testing.assert_allclose(dmala.llr_list(prob, dup, clip=1e9), exact.exact_llr(prob, K), atol=1e-9)
+        one = dmala.llr_list(prob, K[:1])
+        assert np.all(np.abs(one) == dmala.LLR_CLIP)
+
+
+def test_mc_llr_with_exact_frequencies_is_exact():
+    """eq. mc on the bit indicators with every state repeated in proportion to pi tends to eq. exact_llr."""
+    b = W.make_batch(1, 2, 16, 10.0, 2, seed=45)
+    for i in range(2):
+        prob = dmala.Problem(b.H[i], b.y[i], b.sigma2[i], 16, tau=1.0)
+        K = exact.all_states(prob.N, prob.Q)
+        p = np.exp(exact.log_target(prob, K, tempered=False))
+        reps = np.round(p * 1e6).astype(int)
+        samples = np.repeat(K, reps, axis=0)
+        ex = exact.exact_llr(prob, K)
+        mc = dmala.llr_mc(prob, samples, clip=1e9)
+        ok = np.abs(ex) < 8          # bits whose rarer side has at least ~300 samples
+        np.testing.assert_allclose(mc[ok], ex[ok], atol=5e-3)
+        assert dmala.llr_mc(prob, K[:1]).max() == dmala.LLR_CLIP
