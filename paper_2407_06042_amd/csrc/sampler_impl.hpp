@@ -50,10 +50,14 @@ __device__ __forceinline__ double lg2(double x) { return log2(x); }
 // Mode of the discretised Gaussian exp2(-kL (j - mu)^2) over j in [0, Q).
 template <int Q, typename R>
 __device__ __forceinline__ R mode_of(R mu) {
-  R j = rint(mu);
-  j = j < R(0) ? R(0) : j;
-  j = j > R(Q - 1) ? R(Q - 1) : j;
-  return j;
+  if constexpr (std::is_same<R, float>::value) {
+    return __builtin_amdgcn_fmed3f(rintf(mu), 0.0f, float(Q - 1));   // one v_med3 instead of two compare/selects
+  } else {
+    R j = rint(mu);
+    j = j < R(0) ? R(0) : j;
+    j = j > R(Q - 1) ? R(Q - 1) : j;
+    return j;
+  }
 }
 
 // Weights w_j = exp2(-kL ((j - mu)^2 - (js - mu)^2)) of the proposal over the
