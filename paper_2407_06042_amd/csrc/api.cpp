@@ -66,11 +66,12 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
   else if (p->precision == DMALA_FP16) sh.pm = PM_F16X1;
   else sh.pm = PM_F16X2;
   // Proposal window: with the preconditioned parameters kL = 2 log2(e) / (alpha_mult beta_mult)
-  // is the same for every instance; a 3-level window is exact to fp32 when kL * 3 * 4 >= 30.
+  // is the same for every instance; a 3-level window is exact to fp32 when kL * 3 * 4 >= 30, and
+  // its factorised weights (powers up to exp2(3 kL)) stay finite in fp32 for kL <= 40.
   {
     const double am = p->alpha_mult > 0 ? p->alpha_mult : 1.0, bm = p->beta_mult > 0 ? p->beta_mult : 1.0;
     const double kL = 2.0 * 1.4426950408889634 / (am * bm);
-    sh.win = (!fp64 && !pl.naive && !lrn && Q >= 8 && kL * 12.0 >= 30.0) ? 3 : 0;
+    sh.win = (!fp64 && !pl.naive && !lrn && Q >= 8 && kL * 12.0 >= 30.0 && kL <= 40.0) ? 3 : 0;
   }
   if (fp64) {
     sh.frag_bytes = round_up((2 * (size_t)sh.Npad * sh.Npad + 2 * (size_t)sh.Npad) * 8, 16);

@@ -60,29 +60,88 @@ __device__ __forceinline__ R mode_of(R mu) {
   }
 }
 
+// Per-mode coefficient table of the 3-level window (LDS, one row of kCtabStride
+// floats per mode js): c_3, c_2, c_1 for the levels js-3 .. js-1, then c_1, c_2,
+// c_3 for js+1 .. js+3, with c_o = exp2(-kL o^2) and zero for a level outside
+// [0, Q).  Reading the row replaces the per-level range tests of the window.
+// The 48-byte stride keeps the rows of an 8-level table on distinct LDS banks.
+constexpr int kCtabStride = 12;
+constexpr size_t kCtabBytes = 16 * kCtabStride * sizeof(float);  // up to Q = 16
+// every layout but one wave of 8 LDS row tiles (whose matrices take all 160 KiB at fp32)
+constexpr bool win_table(int rtw, int wd, bool mg) { return !(rtw == 8 && wd == 1 && !mg); }
+
+template <int Q>
+__device__ __forceinline__ void ctab_fill(float* ctab, float kL) {
+  for (int i = threadIdx.x; i < Q * kCtabStride; i += blockDim.x) {
+    const int js = i / kCtabStride, sl = i % kCtabStride;
+    float v = 0.f;
+    if (sl < 3) {
+      const int o = 3 - sl;
+      v = (js - o >= 0) ? ex2(-kL * float(o * o)) : 0.f;
+    } else if (sl < 6) {
+      const int o = sl - 2;
+      v = (js + o <= Q - 1) ? ex2(-kL * float(o * o)) : 0.f;
+    }
+    ctab[i] = v;
+  }
+}
+
 // Weights w_j = exp2(-kL ((j - mu)^2 - (js - mu)^2)) of the proposal over the
-// levels j = js - W .. js + W around the mode js (zero outside [0, Q)), in
+// levels j = js - 3 .. js + 3 around the mode js (zero outside [0, Q)), in
 // ascending level order.  With delta = js - mu, F = exp2(-2 kL delta) and
-// c_o = exp2(-kL o^2), the weight of level js + o is c_o F^o above the mode and
-// c_o F^-o below it: two exponentials per dimension instead of one per level.
-// The window is used only when kL W (W + 1) >= 30, so that every omitted level
+// G = 1 / F, the weight of level js + o is c_o F^o above the mode and c_o G^o
+// below it: two exponentials per dimension instead of one per level.
+// A side with a level in range has |2 kL delta| <= kL, so bounding both
+// exponents by kL changes no weight that is used and keeps F^3 and G^3 finite
+// (the window is used only for kL <= 40) where the table entry is zero.
+// The window is used only when 12 kL >= 30, so that every omitted level
 // weighs less than 2^-30 of the mode -- below the fp32 rounding of the sums,
 // i.e. invisible in fp32.
-template <int Q, int W, typename R>
-__device__ __forceinline__ void window_weights(R mu, R kL, const R (&c)[W + 1], R (&e)[2 * W + 1], int& js, R& delta) {
-  const R jf = mode_of<Q>(mu);
+// Coefficients of the window: the LDS table address, or (layouts whose LDS is
+// full: one wave with 8 row tiles of matrices) c_o in registers with range tests.
+struct WinCoef {
+  uint32_t tab;
+  float c[4];
+};
+
+template <int Q, int W, bool TAB>
+__device__ __forceinline__ void window_weights(float mu, float kL, const WinCoef& wc, float (&e)[2 * W + 1], int& js,
+                                               float& delta) {
+  static_assert(W == 3, "the coefficient table holds a 3-level window");
+  const float jf = mode_of<Q>(mu);
   js = (int)jf;
   delta = jf - mu;
-  const R F = ex2(R(-2) * kL * delta);
-  const R G = ex2(R(2) * kL * delta);
-  R pf = R(1), pg = R(1);
-  e[W] = R(1);
+  const float x = 2.0f * kL * delta;
+  if constexpr (TAB) {
+    const float F = ex2(-fmaxf(x, -kL));
+    const float G = ex2(fminf(x, kL));
+    // the row by its 32-bit LDS address (generic pointer arithmetic would be 64-bit)
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) const v4f lds_v4f;
+    typedef __attribute__((address_space(3))) const v2f lds_v2f;
+    const uint32_t row = __umul24((uint32_t)js, (uint32_t)(kCtabStride * sizeof(float))) + wc.tab;   // one v_mad_u32_u24
+    const v4f lo = *(lds_v4f*)(uintptr_t)row;         // c_3, c_2, c_1 below; c_1 above
+    const v2f hi = *(lds_v2f*)(uintptr_t)(row + 16);  // c_2, c_3 above
+    const float F2 = F * F, G2 = G * G;
+    e[W] = 1.0f;
+    e[W + 1] = lo.w * F;
+    e[W - 1] = lo.z * G;
+    e[W + 2] = hi.x * F2;
+    e[W - 2] = lo.y * G2;
+    e[W + 3] = hi.y * (F2 * F);
+    e[W - 3] = lo.x * (G2 * G);
+  } else {
+    const float F = ex2(-x), G = ex2(x);
+    float pf = 1.0f, pg = 1.0f;
+    e[W] = 1.0f;
 #pragma unroll
-  for (int o = 1; o <= W; ++o) {
-    pf *= F;
-    pg *= G;
-    e[W + o] = (js + o <= Q - 1) ? c[o] * pf : R(0);
-    e[W - o] = (js - o >= 0) ? c[o] * pg : R(0);
+    for (int o = 1; o <= W; ++o) {
+      pf *= F;
+      pg *= G;
+      e[W + o] = (js + o <= Q - 1) ? wc.c[o] * pf : 0.0f;
+      e[W - o] = (js - o >= 0) ? wc.c[o] * pg : 0.0f;
+    }
   }
 }
 
@@ -99,13 +158,13 @@ __device__ __forceinline__ void level_weights(R mu, R kL, R (&e)[Q], R& base) {
 }
 
 // log2 of the proposal normaliser sum_j exp2(-kL (j - mu)^2) (eq. softmax).
-template <int Q, int WIN, int W, typename R>
-__device__ __forceinline__ R log2_norm(R mu, R kL, const R (&c)[W + 1]) {
+template <int Q, int WIN, int W, bool TAB, typename R>
+__device__ __forceinline__ R log2_norm(R mu, R kL, const WinCoef& wc) {
   R Z = R(0), base;
   if constexpr (WIN > 0) {
     R e[2 * W + 1];
     int js;
-    window_weights<Q, W>(mu, kL, c, e, js, base);
+    window_weights<Q, W, TAB>(mu, kL, wc, e, js, base);
 #pragma unroll
     for (int i = 0; i <= 2 * W; ++i) Z += e[i];
     base *= base;
@@ -120,13 +179,13 @@ __device__ __forceinline__ R log2_norm(R mu, R kL, const R (&c)[W + 1]) {
 
 // Inverse-CDF draw: the smallest level j with u Z < sum_{i <= j} w_i
 // (ascending levels), Z = sum_i w_i.
-template <int Q, int WIN, int W, typename R>
-__device__ __forceinline__ int draw_level(R mu, R kL, const R (&c)[W + 1], R u) {
+template <int Q, int WIN, int W, bool TAB, typename R>
+__device__ __forceinline__ int draw_level(R mu, R kL, const WinCoef& wc, R u) {
   if constexpr (WIN > 0) {
     R e[2 * W + 1];
     int js;
     R delta;
-    window_weights<Q, W>(mu, kL, c, e, js, delta);
+    window_weights<Q, W, TAB>(mu, kL, wc, e, js, delta);
     R Z = R(0);
 #pragma unroll
     for (int i = 0; i <= 2 * W; ++i) Z += e[i];
@@ -245,15 +304,20 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   unsigned char* xbuf = smem + ((staged + 15) & ~(size_t)15);      // 2 x KB x 1 KiB (WD > 1)
   Red* rbuf = (Red*)(xbuf + (WD > 1 ? 2 * KB * 1024 : 0));          // 2 x WD x 16
   unsigned char* mlp_lds = (unsigned char*)(rbuf + (WD > 1 ? 2 * WD * 16 : 0));   // network image (LRN)
+  // window coefficients: a per-mode LDS table, except where the matrices fill the LDS
+  constexpr bool TAB = WIN > 0 && win_table(RTW, WD, MG);
+  float* ctab_p = (float*)(mlp_lds + (LRN ? kMlpLdsBytes : 0));
+  WinCoef wc;
+  wc.tab = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) float*)ctab_p;
+#pragma unroll
+  for (int o = 0; o < 4; ++o) wc.c[o] = ex2(-(float)ip.kL * float(o * o));
   if constexpr (LRN) mlp_stage(a.mlp, mlp_lds);
+  if constexpr (TAB) ctab_fill<Q>(ctab_p, (float)ip.kL);
   __syncthreads();
 
   const Real kL = (Real)ip.kL;
   const Real rho = (Real)ip.rho;
   const Real sP = (Real)ip.scaleP, sE = (Real)ip.scaleE;
-  Real cw[W + 1];  // exp2(-kL o^2)
-#pragma unroll
-  for (int o = 0; o <= W; ++o) cw[o] = ex2(-kL * Real(o * o));
   const Real* pbv;
   const Real* ezv;
   const double* Pd = nullptr;
@@ -445,7 +509,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   auto proposal_at = [&](const int (&k)[D], Real (&mu)[D], Real (&lz)[D], Real (&eg)[D]) {
     grad_at(k, mu, eg);
 #pragma unroll
-    for (int d = 0; d < D; ++d) lz[d] = log2_norm<Q, WIN, W>(mu[d], kL, cw);
+    for (int d = 0; d < D; ++d) lz[d] = log2_norm<Q, WIN, W, TAB>(mu[d], kL, wc);
   };
 
   // Network features of the lane's antenna in slot (rt, i2) at state k with plain centre mu.
@@ -541,8 +605,8 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
       for (int d = 0; d < D; ++d)
         if (valid[d]) {
           const Real tf = Real(kt[d]) - muL[d], tr = Real(kc[d]) - muLp[d];
-          lqf += -kLL[d] * tf * tf - log2_norm<Q, 0, W>(muL[d], kLL[d], cw);
-          lqr += -kLLp[d] * tr * tr - log2_norm<Q, 0, W>(muLp[d], kLLp[d], cw);
+          lqf += -kLL[d] * tf * tf - log2_norm<Q, 0, W, false>(muL[d], kLL[d], wc);
+          lqr += -kLLp[d] * tr * tr - log2_norm<Q, 0, W, false>(muLp[d], kLLp[d], wc);
           T2 -= Real(kt[d] - kc[d]) * (eg[d] + egp[d]);
         }
     } else {
@@ -642,7 +706,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
           const float t0 = float(kp[d]) - ms;
           S -= valid[d] ? (-ks * t0 * t0 - lzf) : 0.f;
         } else {
-          const int kd = draw_level<Q, WIN, W>(mu[d], kL, cw, u);
+          const int kd = draw_level<Q, WIN, W, TAB>(mu[d], kL, wc, u);
           kp[d] = valid[d] ? kd : kc[d];
           S -= lq(kp[d], mu[d], lz[d]);
         }
@@ -659,7 +723,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
           const float mr = useL ? muLp[d] : mup[d], kr = useL ? kLLp[d] : (float)kL;
-          const float lzr = log2_norm<Q, 0, W>(mr, kr, cw);
+          const float lzr = log2_norm<Q, 0, W, false>(mr, kr, wc);
           const float t0 = float(kc[d]) - mr;
           S += valid[d] ? (-kr * t0 * t0 - lzr) : 0.f;
           T2 -= Real(kp[d] - kc[d]) * (eg[d] + egp[d]);
@@ -781,6 +845,7 @@ inline size_t sampler_cfg_lds(const Shape& sh, int rtw, int wd, bool mg, int wav
   staged = (staged + 15) & ~(size_t)15;
   if (wd > 1) staged += 2 * (size_t)KB * 1024 + 2 * (size_t)wd * 16 * sizeof(Red);
   if (sh.lrn) staged += kMlpLdsBytes;
+  if (sh.win > 0 && win_table(rtw, wd, mg)) staged += kCtabBytes;
   return staged;
 }
 
@@ -796,11 +861,18 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
   }
   const dim3 grid(a.n_inst, gy);
   const size_t lds = sampler_cfg_lds(sh, RTW, WD, MG, waves);
+  // two waves per SIMD where the chain loop fits 256 registers without spilling: the learned
+  // two-tile layouts, and the plain four-tile layouts (the evaluation kernels keep the default)
+  constexpr bool kW2Eval = LRN && RTW == 2;
+  constexpr bool kW2 = kW2Eval || (!LRN && RTW == 4 && !std::is_same<Real, double>::value && (WD < 4 || WIN > 0));
   void (*k)(SamplerArgs);
-  if constexpr (LRN && RTW == 2)
-    k = eval ? sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, true, WIN, LRN> : sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>;
-  else
-    k = eval ? sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN, LRN> : sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>;
+  if (eval) {
+    if constexpr (kW2Eval) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, true, WIN, LRN>;
+    else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN, LRN>;
+  } else {
+    if constexpr (kW2) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>;
+    else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>;
+  }
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -812,12 +884,13 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
 template <typename Real, int RTW, int WD, bool MG, int PM>
 hipError_t launch_q(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
   // the 3-level window is used only for Q >= 8 (it would not be smaller otherwise)
-  const bool win = !std::is_same<Real, double>::value && sh.win == 3;
+  constexpr int WN = std::is_same<Real, double>::value ? 0 : 3;   // the float path only
+  const bool win = WN > 0 && sh.win == 3;
   switch (sh.Q) {
     case 2: return launch_t<Real, RTW, WD, MG, 2, PM, 0>(sh, a, eval, s);
     case 4: return launch_t<Real, RTW, WD, MG, 4, PM, 0>(sh, a, eval, s);
-    case 8: return win ? launch_t<Real, RTW, WD, MG, 8, PM, 3>(sh, a, eval, s) : launch_t<Real, RTW, WD, MG, 8, PM, 0>(sh, a, eval, s);
-    case 16: return win ? launch_t<Real, RTW, WD, MG, 16, PM, 3>(sh, a, eval, s) : launch_t<Real, RTW, WD, MG, 16, PM, 0>(sh, a, eval, s);
+    case 8: return win ? launch_t<Real, RTW, WD, MG, 8, PM, WN>(sh, a, eval, s) : launch_t<Real, RTW, WD, MG, 8, PM, 0>(sh, a, eval, s);
+    case 16: return win ? launch_t<Real, RTW, WD, MG, 16, PM, WN>(sh, a, eval, s) : launch_t<Real, RTW, WD, MG, 16, PM, 0>(sh, a, eval, s);
   }
   return hipErrorInvalidValue;
 }

@@ -109,6 +109,23 @@ def test_edge_shapes_fp32(nt, nr, M, C, T):
         assert not bad
 
 
+@pytest.mark.parametrize("alpha_mult", [0.05, 0.2, 3.0])
+def test_step_size_multiplier_fp32(alpha_mult):
+    """Step size alpha = alpha_mult sigma^2 (Section V-A scales it with the noise): the index-unit
+    precision is kL = 2 log2(e) / alpha_mult, so 0.2 runs the 3-level window (kL = 14.4), 0.05 a
+    kernel too peaked for the window's fp32 factorisation (kL = 57.7, all levels weighted directly)
+    and 3.0 a flat kernel (kL = 0.96).  Chains follow the oracle run with the same alpha."""
+    batch = W.make_batch(8, 8, 64, 20.0, 3, seed=41)
+    b, g = run_gpu(batch, 16, 40, 4242, "fp32", alpha_mult=alpha_mult)
+    assert np.all(np.isfinite(g["best_energy"]))
+    for i in range(3):
+        o = run_oracle(b, i, 16, 40, 4242, estimators=False, alpha=alpha_mult * float(b.sigma2[i]))
+        n_id, n_fd, bad = compare_chains(g["trace_hash"][i], o, *EPS32)
+        _print("alpha", mult=alpha_mult, inst=i, identical=n_id, flagged=n_fd, bad=bad[:3])
+        assert not bad
+        assert n_id >= 12
+
+
 def test_zero_iterations_gives_initial_states():
     batch = W.make_batch(6, 6, 16, 12.0, 2, seed=3)
     b, g = run_gpu(batch, 16, 0, 555, "fp32", trace=False)
