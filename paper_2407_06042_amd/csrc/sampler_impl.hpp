@@ -386,7 +386,9 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
         accE[d] = se;
       }
     } else {
-      // B operand: this wave's K blocks from its own registers
+      // B operand: this wave's K blocks from its own registers.  The packed
+      // matrices are zero in the padding columns, so a padding dimension's
+      // level (any in-range value) contributes nothing and needs no mask.
       half8 bh[KB];
       bf16x8 bb[KB];
 #pragma unroll
@@ -394,8 +396,8 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int d = (2 * kb + (j >> 2)) * 4 + (j & 3);
-          const int lv = (dim_of(d) < N) ? (2 * k[d] - QM1) : 0;
-          bh[wd * KBW + kb][j] = (_Float16)(float)lv;
+          const int lv = 2 * k[d] - QM1;
+          bh[wd * KBW + kb][j] = (_Float16)(int16_t)lv;   // exact: |lv| <= 15
           if constexpr (PM == PM_BF16X1) bb[wd * KBW + kb][j] = (__bf16)(float)lv;
         }
       }
@@ -648,11 +650,14 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
       for (int i = 0; i < 4; ++i) kc[rt * 4 + i] = (int)(((uint64_t)(c[i] >> 8) * Q) >> 24);
     }
     Real muL[D], kLL[D];  // cached learned proposal (LRN)
+    Real lzs = 0;         // sum of the lane's log2 normalisers at the current state (plain kernel)
     if constexpr (LRN) {
       grad_at(kc, mu, eg);
       learned_at(kc, mu, muL, kLL);
     } else {
-      proposal_at(kc, mu, lz, eg);
+      grad_at(kc, mu, eg);
+#pragma unroll
+      for (int d = 0; d < D; ++d) lzs += log2_norm<Q, WIN, W, TAB>(mu[d], kL, wc);
     }
     // E(x) = ||y||^2 + x^T g - z^T x = ||y||^2 + (eunit/2) sum_n lv_n (eg_n - ez_n)
     Real ep = 0;
@@ -690,9 +695,10 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
         philox4x32_10(wm, key0, key1);
         useL = low_bytes24(wm[0], wm[1], wm[2]) >= a.mix_thr;
       }
-      // 1. draw x' (padding dimensions never move) and -log q(x'|x)
+      // 1. draw x' (padding dimensions never move) and -log q(x'|x); the plain
+      // kernel's terms are collected as kL sum (x'_n - mu_n)^2 + sum lz_n
       int kp[D];
-      Real S = 0;
+      Real S = 0, tq = 0;
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         Real u;
@@ -708,13 +714,15 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
         } else {
           const int kd = draw_level<Q, WIN, W, TAB>(mu[d], kL, wc, u);
           kp[d] = valid[d] ? kd : kc[d];
-          S -= lq(kp[d], mu[d], lz[d]);
+          const Real t0 = Real(kp[d]) - mu[d];
+          tq += t0 * t0;
         }
       }
+      if constexpr (!LRN) S = kL * tq + lzs;
       // 2-3. gradient at x', proposal at x', + log q(x|x'), energy term.
-      // A padding dimension contributes exactly zero: its contraction rows are
-      // zero, so mu' = mu, lz' = lz and the two log q terms cancel.
-      Real mup[D], lzp[D], egp[D];
+      // A padding dimension contributes nothing: its contraction rows are zero,
+      // so mu' = mu, lz' = lz and its two log q terms cancel.
+      Real mup[D], egp[D], lzps = 0;
       Real muLp[D], kLLp[D];
       Real T2 = 0;
       if constexpr (LRN) {
@@ -726,15 +734,19 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
           const float lzr = log2_norm<Q, 0, W, false>(mr, kr, wc);
           const float t0 = float(kc[d]) - mr;
           S += valid[d] ? (-kr * t0 * t0 - lzr) : 0.f;
-          T2 -= Real(kp[d] - kc[d]) * (eg[d] + egp[d]);
+          T2 -= (Real(kp[d]) - Real(kc[d])) * (eg[d] + egp[d]);
         }
       } else {
-        proposal_at(kp, mup, lzp, egp);
+        grad_at(kp, mup, egp);
+        Real tr = 0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          S += lq(kc[d], mup[d], lzp[d]);
-          T2 -= Real(kp[d] - kc[d]) * (eg[d] + egp[d]);
+          lzps += log2_norm<Q, WIN, W, TAB>(mup[d], kL, wc);
+          const Real t0 = Real(kc[d]) - mup[d];
+          tr += t0 * t0;
+          T2 -= (Real(kp[d]) - Real(kc[d])) * (eg[d] + egp[d]);
         }
+        S -= kL * tr + lzps;
       }
       S += T2;
       // 4. MH: accept iff  log ratio > log u  (eq. acc_prob: A > u); the MH word
@@ -763,10 +775,9 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
         if constexpr (LRN) {
           muL[d] = acc ? muLp[d] : muL[d];
           kLL[d] = acc ? kLLp[d] : kLL[d];
-        } else {
-          lz[d] = acc ? lzp[d] : lz[d];
         }
       }
+      if constexpr (!LRN) lzs = acc ? lzps : lzs;
       E = acc ? E - T2 * eunit : E;
       nacc += acc ? 1 : 0;
       if (E < Ebest) {
