@@ -363,8 +363,9 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
     return v;
   };
 
-  // [P; EG] x lv(k): accP/accE hold the lane's D outputs.
-  auto contract = [&](const int (&k)[D], Real (&accP)[D], Real (&accE)[D]) {
+  // [P; EG] x lv(k): accP/accE hold the lane's D outputs.  hook(rt) runs after the
+  // products of row tile rt are issued (independent work placed there overlaps them).
+  auto contract = [&](const int (&k)[D], Real (&accP)[D], Real (&accE)[D], auto&& hook) {
     if constexpr (F64) {
       __syncthreads();
 #pragma unroll
@@ -385,6 +386,8 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
         accP[d] = sp;
         accE[d] = se;
       }
+#pragma unroll
+      for (int rt = 0; rt < RTW; ++rt) hook(rt);
     } else {
       // B operand: this wave's K blocks from its own registers.  The packed
       // matrices are zero in the padding columns, so a padding dimension's
@@ -465,6 +468,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) accP[rt * 4 + i] = q[i];
           }
+          hook(rt);
           continue;
         }
 #pragma unroll
@@ -488,14 +492,17 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) accP[rt * 4 + i] = q[i];
         }
+        hook(rt);
+        __builtin_amdgcn_sched_barrier(0);   // keep the hook's work beside this tile's products
       }
     }
   };
 
   // Proposal centre and energy gradient at state k from the contraction.
-  auto grad_at = [&](const int (&k)[D], Real (&mu)[D], Real (&eg)[D]) {
+  auto nohook = [](int) {};
+  auto grad_at = [&](const int (&k)[D], Real (&mu)[D], Real (&eg)[D], auto&& hook) {
     Real accP[D], accE[D];
-    contract(k, accP, accE);
+    contract(k, accP, accE, hook);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int n = dim_of(d);
@@ -509,7 +516,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   };
   // ... and the log2 normalisers.
   auto proposal_at = [&](const int (&k)[D], Real (&mu)[D], Real (&lz)[D], Real (&eg)[D]) {
-    grad_at(k, mu, eg);
+    grad_at(k, mu, eg, nohook);
 #pragma unroll
     for (int d = 0; d < D; ++d) lz[d] = log2_norm<Q, WIN, W, TAB>(mu[d], kL, wc);
   };
@@ -599,9 +606,9 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
     if constexpr (LRN) {
       // the learned kernel alone (the mixture's other component is the plain kernel)
       Real muL[D], kLL[D], muLp[D], kLLp[D];
-      grad_at(kc, mu, eg);
+      grad_at(kc, mu, eg, nohook);
       learned_at(kc, mu, muL, kLL);
-      grad_at(kt, mup, egp);
+      grad_at(kt, mup, egp, nohook);
       learned_at(kt, mup, muLp, kLLp);
 #pragma unroll
       for (int d = 0; d < D; ++d)
@@ -652,10 +659,10 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
     Real muL[D], kLL[D];  // cached learned proposal (LRN)
     Real lzs = 0;         // sum of the lane's log2 normalisers at the current state (plain kernel)
     if constexpr (LRN) {
-      grad_at(kc, mu, eg);
+      grad_at(kc, mu, eg, nohook);
       learned_at(kc, mu, muL, kLL);
     } else {
-      grad_at(kc, mu, eg);
+      grad_at(kc, mu, eg, nohook);
 #pragma unroll
       for (int d = 0; d < D; ++d) lzs += log2_norm<Q, WIN, W, TAB>(mu[d], kL, wc);
     }
@@ -679,12 +686,24 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
     uint32_t abits = 0;
     const size_t trow = (size_t)rid * a.C + (live ? chain : 0);
 
-    for (int t = 1; t <= a.T; ++t) {
-      uint32_t w[RTW][4];
+    // Random words of transition t (counter (4 rt + h, t, chain, instance)).  They do not
+    // depend on the chain: on the one-wave layouts with up to 4 row tiles the words of
+    // t + 1 are generated while the contraction of t runs on the matrix cores (elsewhere
+    // the registers they would hold meanwhile are not free).
+    constexpr bool PIPE = !LRN && !F64 && WD == 1 && RTW <= 4;
+    uint32_t w[RTW][4];
+    auto word_block = [&](int rt, int tt) {
+      w[rt][0] = (uint32_t)(4 * (rt0 + rt) + h); w[rt][1] = (uint32_t)tt; w[rt][2] = (uint32_t)chain; w[rt][3] = rid;
+      philox4x32_10(w[rt], key0, key1);
+    };
+    if constexpr (PIPE) {
 #pragma unroll
-      for (int rt = 0; rt < RTW; ++rt) {
-        w[rt][0] = (uint32_t)(4 * (rt0 + rt) + h); w[rt][1] = (uint32_t)t; w[rt][2] = (uint32_t)chain; w[rt][3] = rid;
-        philox4x32_10(w[rt], key0, key1);
+      for (int rt = 0; rt < RTW; ++rt) word_block(rt, 1);
+    }
+    for (int t = 1; t <= a.T; ++t) {
+      if constexpr (!PIPE) {
+#pragma unroll
+        for (int rt = 0; rt < RTW; ++rt) word_block(rt, t);
       }
       // kernel choice of the mixture (LRN): learned unless the uniform from the
       // low bytes of words 4, 5, 6 falls below eps; every lane of the chain
@@ -719,6 +738,15 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
         }
       }
       if constexpr (!LRN) S = kL * tq + lzs;
+      // the MH word is held by the lanes that own dimensions 0..3 (h = 0 of the first slice)
+      const uint32_t um = low_bytes24(w[0][0], w[0][1], w[0][2]);
+      auto next_words = [&](int rt) {
+        if constexpr (PIPE) {
+          word_block(rt, t + 1);
+          // pin the block here: otherwise it is sunk to the end of the iteration
+          asm volatile("" : "+v"(w[rt][0]), "+v"(w[rt][1]), "+v"(w[rt][2]), "+v"(w[rt][3]));
+        }
+      };
       // 2-3. gradient at x', proposal at x', + log q(x|x'), energy term.
       // A padding dimension contributes nothing: its contraction rows are zero,
       // so mu' = mu, lz' = lz and its two log q terms cancel.
@@ -726,7 +754,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
       Real muLp[D], kLLp[D];
       Real T2 = 0;
       if constexpr (LRN) {
-        grad_at(kp, mup, egp);
+        grad_at(kp, mup, egp, next_words);
         learned_at(kp, mup, muLp, kLLp);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -737,7 +765,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
           T2 -= (Real(kp[d]) - Real(kc[d])) * (eg[d] + egp[d]);
         }
       } else {
-        grad_at(kp, mup, egp);
+        grad_at(kp, mup, egp, next_words);
         Real tr = 0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -749,10 +777,8 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
         S -= kL * tr + lzps;
       }
       S += T2;
-      // 4. MH: accept iff  log ratio > log u  (eq. acc_prob: A > u); the MH word
-      // is held by the lanes that own dimensions 0..3 (h = 0 of the first slice)
+      // 4. MH: accept iff  log ratio > log u  (eq. acc_prob: A > u)
       {
-        const uint32_t um = low_bytes24(w[0][0], w[0][1], w[0][2]);
         Real lu;
         if constexpr (F64) lu = lg2((double)um * 5.9604644775390625e-08);
         else lu = lg2((float)um * 5.9604644775390625e-08f);
@@ -875,7 +901,7 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
   // two waves per SIMD where the chain loop fits 256 registers without spilling: the learned
   // two-tile layouts, and the plain four-tile layouts (the evaluation kernels keep the default)
   constexpr bool kW2Eval = LRN && RTW == 2;
-  constexpr bool kW2 = kW2Eval || (!LRN && RTW == 4 && !std::is_same<Real, double>::value && (WD < 4 || WIN > 0));
+  constexpr bool kW2 = kW2Eval || (!LRN && RTW == 4 && !std::is_same<Real, double>::value && (WD < 4 || (WIN > 0 && PM != PM_NAIVE)));
   void (*k)(SamplerArgs);
   if (eval) {
     if constexpr (kW2Eval) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, true, WIN, LRN>;
