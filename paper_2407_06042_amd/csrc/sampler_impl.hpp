@@ -91,9 +91,11 @@ __device__ __forceinline__ void ctab_fill(float* ctab, float kL) {
 // ascending level order.  With delta = js - mu, F = exp2(-2 kL delta) and
 // G = 1 / F, the weight of level js + o is c_o F^o above the mode and c_o G^o
 // below it: two exponentials per dimension instead of one per level.
-// A side with a level in range has |2 kL delta| <= kL, so bounding both
-// exponents by kL changes no weight that is used and keeps F^3 and G^3 finite
-// (the window is used only for kL <= 40) where the table entry is zero.
+// |delta| is bounded by dmax = max(1/2, 12.5 / kL) for the exponentials: |delta|
+// exceeds 1/2 only at an edge mode, where the clamped side is out of range (table
+// entry zero) and the other side's weights stay below 2^-(kL+25) of the mode either
+// way, which leaves every fp32 sum unchanged; the bound keeps F^3 and G^3 finite
+// (the window is used only for kL <= 40).
 // The window is used only when 12 kL >= 30, so that every omitted level
 // weighs less than 2^-30 of the mode -- below the fp32 rounding of the sums,
 // i.e. invisible in fp32.
@@ -101,6 +103,7 @@ __device__ __forceinline__ void ctab_fill(float* ctab, float kL) {
 // full: one wave with 8 row tiles of matrices) c_o in registers with range tests.
 struct WinCoef {
   uint32_t tab;
+  float dmax;   // bound on |js - mu| for the two exponentials (table layouts)
   float c[4];
 };
 
@@ -111,11 +114,9 @@ __device__ __forceinline__ void window_weights(float mu, float kL, const WinCoef
   const float jf = mode_of<Q>(mu);
   js = (int)jf;
   delta = jf - mu;
-  const float x = 2.0f * kL * delta;
   if constexpr (TAB) {
-    const float F = ex2(-fmaxf(x, -kL));
-    const float G = ex2(fminf(x, kL));
-    // the row by its 32-bit LDS address (generic pointer arithmetic would be 64-bit)
+    // the row by its 32-bit LDS address (generic pointer arithmetic would be 64-bit),
+    // read before the exponentials so that they cover the LDS latency
     typedef float v4f __attribute__((ext_vector_type(4)));
     typedef float v2f __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(3))) const v4f lds_v4f;
@@ -123,6 +124,9 @@ __device__ __forceinline__ void window_weights(float mu, float kL, const WinCoef
     const uint32_t row = __umul24((uint32_t)js, (uint32_t)(kCtabStride * sizeof(float))) + wc.tab;   // one v_mad_u32_u24
     const v4f lo = *(lds_v4f*)(uintptr_t)row;         // c_3, c_2, c_1 below; c_1 above
     const v2f hi = *(lds_v2f*)(uintptr_t)(row + 16);  // c_2, c_3 above
+    const float x = 2.0f * kL * __builtin_amdgcn_fmed3f(delta, -wc.dmax, wc.dmax);
+    const float F = ex2(-x);
+    const float G = ex2(x);
     const float F2 = F * F, G2 = G * G;
     e[W] = 1.0f;
     e[W + 1] = lo.w * F;
@@ -132,6 +136,7 @@ __device__ __forceinline__ void window_weights(float mu, float kL, const WinCoef
     e[W + 3] = hi.y * (F2 * F);
     e[W - 3] = lo.x * (G2 * G);
   } else {
+    const float x = 2.0f * kL * delta;
     const float F = ex2(-x), G = ex2(x);
     float pf = 1.0f, pg = 1.0f;
     e[W] = 1.0f;
@@ -160,19 +165,23 @@ __device__ __forceinline__ void level_weights(R mu, R kL, R (&e)[Q], R& base) {
 // log2 of the proposal normaliser sum_j exp2(-kL (j - mu)^2) (eq. softmax).
 template <int Q, int WIN, int W, bool TAB, typename R>
 __device__ __forceinline__ R log2_norm(R mu, R kL, const WinCoef& wc) {
-  R Z = R(0), base;
+  // the sums start from the first weight, not from zero (0 + x is exact, and a
+  // zero start would cost a separate fused multiply-add)
+  R Z, base;
   if constexpr (WIN > 0) {
     R e[2 * W + 1];
     int js;
     window_weights<Q, W, TAB>(mu, kL, wc, e, js, base);
+    Z = e[0];
 #pragma unroll
-    for (int i = 0; i <= 2 * W; ++i) Z += e[i];
+    for (int i = 1; i <= 2 * W; ++i) Z += e[i];
     base *= base;
   } else {
     R e[Q];
     level_weights<Q>(mu, kL, e, base);
+    Z = e[0];
 #pragma unroll
-    for (int j = 0; j < Q; ++j) Z += e[j];
+    for (int j = 1; j < Q; ++j) Z += e[j];
   }
   return lg2(Z) - kL * base;
 }
@@ -186,14 +195,14 @@ __device__ __forceinline__ int draw_level(R mu, R kL, const WinCoef& wc, R u) {
     int js;
     R delta;
     window_weights<Q, W, TAB>(mu, kL, wc, e, js, delta);
-    R Z = R(0);
+    R Z = e[0];
 #pragma unroll
-    for (int i = 0; i <= 2 * W; ++i) Z += e[i];
+    for (int i = 1; i <= 2 * W; ++i) Z += e[i];
     const R target = u * Z;
-    R cum = R(0);
-    int cnt = 0;
+    R cum = e[0];
+    int cnt = (cum <= target) ? 1 : 0;
 #pragma unroll
-    for (int i = 0; i < 2 * W; ++i) {
+    for (int i = 1; i < 2 * W; ++i) {
       cum += e[i];
       cnt += (cum <= target) ? 1 : 0;
     }
@@ -309,6 +318,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   float* ctab_p = (float*)(mlp_lds + (LRN ? kMlpLdsBytes : 0));
   WinCoef wc;
   wc.tab = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) float*)ctab_p;
+  wc.dmax = fmaxf(0.5f, 12.5f / (float)ip.kL);
 #pragma unroll
   for (int o = 0; o < 4; ++o) wc.c[o] = ex2(-(float)ip.kL * float(o * o));
   if constexpr (LRN) mlp_stage(a.mlp, mlp_lds);
