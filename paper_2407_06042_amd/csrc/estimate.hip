@@ -24,6 +24,10 @@
 namespace dmala {
 
 __device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ float fex2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float flg2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ double fex2(double x) { return exp2(x); }
+__device__ __forceinline__ double flg2(double x) { return log2(x); }
 __device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
 __device__ __forceinline__ double fexp(double x) { return exp(x); }
 __device__ __forceinline__ double flog(double x) { return log(x); }
@@ -87,7 +91,8 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
   R* fs = rb2 + (size_t)CH * nr;                     // CH
   R* ebs = fs + CH;                                  // CH
   R* a2 = ebs + CH;                                  // nt
-  int8_t* Ks = (int8_t*)(a2 + nt);                   // CH x N
+  R* ys = a2 + nt;                                   // nr complex: y + s (Q-1) sum_m h_m
+  int8_t* Ks = (int8_t*)(ys + 2 * nr);               // CH x N
   int8_t* Kbs = Ks + (size_t)CH * N;                 // CH x N
   __shared__ R best_e;
   __shared__ int best_c;
@@ -96,7 +101,10 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
   // with a padded row (Ht[i][m], leading dimension nt + 1) so that both the
   // row-wise (residual) and the column-wise (H^H r) sweeps are conflict-free.
   const int ldh = nt + 1;
-  R* Ht = (R*)(((uintptr_t)(Kbs + (size_t)CH * N) + 15) & ~(uintptr_t)15);
+  // (an offset from the LDS array itself: a round trip through an integer address
+  // would leave a generic pointer, and flat loads, for every read of H)
+  const size_t ht_off = ((size_t)((const unsigned char*)(Kbs + (size_t)CH * N) - esm) + 15) & ~(size_t)15;
+  R* Ht = (R*)(esm + ht_off);
   if constexpr (SH) {
     for (int e = tid; e < nt * nr; e += nth) {
       const int m = e / nr, i = e % nr;
@@ -108,8 +116,15 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
   auto hre = [&](int m, int i) -> R { if constexpr (SH) return Ht[2 * (i * ldh + m)]; else return Hg[2 * ((size_t)m * nr + i)]; };
   auto him = [&](int m, int i) -> R { if constexpr (SH) return Ht[2 * (i * ldh + m) + 1]; else return Hg[2 * ((size_t)m * nr + i) + 1]; };
 
-  auto level = [&](int k) { return s * R(2 * k - Q + 1); };
-
+  // With the symbol x_m = s ((2 kI - Q + 1) + j (2 kQ - Q + 1)) of level indices k the
+  // residual is r = y - H x = y' - 2 s H k, k_m = kI + j kQ, y' = y + s (Q - 1) (1 + j)
+  // sum_m h_m: the level indices enter the products directly.
+  for (int i = tid; i < nr; i += nth) {
+    R sr = 0, si = 0;
+    for (int m = 0; m < nt; ++m) { sr += hre(m, i) - him(m, i); si += hre(m, i) + him(m, i); }
+    ys[2 * i] = y[2 * i] + s * R(Q - 1) * sr;
+    ys[2 * i + 1] = y[2 * i + 1] + s * R(Q - 1) * si;
+  }
   for (int m = tid; m < nt; m += nth) {
     R g = 0;
     for (int i = 0; i < nr; ++i) {
@@ -152,7 +167,12 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
 
   for (int rb = 0; rb < n_rb; ++rb) {
     const int row = rb * nth + tid;
-    OnlineLse<R> acc[Q];
+    // row sums sum_c 2^(v_c(kQ) - Mx) (log2 units) with one running maximum Mx for the
+    // row: a point more than 2^-126 below the row's largest term underflows to zero,
+    // as it would in the normalised marginal anyway
+    R Mx = R(-INFINITY), sums[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) sums[j] = R(0);
     int cnt[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) cnt[j] = 0;
@@ -170,17 +190,23 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
         // residuals of the final and of the best states
         for (int it = tid; it < ch * nr; it += nth) {
           const int c = it / nr, i = it % nr;
-          R re = y[2 * i], im = y[2 * i + 1];
-          R bre = re, bim = im;
+          const uint16_t* kf = (const uint16_t*)(Ks + c * N);   // (k_I, k_Q) of antenna m, as bytes
+          const uint16_t* kb = (const uint16_t*)(Kbs + c * N);
+          R re = 0, im = 0, bre = 0, bim = 0;
           for (int m = 0; m < nt; ++m) {
             const R hr = hre(m, i), hi = him(m, i);
-            const R xr = level(Ks[c * N + 2 * m]), xi = level(Ks[c * N + 2 * m + 1]);
-            re -= hr * xr - hi * xi;
-            im -= hr * xi + hi * xr;
-            const R br = level(Kbs[c * N + 2 * m]), bi = level(Kbs[c * N + 2 * m + 1]);
-            bre -= hr * br - hi * bi;
-            bim -= hr * bi + hi * br;
+            const uint32_t f = kf[m], g = kb[m];
+            const R xr = R(f & 0xFFu), xi = R(f >> 8), br = R(g & 0xFFu), bi = R(g >> 8);
+            re += hr * xr - hi * xi;
+            im += hr * xi + hi * xr;
+            bre += hr * br - hi * bi;
+            bim += hr * bi + hi * br;
           }
+          const R s2 = R(2) * s;
+          re = ys[2 * i] - s2 * re;
+          im = ys[2 * i + 1] - s2 * im;
+          bre = ys[2 * i] - s2 * bre;
+          bim = ys[2 * i + 1] - s2 * bim;
           rs[2 * it] = re;
           rs[2 * it + 1] = im;
           rb2[it] = bre * bre + bim * bim;
@@ -233,15 +259,25 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
       if (row < n_rows) {
         const int m = row / Q, kIt = row % Q;
         const R q2 = a2[m];
+        const R l2e = R(1.4426950408889634), q2l = q2 * l2e;
         for (int c = 0; c < ch; ++c) {
           const CM<R> v = cm[c * nt + m];
           const R eI = R(kIt - v.kI);
-          const R b0 = v.base + eI * (v.aI - q2 * eI);
+          const R b0 = (v.base + eI * (v.aI - q2 * eI)) * l2e;
+          const R aQl = v.aQ * l2e;
+          R val[Q];
+          R lm = R(-INFINITY);
 #pragma unroll
           for (int kQt = 0; kQt < Q; ++kQt) {
             const R eQ = R(kQt - v.kQ);
-            acc[kQt].add(b0 + eQ * (v.aQ - q2 * eQ));
+            val[kQt] = b0 + eQ * (aQl - q2l * eQ);
+            lm = val[kQt] > lm ? val[kQt] : lm;
           }
+          const R Mn = lm > Mx ? lm : Mx;
+          const R sc = fex2(Mx - Mn);
+#pragma unroll
+          for (int kQt = 0; kQt < Q; ++kQt) sums[kQt] = sums[kQt] * sc + fex2(val[kQt] - Mn);
+          Mx = Mn;
           if (want_mc) {
 #pragma unroll
             for (int kQt = 0; kQt < Q; ++kQt) cnt[kQt] += (v.kI == kIt && v.kQ == kQt) ? 1 : 0;
@@ -291,7 +327,10 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
       R lv[Q];
       R mx = R(-INFINITY);
 #pragma unroll
-      for (int j = 0; j < Q; ++j) { lv[j] = acc[j].value(); mx = lv[j] > mx ? lv[j] : mx; }
+      for (int j = 0; j < Q; ++j) {
+        lv[j] = (Mx + flg2(sums[j])) * R(0.6931471805599453);
+        mx = lv[j] > mx ? lv[j] : mx;
+      }
 #pragma unroll
       for (int off = 1; off < Q; off <<= 1) { const R o = __shfl_xor(mx, off); mx = o > mx ? o : mx; }
       R sm = R(0);
@@ -349,7 +388,7 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
 size_t estimate_lds_bytes(int nt, int nr, int M, int N, int chunk, bool fp64) {
   const size_t R = fp64 ? 8 : 4;
   const size_t cm = fp64 ? 32 : 20;
-  return cm * (size_t)chunk * nt + R * (3 * (size_t)chunk * nr + 2 * (size_t)chunk + nt) +
+  return cm * (size_t)chunk * nt + R * (3 * (size_t)chunk * nr + 2 * (size_t)chunk + nt + 2 * (size_t)nr) +
          2 * (size_t)chunk * N + 16;
 }
 
