@@ -145,7 +145,7 @@ __global__ __launch_bounds__(BS) void setup_kernel(SetupArgs a) {
   // its (m, m2) entries (and entries of z) in registers across the chunks.
   double nonfinite = 0.0;
   {
-    constexpr int kIC = 32, kEPT = BS >= 1024 ? 5 : 17;  // entries per thread per group
+    constexpr int kIC = 32, kEPT = 5;  // entries per thread per group (one group up to nt = 32 at 256 threads, 64 at 1024)
     typedef cd tc;
     tc* Ht = (tc*)(red + BS);           // kIC x (nt + 1)
     tc* yc = Ht + kIC * ld;              // kIC
