@@ -48,6 +48,14 @@ __device__ double block_reduce(double v, double* red, bool is_max) {
   return r;
 }
 
+// double -> float in hardware, kept as a separate step: the compiler would otherwise
+// fold the two conversions to half (or bfloat16) into one emulated in software.
+__device__ __forceinline__ float via_float(double v) {
+  float f = (float)v;
+  asm volatile("" : "+v"(f));
+  return f;
+}
+
 // Pack c * R(X) (N x N, zero-padded to Npad) into MFMA fragments.
 // npass = 3 (fp16 lo, mid, hi), 2 (fp16 lo, hi) or 1 (fp16 or bf16 when bf16 != 0);
 // the terms are stored in accumulation order, small terms first.
@@ -81,13 +89,13 @@ __device__ float pack_fragments(const cd* X, int ld, double c, int nt, int N, in
       const int n2 = 16 * (2 * kb + (j >> 2)) + 4 * (l >> 4) + (j & 3);
       const double v = (n < N && n2 < N) ? sc * realeq(X, ld, n, n2) : 0.0;
       if (bf16) {
-        f0.b[j] = (__bf16)(float)v;
+        f0.b[j] = (__bf16)via_float(v);
       } else {
-        const _Float16 hi = (_Float16)(float)v;
+        const _Float16 hi = (_Float16)via_float(v);
         const double r1 = v - (double)hi;
-        const _Float16 mid = (_Float16)(float)r1;
+        const _Float16 mid = (_Float16)via_float(r1);
         const double r2 = r1 - (double)mid;
-        if (npass == 3) { f0.h[j] = (_Float16)(float)r2; f1.h[j] = mid; f2.h[j] = hi; }
+        if (npass == 3) { f0.h[j] = (_Float16)via_float(r2); f1.h[j] = mid; f2.h[j] = hi; }
         else if (npass == 2) { f0.h[j] = mid; f1.h[j] = hi; }
         else f0.h[j] = hi;
       }
