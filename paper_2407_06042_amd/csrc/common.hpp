@@ -163,16 +163,24 @@ int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64);
 
 // ------------------------------------------------------------------ device helpers
 
+// a ^ b ^ k as one three-input bit operation (truth table 0x96; the compiler emits
+// two xors).  k must be wave-uniform: it is bound to a scalar register.
+__device__ __forceinline__ uint32_t xor3_uniform(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
+
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the 4x32 S-box, key bumped
-// by the Weyl constants between rounds.
+// by the Weyl constants between rounds.  The key (k0, k1) must be wave-uniform.
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
     const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    const uint32_t n0 = xor3_uniform((uint32_t)(p1 >> 32), c[1], k0);
+    const uint32_t n2 = xor3_uniform((uint32_t)(p0 >> 32), c[3], k1);
     c[0] = n0; c[1] = (uint32_t)p1; c[2] = n2; c[3] = (uint32_t)p0;
   }
 }
