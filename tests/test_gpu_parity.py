@@ -183,6 +183,48 @@ def test_device_kernel_detailed_balance(precision, nt, M):
     np.testing.assert_allclose(DF, fo[None, :] - fo[:, None], atol=ftol * max(1.0, np.abs(fo).max()))
 
 
+def _proposal_centres(prob, K):
+    """Continuous centres (index units) of the oracle's quadratic proposal logits, per state and dimension."""
+    lg = prob.proposal_logits(prob.x_of(K))
+    a = (lg[:, :, 2] - 2 * lg[:, :, 1] + lg[:, :, 0]) / 2
+    return -(lg[:, :, 1] - lg[:, :, 0] - a) / (2 * a)
+
+
+@pytest.mark.parametrize("M,snr,shift", [(64, 6.0, 0.0), (64, 30.0, 0.0), (64, 30.0, 8.0), (64, 30.0, -8.0),
+                                         (256, 30.0, 8.0)])
+def test_windowed_proposal_matches_oracle(M, snr, shift):
+    """The 3-level window of the fp32 proposal (Q >= 8) with its per-mode coefficient table: log q(x'|x)
+    for every state pair of a 1x2 system equals the oracle's exact discretised Gaussian.  With y moved
+    along h by shift (1 + j) (a received vector far outside the constellation) the proposal centres lie
+    many levels outside [0, Q): edge modes with |mode - centre| > 1/2, where the bound on the window's
+    exponentials applies; a negative shift puts them below the lowest level."""
+    import torch
+    import paper_2407_06042_amd as dm
+    b = W.make_batch(1, 2, M, snr, 1, seed=90 + M + int(snr)).as_precision(np.float32)
+    b.y[0] = (b.y[0] + b.H[0][:, 0] * shift * (1 + 1j)).astype(b.y.dtype)
+    prob = odm.Problem(b.H[0], b.y[0], b.sigma2[0], M)
+    K = exact.all_states(prob.N, prob.Q)
+    S = len(K)
+    mu = _proposal_centres(prob, K)
+    outside = float(np.mean((mu < -0.5) | (mu > prob.Q - 0.5)))
+    if shift > 0:
+        # most centres outside, some beyond the bound max(1/2, 12.5 / kL) = 4.33 levels (kL = 2 log2 e)
+        assert outside > 0.5 and mu.max() > prob.Q - 1 + 12.5 / (2 * np.log2(np.e))
+    if shift < 0:
+        assert outside > 0.5 and mu.min() < -12.5 / (2 * np.log2(np.e))
+    per = 1024
+    rep = (S * S) // per
+    xf = np.repeat(K, S, axis=0).reshape(rep, per, -1)
+    xt = np.tile(K, (S, 1)).reshape(rep, per, -1)
+    Hcm, y, s2 = dm.device_inputs(np.repeat(b.H, rep, 0), np.repeat(b.y, rep, 0), np.repeat(b.sigma2, rep, 0))
+    out = dm.debug_eval(Hcm, y, s2, M, torch.from_numpy(xf).cuda(), torch.from_numpy(xt).cuda()).cpu().numpy()
+    LQ = out.reshape(S * S, 4)[:, 0].reshape(S, S)
+    _, LQo, _ = exact.transition_matrix(prob, K)
+    _print("window", M=M, snr=snr, shift=shift, outside=outside, err=float(np.abs(LQ - LQo).max()),
+           scale=float(np.abs(LQo).max()))
+    np.testing.assert_allclose(LQ, LQo, rtol=1e-4, atol=1e-4 * max(1.0, np.abs(LQo).max()))
+
+
 @pytest.mark.parametrize("nt,M,rho,snr,C,T,tile", [
     (48, 64, 0.0, 20.0, 32, 30, 0),      # 96 dims padded to 128, automatic layout
     (64, 64, 0.0, 22.0, 32, 30, 3),      # one wave per 16 chains, matrices in LDS
