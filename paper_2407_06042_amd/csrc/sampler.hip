@@ -47,7 +47,7 @@ int sampler_default_cfg(const Shape& sh) {
   switch (sh.RT) {
     case 2: return 0;
     case 4: return sh.lrn ? 5 : 1;
-    case 8: return sh.lrn ? 6 : (sampler_cfg_valid(sh, 2) ? 2 : 3);
+    case 8: return sh.lrn ? 6 : 3;   // two waves of 4 tiles at two waves per SIMD beat one wave of 8 tiles
     case 16: return 4;
   }
   return -1;
