@@ -253,7 +253,7 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-per-snr", type=int, default=12)
+    ap.add_argument("--cpu-per-snr", type=int, default=24)
     ap.add_argument("--forms", default="fp32,bf16", help="comma list; the first is the reported value")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference kernel for HBM counters)")
