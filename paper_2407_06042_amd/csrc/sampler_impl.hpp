@@ -163,11 +163,12 @@ __device__ __forceinline__ void level_weights(R mu, R kL, R (&e)[Q], R& base) {
 }
 
 // log2 of the proposal normaliser sum_j exp2(-kL (j - mu)^2) (eq. softmax).
+// Its two parts: the weight sum Z relative to the mode (1 <= Z <= Q) and the squared
+// mode offset base, log2 normaliser = log2 Z - kL base.
 template <int Q, int WIN, int W, bool TAB, typename R>
-__device__ __forceinline__ R log2_norm(R mu, R kL, const WinCoef& wc) {
+__device__ __forceinline__ void norm_parts(R mu, R kL, const WinCoef& wc, R& Z, R& base) {
   // the sums start from the first weight, not from zero (0 + x is exact, and a
   // zero start would cost a separate fused multiply-add)
-  R Z, base;
   if constexpr (WIN > 0) {
     R e[2 * W + 1];
     int js;
@@ -183,6 +184,12 @@ __device__ __forceinline__ R log2_norm(R mu, R kL, const WinCoef& wc) {
 #pragma unroll
     for (int j = 1; j < Q; ++j) Z += e[j];
   }
+}
+
+template <int Q, int WIN, int W, bool TAB, typename R>
+__device__ __forceinline__ R log2_norm(R mu, R kL, const WinCoef& wc) {
+  R Z, base;
+  norm_parts<Q, WIN, W, TAB>(mu, kL, wc, Z, base);
   return lg2(Z) - kL * base;
 }
 
@@ -776,14 +783,21 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
         }
       } else {
         grad_at(kp, mup, egp, next_words);
-        Real tr = 0;
+        // sum of the lane's log2 normalisers as log2 of the product of the weight sums
+        // (each in [1, Q], so the product of D of them stays far inside the exponent
+        // range): one logarithm per lane instead of one per dimension
+        Real tr = 0, zp = 1, bs = 0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          lzps += log2_norm<Q, WIN, W, TAB>(mup[d], kL, wc);
+          Real Z, b2;
+          norm_parts<Q, WIN, W, TAB>(mup[d], kL, wc, Z, b2);
+          zp *= Z;
+          bs += b2;
           const Real t0 = Real(kc[d]) - mup[d];
           tr += t0 * t0;
           T2 -= (Real(kp[d]) - Real(kc[d])) * (eg[d] + egp[d]);
         }
+        lzps = lg2(zp) - kL * bs;
         S -= kL * tr + lzps;
       }
       S += T2;
