@@ -44,12 +44,6 @@ struct OnlineLse {
   __device__ R value() const { return mx + flog(sum); }
 };
 
-template <typename R>
-__device__ __forceinline__ R softplus(R a) {  // log(1 + e^a)
-  const R z = fexp(-fabs(a));
-  return (a > R(0) ? a : R(0)) + flog(R(1) + z);
-}
-
 __device__ __forceinline__ int ungray(int g) {
   g ^= g >> 1; g ^= g >> 2; g ^= g >> 4;
   return g;
@@ -303,8 +297,11 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
                 const R Fp = fs[c] + ep * (av - q2 * ep);
                 const R Fm = fs[c] + em * (av - q2 * em);
                 const R gm = (Fp - Fm) * inv_tau;
-                lnum[q].add(cw * Fp - softplus(-gm));
-                lden[q].add(cw * Fm - softplus(gm));
+                // F(gm) and F(-gm), F(a) = log(1 + e^a), share log(1 + e^-|gm|) and differ by
+                // max(gm, 0) vs max(-gm, 0)
+                const R l1 = flog(R(1) + fexp(-fabs(gm)));
+                lnum[q].add(cw * Fp - ((gm < R(0) ? -gm : R(0)) + l1));
+                lden[q].add(cw * Fm - ((gm > R(0) ? gm : R(0)) + l1));
               } else {
                 const bool plus = (g & mask) == 0;   // label bit 0 <-> b = +1
                 if (mode == 1) {
