@@ -172,15 +172,25 @@ __device__ __forceinline__ uint32_t xor3_uniform(uint32_t a, uint32_t b, uint32_
 }
 
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the 4x32 S-box, key bumped
-// by the Weyl constants between rounds.  The key (k0, k1) must be wave-uniform.
+// by the Weyl constants between rounds.  BITOP3: the xors as three-input bit
+// operations (the key (k0, k1) must then be wave-uniform); they pay on the
+// one-wave layouts, while on the dimension-split layouts the pinned asm slows
+// the schedule down.
+template <bool BITOP3>
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
     const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-    const uint32_t n0 = xor3_uniform((uint32_t)(p1 >> 32), c[1], k0);
-    const uint32_t n2 = xor3_uniform((uint32_t)(p0 >> 32), c[3], k1);
+    uint32_t n0, n2;
+    if constexpr (BITOP3) {
+      n0 = xor3_uniform((uint32_t)(p1 >> 32), c[1], k0);
+      n2 = xor3_uniform((uint32_t)(p0 >> 32), c[3], k1);
+    } else {
+      n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+      n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    }
     c[0] = n0; c[1] = (uint32_t)p1; c[2] = n2; c[3] = (uint32_t)p0;
   }
 }

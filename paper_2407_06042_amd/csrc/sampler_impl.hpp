@@ -293,6 +293,9 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   constexpr int NPP = p_passes(PM);
   constexpr int QM1 = Q - 1;
   constexpr int W = WIN > 0 ? WIN : Q - 1;
+  // one-wave layouts with up to 4 row tiles: the next transition's random words are
+  // generated beside the contraction, with three-input xors in the Philox rounds
+  constexpr bool PIPE = !LRN && !F64 && WD == 1 && RTW <= 4;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
   const int inst = blockIdx.x;                            // index within this launch (workspace slot)
@@ -669,7 +672,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
 #pragma unroll
     for (int rt = 0; rt < RTW; ++rt) {
       uint32_t c[4] = {(uint32_t)(4 * (rt0 + rt) + h), 0u, (uint32_t)chain, rid};
-      philox4x32_10(c, key0, key1);
+      philox4x32_10<PIPE>(c, key0, key1);
 #pragma unroll
       for (int i = 0; i < 4; ++i) kc[rt * 4 + i] = (int)(((uint64_t)(c[i] >> 8) * Q) >> 24);
     }
@@ -707,11 +710,10 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
     // depend on the chain: on the one-wave layouts with up to 4 row tiles the words of
     // t + 1 are generated while the contraction of t runs on the matrix cores (elsewhere
     // the registers they would hold meanwhile are not free).
-    constexpr bool PIPE = !LRN && !F64 && WD == 1 && RTW <= 4;
     uint32_t w[RTW][4];
     auto word_block = [&](int rt, int tt) {
       w[rt][0] = (uint32_t)(4 * (rt0 + rt) + h); w[rt][1] = (uint32_t)tt; w[rt][2] = (uint32_t)chain; w[rt][3] = rid;
-      philox4x32_10(w[rt], key0, key1);
+      philox4x32_10<PIPE>(w[rt], key0, key1);
     };
     if constexpr (PIPE) {
 #pragma unroll
@@ -728,7 +730,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
       bool useL = false;
       if constexpr (LRN) {
         uint32_t wm[4] = {1u, (uint32_t)t, (uint32_t)chain, rid};
-        philox4x32_10(wm, key0, key1);
+        philox4x32_10<PIPE>(wm, key0, key1);
         useL = low_bytes24(wm[0], wm[1], wm[2]) >= a.mix_thr;
       }
       // 1. draw x' (padding dimensions never move) and -log q(x'|x); the plain
