@@ -111,7 +111,8 @@ typedef struct {
   double alpha_mult;         /* alpha = alpha_mult * sigma^2;          <= 0 selects 1 */
   double beta_mult;          /* beta  = beta_mult * dmin^2 / sigma^2;  <= 0 selects 1 */
   double gamma_mult;         /* gamma = gamma_mult * sigma^2 / (2 dmin^2); <= 0 selects 1 */
-  int32_t tile_config;       /* sampler work layout: 0 = automatic; k >= 1 selects layout k - 1:
+  int32_t tile_config;       /* sampler work layout: 0 = automatic (32 dims: layout 0, 64: 1, 128: 3,
+                                256: 4; LEARNED 64: 5, 128: 6); k >= 1 selects layout k - 1:
                                 0: 32 dims, 1 wave / 16 chains, matrices in LDS
                                 1: 64 dims, 1 wave / 16 chains, LDS
                                 2: 128 dims, 1 wave / 16 chains, LDS
