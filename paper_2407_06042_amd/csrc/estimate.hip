@@ -287,11 +287,12 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
             const int m = it / (2 * NB), ax = (it / NB) % 2, bit = it % NB;
             const int mask = 1 << (NB - 1 - bit);
             const R q2 = a2[m];
-            for (int c = 0; c < ch; ++c) {
-              const CM<R> v = cm[c * nt + m];
-              const int k = ax ? v.kQ : v.kI;
-              const int g = k ^ (k >> 1);
-              if (mode == 0) {
+            // one loop per form (the form is uniform: no branch inside the chain loop)
+            if (mode == 0) {
+              for (int c = 0; c < ch; ++c) {
+                const CM<R> v = cm[c * nt + m];
+                const int k = ax ? v.kQ : v.kI;
+                const int g = k ^ (k >> 1);
                 const R av = ax ? v.aQ : v.aI;
                 const R ep = R(ungray(g & ~mask) - k), em = R(ungray(g | mask) - k);
                 const R Fp = fs[c] + ep * (av - q2 * ep);
@@ -302,16 +303,22 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
                 const R l1 = flog(R(1) + fexp(-fabs(gm)));
                 lnum[q].add(cw * Fp - ((gm < R(0) ? -gm : R(0)) + l1));
                 lden[q].add(cw * Fm - ((gm > R(0) ? gm : R(0)) + l1));
-              } else {
-                const bool plus = (g & mask) == 0;   // label bit 0 <-> b = +1
-                if (mode == 1) {
-                  if (!dupf[c0 + c]) {
-                    if (plus) lnum[q].add(fs[c]);
-                    else lden[q].add(fs[c]);
-                  }
-                } else {
-                  cplus[q] += plus ? 1 : 0;
+              }
+            } else if (mode == 1) {
+              for (int c = 0; c < ch; ++c) {
+                const CM<R> v = cm[c * nt + m];
+                const int k = ax ? v.kQ : v.kI;
+                const bool plus = ((k ^ (k >> 1)) & mask) == 0;   // label bit 0 <-> b = +1
+                if (!dupf[c0 + c]) {
+                  if (plus) lnum[q].add(fs[c]);
+                  else lden[q].add(fs[c]);
                 }
+              }
+            } else {
+              for (int c = 0; c < ch; ++c) {
+                const CM<R> v = cm[c * nt + m];
+                const int k = ax ? v.kQ : v.kI;
+                cplus[q] += (((k ^ (k >> 1)) & mask) == 0) ? 1 : 0;
               }
             }
           }
