@@ -173,9 +173,13 @@ __device__ __forceinline__ void norm_parts(R mu, R kL, const WinCoef& wc, R& Z, 
     R e[2 * W + 1];
     int js;
     window_weights<Q, W, TAB>(mu, kL, wc, e, js, base);
-    Z = e[0];
+    // from the mode outwards: every other weight's product fuses into the sum
+    Z = e[W];
 #pragma unroll
-    for (int i = 1; i <= 2 * W; ++i) Z += e[i];
+    for (int o = 1; o <= W; ++o) {
+      Z += e[W - o];
+      Z += e[W + o];
+    }
     base *= base;
   } else {
     R e[Q];
