@@ -35,6 +35,31 @@ __device__ __forceinline__ double realeq(const cd* X, int ld, int n, int n2) {
 }
 __device__ __forceinline__ double realeq_vec(const cd* v, int n) { return (n & 1) ? v[n >> 1].im : v[n >> 1].re; }
 
+// Value of v in lane `lane` of the wavefront (lane uniform).
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Four complex entries 16 TPR bytes apart from LDS address a, waited for in
+// the same block: the Gauss-Jordan update keeps four row entries in flight
+// (the compiler would otherwise load all of them at once and spill the matrix).
+typedef double d2v __attribute__((ext_vector_type(2)));
+template <int TPR>
+__device__ __forceinline__ void lds_read4(uint32_t a, d2v (&r)[4]) {
+  asm volatile(
+      "ds_read2_b64 %0, %4 offset1:1\n\t"
+      "ds_read2_b64 %1, %4 offset0:%5 offset1:%6\n\t"
+      "ds_read2_b64 %2, %4 offset0:%7 offset1:%8\n\t"
+      "ds_read2_b64 %3, %4 offset0:%9 offset1:%10\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3])
+      : "v"(a), "i"(2 * TPR), "i"(2 * TPR + 1), "i"(4 * TPR), "i"(4 * TPR + 1), "i"(6 * TPR), "i"(6 * TPR + 1)
+      : "memory");
+}
+
 __device__ double block_reduce(double v, double* red, bool is_max) {
   const int tid = threadIdx.x;
   red[tid] = v;
@@ -242,15 +267,22 @@ __global__ __launch_bounds__(BS) void setup_kernel(SetupArgs a) {
     for (int m = tid; m < nt; m += blockDim.x) W[m * ld + m].re += gamma;
     __syncthreads();
     // Gauss-Jordan with the working matrix in registers: thread t keeps row
-    // t / TPR, columns t % TPR + TPR k (k < KMAX), for the whole sweep.  Step p:
-    // the owners of column p publish it (colp), the owners of row p publish the row
-    // scaled by the pivot inverse (rowp, with the inverse itself in column p), and
-    // every other row i subtracts colp[i] * rowp, column p counting as zero so that
-    // it receives -colp[i] * inv.  The two vectors alternate between steps, so two
-    // barriers per step order all reads and writes.
+    // t / TPR, columns t % TPR + TPR k (k < KMAX), for the whole sweep.  A step on
+    // pivot p: the owners of column p publish it (colp); the threads of row p,
+    // which share a wavefront with the pivot, read the pivot from its lane, scale
+    // their row by its inverse (the inverse itself in column p) and publish it
+    // (rowp); after one barrier every other row i clears its column p and
+    // subtracts colp[i] * rowp, which leaves -w_ip / w_pp there.  The steps on
+    // different pivots commute (G + gamma I is Hermitian positive definite, so
+    // every pivot stays nonzero in any order), so they run in the order
+    // p = o + TPR kb, o outer: column p then sits in register slot kb, a
+    // compile-time index of the unrolled inner loop.  The two vectors alternate
+    // between steps, so one barrier per step orders all reads and writes.
     constexpr int RMAX = WGLOB ? 128 : (BS >= 1024 ? 64 : 32);  // rows covered (nt <= RMAX)
     constexpr int TPR = BS / RMAX;                               // threads per row
     constexpr int KMAX = RMAX / TPR;                             // columns per thread
+    static_assert(64 % TPR == 0, "the threads of a row share a wavefront");
+    static_assert(KMAX % 4 == 0 && 6 * TPR + 1 < 256, "row entries are read four at a time");
     const int gi = tid / TPR, gj = tid % TPR;
     cd w[KMAX];
 #pragma unroll
@@ -258,40 +290,50 @@ __global__ __launch_bounds__(BS) void setup_kernel(SetupArgs a) {
       const int j = gj + TPR * k;
       w[k] = (gi < nt && j < nt) ? W[gi * ld + j] : cd{0.0, 0.0};
     }
-    for (int p = 0; p < nt; ++p) {
-      cd* rp = rowp + (p & 1) * nt;
-      cd* cp = colp + (p & 1) * nt;
-      const int kp = p / TPR;
-      if (gi < nt && gj == p % TPR) {
+    int par = 0;
+#pragma unroll 1
+    for (int o = 0; o < TPR && o < nt; ++o) {
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-          if (k == kp) cp[gi] = w[k];
-      }
-      __syncthreads();
-      if (gi == p) {
-        const cd piv = cp[p];
-        const double den = piv.re * piv.re + piv.im * piv.im;
-        const cd inv = {piv.re / den, -piv.im / den};
+      for (int kb = 0; kb < KMAX; ++kb) {
+        const int p = o + TPR * kb;
+        if (p < nt) {
+          cd* rp = rowp + par * nt;
+          cd* cp = colp + par * nt;
+          par ^= 1;
+          if (gi < nt && gj == o) cp[gi] = w[kb];
+          if (gi == p) {
+            const int lane = (p * TPR + o) & 63;
+            const cd piv = {readlane_f64(w[kb].re, lane), readlane_f64(w[kb].im, lane)};
+            const double rd = 1.0 / (piv.re * piv.re + piv.im * piv.im);
+            const cd inv = {piv.re * rd, -piv.im * rd};
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-          const int j = gj + TPR * k;
-          if (j < nt) rp[j] = (j == p) ? inv : cmul(w[k], inv);
-        }
-      }
-      __syncthreads();
-      if (gi < nt) {
-        const cd ci = cp[gi];
+            for (int k = 0; k < KMAX; ++k) w[k] = cmul(w[k], inv);
+            if (gj == o) w[kb] = inv;
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-          const int j = gj + TPR * k;
-          if (j < nt) {
-            const cd sr = rp[j];
-            if (gi == p) {
-              w[k] = sr;
-            } else {
-              const cd t = cmul(ci, sr);
-              const cd w0 = (j == p) ? cd{0.0, 0.0} : w[k];
-              w[k] = {w0.re - t.re, w0.im - t.im};
+            for (int k = 0; k < KMAX; ++k) {
+              const int j = gj + TPR * k;
+              if (j < nt) rp[j] = w[k];
+            }
+          }
+          __syncthreads();
+          if (gi < nt && gi != p) {
+            const cd ci = cp[gi];
+            if (gj == o) w[kb] = {0.0, 0.0};
+            // entries past column nt - 1 read whatever follows rowp in LDS (inside the
+            // allocation); they are never stored
+            const uint32_t ra = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) cd*)(rp + gj);
+#pragma unroll
+            for (int k0 = 0; k0 < KMAX; k0 += 4) {
+              if (TPR * k0 < nt) {
+                d2v r[4];
+                lds_read4<TPR>(ra + 16 * TPR * k0, r);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  cd& v = w[k0 + q];
+                  v.re = fma(-ci.re, r[q].x, fma(ci.im, r[q].y, v.re));
+                  v.im = fma(-ci.re, r[q].y, fma(-ci.im, r[q].x, v.im));
+                }
+              }
             }
           }
         }
