@@ -178,50 +178,91 @@ __global__ __launch_bounds__(BS) void setup_kernel(SetupArgs a) {
   // its (m, m2) entries (and entries of z) in registers across the chunks.
   double nonfinite = 0.0;
   {
-    constexpr int kIC = 32, kEPT = 5;  // entries per thread per group (one group up to nt = 32 at 256 threads, 64 at 1024)
-    typedef cd tc;
-    tc* Ht = (tc*)(red + BS);           // kIC x (nt + 1)
-    tc* yc = Ht + kIC * ld;              // kIC
-    const int total = nt * nt + nt;
-    for (int e0 = 0; e0 < total; e0 += kEPT * (int)blockDim.x) {  // groups of entries held in registers
-      double are[kEPT], aim[kEPT];
+    // H is staged in LDS in chunks of receive antennas, transposed with a padded
+    // row whose last entry holds y (Ht[i][m], Ht[i][nt] = y_i), so that z is one
+    // more column of the product: z_m = (H^H [H y])_{m, nt}.  Each thread
+    // accumulates a 2 x 2 block of entries in registers across the chunks; only
+    // blocks on or above the diagonal and the blocks of the z column are
+    // computed, and the lower triangle is written as the conjugate.
+    constexpr int kIC = 32;
+    constexpr int kBPT = WGLOB ? 3 : 1;     // blocks per thread per group (one group up to nt = 128)
+    cd* Ht = (cd*)(red + BS);               // kIC x ld, then one spare row read past the last column
+    const int nb = (nt + 1) >> 1;           // 2-row blocks
+    const int nbu = nb * (nb + 1) / 2;      // blocks on or above the diagonal
+    const int nblk = nbu + nb;              // ... and the z column
+    for (int b0 = 0; b0 < nblk; b0 += kBPT * BS) {
+      int m[kBPT], m2[kBPT];
+      cd acc[kBPT][2][2];
 #pragma unroll
-      for (int q = 0; q < kEPT; ++q) { are[q] = 0.0; aim[q] = 0.0; }
+      for (int q = 0; q < kBPT; ++q) {
+        int bi = b0 + tid + q * BS;
+        if (bi < nbu) {           // upper block (br, bc), bc >= br, row-major over the triangle
+          int br = 0;
+          while (bi >= nb - br) { bi -= nb - br; ++br; }
+          m[q] = 2 * br;
+          m2[q] = 2 * (br + bi);
+        } else {                  // z block (past nblk: idle)
+          m[q] = 2 * (bi - nbu);
+          m2[q] = nt;
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) acc[q][r][c] = {0.0, 0.0};
+      }
       for (int i0 = 0; i0 < nr; i0 += kIC) {
         const int ic = nr - i0 < kIC ? nr - i0 : kIC;
-        for (int e = tid; e < ic * nt; e += blockDim.x) {
-          const int m = e / ic, ii = e % ic;
-          Ht[ii * ld + m] = {(double)Hg[2 * ((size_t)m * nr + i0 + ii)], (double)Hg[2 * ((size_t)m * nr + i0 + ii) + 1]};
+        for (int e = tid; e < ic * (nt + 1); e += BS) {
+          const int mm = e / ic, ii = e % ic;
+          const TIn* src = mm < nt ? Hg + 2 * ((size_t)mm * nr + i0 + ii) : y + 2 * (i0 + ii);
+          Ht[ii * ld + mm] = {(double)src[0], (double)src[1]};
         }
-        for (int ii = tid; ii < ic; ii += blockDim.x) yc[ii] = {(double)y[2 * (i0 + ii)], (double)y[2 * (i0 + ii) + 1]};
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kEPT; ++q) {
-          const int e = e0 + tid + q * (int)blockDim.x;
-          if (e < total) {
-            const bool isz = e >= nt * nt;
-            const int m = isz ? e - nt * nt : e / nt, m2 = isz ? 0 : e % nt;
-            double re = are[q], im = aim[q];
+        for (int q = 0; q < kBPT; ++q) {
+          if (b0 + tid + q * BS < nblk) {
+            // reads reach one entry past a row (column nt + 1, or row nt of an odd nt):
+            // those products are never stored
+            const cd* ha = Ht + m[q];
+            const cd* hb = Ht + m2[q];
             for (int ii = 0; ii < ic; ++ii) {
-              const tc hv = Ht[ii * ld + m];
-              const tc bvv = isz ? yc[ii] : Ht[ii * ld + m2];
-              const double ar = hv.re, ai = hv.im, br = bvv.re, bi = bvv.im;
-              re += ar * br + ai * bi;
-              im += ar * bi - ai * br;
+              const cd a0 = ha[ii * ld], a1 = ha[ii * ld + 1];
+              const cd c0 = hb[ii * ld], c1 = hb[ii * ld + 1];
+              const cd av[2] = {a0, a1}, cv[2] = {c0, c1};
+#pragma unroll
+              for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                  cd& g = acc[q][r][c];
+                  g.re = fma(av[r].re, cv[c].re, fma(av[r].im, cv[c].im, g.re));
+                  g.im = fma(av[r].re, cv[c].im, fma(-av[r].im, cv[c].re, g.im));
+                }
             }
-            are[q] = re;
-            aim[q] = im;
           }
         }
         __syncthreads();
       }
 #pragma unroll
-      for (int q = 0; q < kEPT; ++q) {
-        const int e = e0 + tid + q * (int)blockDim.x;
-        if (e < total) {
-          if (e >= nt * nt) z[e - nt * nt] = {are[q], aim[q]};
-          else W[(e / nt) * ld + e % nt] = {are[q], aim[q]};
-          if (!isfinite(are[q]) || !isfinite(aim[q])) nonfinite = 1.0;
+      for (int q = 0; q < kBPT; ++q) {
+        if (b0 + tid + q * BS < nblk) {
+#pragma unroll
+          for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const int i = m[q] + r, j = m2[q] + c;
+              const cd g = acc[q][r][c];
+              if (i >= nt) continue;
+              if (m2[q] == nt) {
+                if (c == 0) z[i] = g;
+                else continue;
+              } else if (j < nt) {
+                W[i * ld + j] = g;
+                if (m2[q] != m[q]) W[j * ld + i] = {g.re, -g.im};
+              } else {
+                continue;
+              }
+              if (!isfinite(g.re) || !isfinite(g.im)) nonfinite = 1.0;
+            }
         }
       }
     }
