@@ -80,8 +80,10 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
 
   extern __shared__ __attribute__((aligned(16))) unsigned char esm[];
   CM<R>* cm = (CM<R>*)esm;                           // CH x nt
+  const int lrs = 2 * nr + 2;                        // residual row stride (one pad entry: chain-strided reads
+                                                     // of one column hit distinct banks)
   R* rs = (R*)(cm + (size_t)CH * nt);                // CH x nr complex residuals of the final states
-  R* rb2 = rs + 2 * (size_t)CH * nr;                 // CH x nr |residual|^2 of the best states
+  R* rb2 = rs + (size_t)CH * lrs;                    // CH x nr |residual|^2 of the best states
   R* fs = rb2 + (size_t)CH * nr;                     // CH
   R* ebs = fs + CH;                                  // CH
   R* a2 = ebs + CH;                                  // nt
@@ -201,28 +203,31 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
           im = ys[2 * i + 1] - s2 * im;
           bre = ys[2 * i] - s2 * bre;
           bim = ys[2 * i + 1] - s2 * bim;
-          rs[2 * it] = re;
-          rs[2 * it + 1] = im;
+          rs[c * lrs + 2 * i] = re;
+          rs[c * lrs + 2 * i + 1] = im;
           rb2[it] = bre * bre + bim * bim;
         }
         __syncthreads();
         for (int c = tid; c < ch; c += nth) {
           R e = 0, eb = 0;
           for (int i = 0; i < nr; ++i) {
-            e += rs[2 * (c * nr + i)] * rs[2 * (c * nr + i)] + rs[2 * (c * nr + i) + 1] * rs[2 * (c * nr + i) + 1];
+            e += rs[c * lrs + 2 * i] * rs[c * lrs + 2 * i] + rs[c * lrs + 2 * i + 1] * rs[c * lrs + 2 * i + 1];
             eb += rb2[c * nr + i];
           }
           fs[c] = -e * inv_s2;
           ebs[c] = eb;
         }
         __syncthreads();
-        // per (chain, antenna): H^H r, the per-axis log normalisers, the base term
+        // per (chain, antenna): H^H r, the per-axis log normalisers, the base term.  With H
+        // in LDS consecutive lanes take consecutive antennas (conflict-free columns of Ht);
+        // with H in global memory they take consecutive chains, so that the lanes of one
+        // antenna share each cache line of its column
         for (int it = tid; it < ch * nt; it += nth) {
-          const int c = it / nt, m = it % nt;
+          const int c = SH ? it / nt : it % ch, m = SH ? it % nt : it / ch;
           R re = 0, im = 0;
           for (int i = 0; i < nr; ++i) {
             const R hr = hre(m, i), hi = him(m, i);
-            const R rr = rs[2 * (c * nr + i)], ri = rs[2 * (c * nr + i) + 1];
+            const R rr = rs[c * lrs + 2 * i], ri = rs[c * lrs + 2 * i + 1];
             re += hr * rr + hi * ri;
             im += hr * ri - hi * rr;
           }
@@ -240,7 +245,7 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
             lq.add(eQ * (v.aQ - q2 * eQ) * inv_tau);
           }
           v.base = cw * fs[c] - li.value() - lq.value();
-          cm[it] = v;
+          cm[c * nt + m] = v;
         }
         if (tid == 0 && rb == 0) {
           for (int c = 0; c < ch; ++c)
@@ -379,12 +384,13 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
       }
     }
   }
-  // hard decision: smallest recomputed energy among the chains' best states
-  if (tid == 0) {
+  // hard decision: smallest recomputed energy among the chains' best states (best_c and
+  // best_e were last written before a barrier inside the chunk loop)
+  {
     const int bc = best_c;
-    if (a.best_energy) a.best_energy[dsc.orig] = (float)best_e;
+    if (a.best_energy && tid == 0) a.best_energy[dsc.orig] = (float)best_e;
     if (a.symbols)
-      for (int m = 0; m < nt; ++m)
+      for (int m = tid; m < nt; m += nth)
         a.symbols[dsc.sym_off + m] = Kb[(size_t)bc * Npad + 2 * m] * Q + Kb[(size_t)bc * Npad + 2 * m + 1];
   }
 }
@@ -392,7 +398,7 @@ __global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
 size_t estimate_lds_bytes(int nt, int nr, int M, int N, int chunk, bool fp64) {
   const size_t R = fp64 ? 8 : 4;
   const size_t cm = fp64 ? 32 : 20;
-  return cm * (size_t)chunk * nt + R * (3 * (size_t)chunk * nr + 2 * (size_t)chunk + nt + 2 * (size_t)nr) +
+  return cm * (size_t)chunk * nt + R * (3 * (size_t)chunk * nr + 4 * (size_t)chunk + nt + 2 * (size_t)nr) +
          2 * (size_t)chunk * N + 16;
 }
 
