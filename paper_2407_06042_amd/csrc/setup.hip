@@ -141,8 +141,10 @@ __device__ void pack_dense(const cd* X, int ld, double c, int N, int Npad, doubl
   }
 }
 
+// 256-thread workgroups (instances up to 32 antennas) run five per CU: at most 96 registers, and
+// about 31 KiB of LDS with H staged 16 receive antennas at a time.
 template <typename TIn, bool WGLOB, int BS>
-__global__ __launch_bounds__(BS) void setup_kernel(SetupArgs a) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 5 : 1))) void setup_kernel(SetupArgs a) {
   const int b = blockIdx.x, tid = threadIdx.x, nt = a.nt, nr = a.nr, N = a.N, Npad = a.Npad;
   const int ld = nt + 1;  // padded leading dimension of the LDS matrices (no bank conflicts on columns)
   const InstDesc dsc = inst_desc(a.desc, b, nt, nr, a.Q * a.Q, 1);
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(BS) void setup_kernel(SetupArgs a) {
     // accumulates a 2 x 2 block of entries in registers across the chunks; only
     // blocks on or above the diagonal and the blocks of the z column are
     // computed, and the lower triangle is written as the conjugate.
-    constexpr int kIC = 32;
+    constexpr int kIC = BS == 256 ? 16 : 32;
     constexpr int kBPT = WGLOB ? 3 : 1;     // blocks per thread per group (one group up to nt = 128)
     cd* Ht = (cd*)(red + BS);               // kIC x ld, then one spare row read past the last column
     const int nb = (nt + 1) >> 1;           // 2-row blocks
@@ -442,7 +444,7 @@ template <int BS>
 hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s) {
   const bool wg = setup_w_global(a.nt);
   const size_t lds = (size_t)((wg ? 0 : a.nt * (a.nt + 1)) + 6 * a.nt) * sizeof(cd) + BS * sizeof(double) +
-                     (32 * (size_t)(a.nt + 1) + 32) * sizeof(cd);
+                     ((BS == 256 ? 16 : 32) * (size_t)(a.nt + 1) + 32) * sizeof(cd);
   void (*k)(SetupArgs);
   if constexpr (BS >= 1024)   // the working matrix goes to the workspace only for nt > 64 (1024 threads)
     k = a.fp64 ? (wg ? setup_kernel<double, true, BS> : setup_kernel<double, false, BS>)
