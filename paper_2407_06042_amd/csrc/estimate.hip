@@ -61,7 +61,8 @@ struct CM {
 };
 
 template <typename R, int Q, bool SH, int BS>
-__global__ __launch_bounds__(BS) void estimate_kernel(EstArgs a) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 && sizeof(R) == 4 && Q <= 8 ? 5 : 1)))
+void estimate_kernel(EstArgs a) {
   constexpr int M = Q * Q;
   constexpr int NB = Q == 2 ? 1 : (Q == 4 ? 2 : (Q == 8 ? 3 : 4));
   const int b = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
@@ -408,6 +409,16 @@ size_t estimate_lds_bytes(int nt, int nr, int M, int N, int chunk, bool fp64) {
 int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64) {
   int ch = C;
   while (ch > 1 && estimate_lds_bytes(nt, nr, M, N, ch, fp64) > 96 * 1024) ch = (ch + 1) / 2;
+  // 256-thread workgroups run five per CU when their LDS (with H staged) fits 32 KiB: take the
+  // smaller chunk that gets there, if it keeps at least 16 chains
+  const int Q = M <= 4 ? 2 : (M <= 16 ? 4 : (M <= 64 ? 8 : 16));
+  if (!fp64 && nt * Q <= 256) {
+    const size_t hb = 2 * (size_t)(nt + 1) * nr * sizeof(float);
+    const size_t hx = hb <= 65536 ? hb + 16 : 0;
+    int c2 = ch;
+    while (c2 > 16 && estimate_lds_bytes(nt, nr, M, N, c2, false) + hx > 32 * 1024) c2 = (c2 + 1) / 2;
+    if (estimate_lds_bytes(nt, nr, M, N, c2, false) + hx <= 32 * 1024) ch = c2;
+  }
   return ch;
 }
 
