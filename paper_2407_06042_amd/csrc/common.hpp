@@ -117,7 +117,7 @@ struct SetupArgs {
   const InstDesc* desc;
   const void* H; const void* y; const void* sigma2;
   unsigned char* ws_inst; size_t inst_stride;
-  unsigned char* wscratch; size_t wscratch_stride;  // per-instance working matrix when nt > 64
+  unsigned char* wscratch; size_t wscratch_stride;  // per-instance working matrix when nt > 32
   int n_inst, nt, nr, Q, N, Npad, RT, KB, fp64, pm, naive;
   double tau, alpha_mult, beta_mult, gamma_mult;
 };

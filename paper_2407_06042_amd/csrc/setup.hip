@@ -187,7 +187,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 
     // blocks on or above the diagonal and the blocks of the z column are
     // computed, and the lower triangle is written as the conjugate.
     constexpr int kIC = BS == 256 ? 16 : 32;
-    constexpr int kBPT = WGLOB ? 3 : 1;     // blocks per thread per group (one group up to nt = 128)
+    constexpr int kBPT = WGLOB ? (BS >= 1024 ? 3 : 2) : 1;  // blocks per thread per group (one group for every nt)
     cd* Ht = (cd*)(red + BS);               // kIC x ld, then one spare row read past the last column
     const int nb = (nt + 1) >> 1;           // 2-row blocks
     const int nbu = nb * (nb + 1) / 2;      // blocks on or above the diagonal
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 
     // p = o + TPR kb, o outer: column p then sits in register slot kb, a
     // compile-time index of the unrolled inner loop.  The two vectors alternate
     // between steps, so one barrier per step orders all reads and writes.
-    constexpr int RMAX = WGLOB ? 128 : (BS >= 1024 ? 64 : 32);  // rows covered (nt <= RMAX)
+    constexpr int RMAX = BS >= 1024 ? 128 : (BS >= 512 ? 64 : 32);  // rows covered (nt <= RMAX)
     constexpr int TPR = BS / RMAX;                               // threads per row
     constexpr int KMAX = RMAX / TPR;                             // columns per thread
     static_assert(64 % TPR == 0, "the threads of a row share a wavefront");
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 
   }
 }
 
-bool setup_w_global(int nt) { return nt > 64; }
+bool setup_w_global(int nt) { return nt > 32; }
 
 template <int BS>
 hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s) {
@@ -446,9 +446,9 @@ hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s) {
   const size_t lds = (size_t)((wg ? 0 : a.nt * (a.nt + 1)) + 6 * a.nt) * sizeof(cd) + BS * sizeof(double) +
                      ((BS == 256 ? 16 : 32) * (size_t)(a.nt + 1) + 32) * sizeof(cd);
   void (*k)(SetupArgs);
-  if constexpr (BS >= 1024)   // the working matrix goes to the workspace only for nt > 64 (1024 threads)
-    k = a.fp64 ? (wg ? setup_kernel<double, true, BS> : setup_kernel<double, false, BS>)
-               : (wg ? setup_kernel<float, true, BS> : setup_kernel<float, false, BS>);
+  if (wg != (BS > 256)) return hipErrorInvalidValue;   // the working matrix is in LDS exactly for 256 threads
+  if constexpr (BS > 256)
+    k = a.fp64 ? setup_kernel<double, true, BS> : setup_kernel<float, true, BS>;
   else
     k = a.fp64 ? setup_kernel<double, false, BS> : setup_kernel<float, false, BS>;
   if (lds > 65536) {
@@ -459,10 +459,13 @@ hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Large instances leave one workgroup per CU (LDS), so they get 16 waves instead of 4 to hide
-// the latency of the double-precision LDS traffic of the Gauss-Jordan sweep.
+// Up to 32 antennas: 256 threads, the working matrix in LDS, five workgroups per CU.  Larger
+// instances keep the working matrix in the workspace between phases (in registers during the
+// sweep), so that LDS holds only the staging buffers: 512 threads and two workgroups per CU up to
+// 64 antennas (their latency-bound Gauss-Jordan steps overlap), 1024 threads beyond.
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
-  return a.nt > 32 ? launch_setup_bs<1024>(a, s) : launch_setup_bs<256>(a, s);
+  if (a.nt <= 32) return launch_setup_bs<256>(a, s);
+  return a.nt <= 64 ? launch_setup_bs<512>(a, s) : launch_setup_bs<1024>(a, s);
 }
 
 }  // namespace dmala
