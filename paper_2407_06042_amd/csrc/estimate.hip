@@ -409,15 +409,17 @@ size_t estimate_lds_bytes(int nt, int nr, int M, int N, int chunk, bool fp64) {
 int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64) {
   int ch = C;
   while (ch > 1 && estimate_lds_bytes(nt, nr, M, N, ch, fp64) > 96 * 1024) ch = (ch + 1) / 2;
-  // 256-thread workgroups run five per CU when their LDS (with H staged) fits 32 KiB: take the
-  // smaller chunk that gets there, if it keeps at least 16 chains
+  // 256-thread workgroups run five per CU when their LDS (with H staged) fits 32 KiB, 512-thread
+  // ones two per CU within 80 KiB: take the smaller chunk that gets there, if it keeps at least
+  // 16 chains
   const int Q = M <= 4 ? 2 : (M <= 16 ? 4 : (M <= 64 ? 8 : 16));
-  if (!fp64 && nt * Q <= 256) {
+  if (!fp64 && nt * Q <= 512) {
+    const size_t budget = (nt * Q <= 256 ? 32 : 80) * 1024;
     const size_t hb = 2 * (size_t)(nt + 1) * nr * sizeof(float);
     const size_t hx = hb <= 65536 ? hb + 16 : 0;
     int c2 = ch;
-    while (c2 > 16 && estimate_lds_bytes(nt, nr, M, N, c2, false) + hx > 32 * 1024) c2 = (c2 + 1) / 2;
-    if (estimate_lds_bytes(nt, nr, M, N, c2, false) + hx <= 32 * 1024) ch = c2;
+    while (c2 > 16 && estimate_lds_bytes(nt, nr, M, N, c2, false) + hx > budget) c2 = (c2 + 1) / 2;
+    if (estimate_lds_bytes(nt, nr, M, N, c2, false) + hx <= budget) ch = c2;
   }
   return ch;
 }
@@ -439,7 +441,8 @@ static hipError_t launch_eb(const EstArgs& a, hipStream_t s) {
 template <typename R, int Q>
 static hipError_t launch_e(const EstArgs& a, hipStream_t s) {
   if constexpr (sizeof(R) == 8) return launch_eb<R, Q, 256>(a, s);  // the float64 path (nt <= 32) keeps 256
-  else return a.nt * Q > 256 ? launch_eb<R, Q, 1024>(a, s) : launch_eb<R, Q, 256>(a, s);
+  else if (a.nt * Q <= 256) return launch_eb<R, Q, 256>(a, s);
+  else return a.nt * Q <= 512 ? launch_eb<R, Q, 512>(a, s) : launch_eb<R, Q, 1024>(a, s);
 }
 
 template <typename R>
