@@ -406,6 +406,20 @@ size_t estimate_lds_bytes(int nt, int nr, int M, int N, int chunk, bool fp64) {
 // Chains per chunk (LDS budget 96 KiB).  When the (antenna, kI) rows outnumber
 // the 256 threads and there are several chunks, the chunks are staged again
 // for every block of rows.
+// H is staged in LDS when it fits 64 KiB (transposed, padded rows).
+static bool estimate_h_in_lds(int nt, int nr, bool fp64) {
+  return 2 * (size_t)(nt + 1) * nr * (fp64 ? 8 : 4) <= 65536;
+}
+
+// Threads per workgroup: one (antenna, kI) row each, in 256, 512 or 1024 threads; 1024 whenever H is
+// read from global memory (the residual and H^H r sweeps, O(C nt nr), then dominate).  The float64
+// path (nt <= 32) keeps 256.
+static int estimate_threads(int nt, int nr, int Q, bool fp64) {
+  if (fp64) return 256;
+  if (!estimate_h_in_lds(nt, nr, false) || nt * Q > 512) return 1024;
+  return nt * Q > 256 ? 512 : 256;
+}
+
 int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64) {
   int ch = C;
   while (ch > 1 && estimate_lds_bytes(nt, nr, M, N, ch, fp64) > 96 * 1024) ch = (ch + 1) / 2;
@@ -413,10 +427,10 @@ int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64) {
   // ones two per CU within 80 KiB: take the smaller chunk that gets there, if it keeps at least
   // 16 chains
   const int Q = M <= 4 ? 2 : (M <= 16 ? 4 : (M <= 64 ? 8 : 16));
-  if (!fp64 && nt * Q <= 512) {
-    const size_t budget = (nt * Q <= 256 ? 32 : 80) * 1024;
-    const size_t hb = 2 * (size_t)(nt + 1) * nr * sizeof(float);
-    const size_t hx = hb <= 65536 ? hb + 16 : 0;
+  const int bs = estimate_threads(nt, nr, Q, fp64);
+  if (!fp64 && bs <= 512) {
+    const size_t budget = (bs == 256 ? 32 : 80) * 1024;
+    const size_t hx = 2 * (size_t)(nt + 1) * nr * sizeof(float) + 16;   // H is in LDS (bs < 1024)
     int c2 = ch;
     while (c2 > 16 && estimate_lds_bytes(nt, nr, M, N, c2, false) + hx > budget) c2 = (c2 + 1) / 2;
     if (estimate_lds_bytes(nt, nr, M, N, c2, false) + hx <= budget) ch = c2;
@@ -427,7 +441,7 @@ int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64) {
 template <typename R, int Q, int BS>
 static hipError_t launch_eb(const EstArgs& a, hipStream_t s) {
   const size_t hbytes = 2 * (size_t)(a.nt + 1) * a.nr * sizeof(R);
-  const bool sh = hbytes <= 65536;
+  const bool sh = estimate_h_in_lds(a.nt, a.nr, sizeof(R) == 8);
   const size_t lds = estimate_lds_bytes(a.nt, a.nr, Q * Q, a.N, a.chunk, a.fp64) + (sh ? hbytes + 16 : 0);
   auto k = sh ? estimate_kernel<R, Q, true, BS> : estimate_kernel<R, Q, false, BS>;
   if (lds > 65536) {
@@ -440,9 +454,12 @@ static hipError_t launch_eb(const EstArgs& a, hipStream_t s) {
 
 template <typename R, int Q>
 static hipError_t launch_e(const EstArgs& a, hipStream_t s) {
-  if constexpr (sizeof(R) == 8) return launch_eb<R, Q, 256>(a, s);  // the float64 path (nt <= 32) keeps 256
-  else if (a.nt * Q <= 256) return launch_eb<R, Q, 256>(a, s);
-  else return a.nt * Q <= 512 ? launch_eb<R, Q, 512>(a, s) : launch_eb<R, Q, 1024>(a, s);
+  if constexpr (sizeof(R) == 8) {
+    return launch_eb<R, Q, 256>(a, s);
+  } else {
+    const int bs = estimate_threads(a.nt, a.nr, Q, false);
+    return bs == 256 ? launch_eb<R, Q, 256>(a, s) : (bs == 512 ? launch_eb<R, Q, 512>(a, s) : launch_eb<R, Q, 1024>(a, s));
+  }
 }
 
 template <typename R>
