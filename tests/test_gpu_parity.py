@@ -232,6 +232,7 @@ def test_windowed_proposal_matches_oracle(M, snr, shift):
     (128, 256, 0.5, 30.0, 32, 20, 0),    # Kronecker-correlated 128x128 256-QAM, four waves per 16 chains
     (41, 16, 0.0, 18.0, 32, 30, 0),      # 1024-thread setup, 41 rows over 16 threads per row (ragged slots)
     (70, 64, 0.0, 22.0, 32, 20, 0),      # working matrix in the workspace, 70 rows over 8 threads per row
+    (128, 4, 0.0, 8.0, 32, 20, 0),       # QPSK: 256 marginal rows, H read from global memory (1024 threads)
 ])
 def test_large_shapes_fp32(nt, M, rho, snr, C, T, tile):
     """Chain identity on the large layouts; estimators on a few antennas (oracle one by one)."""
