@@ -60,6 +60,7 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
   sh.C = p->n_chains; sh.Cpad = 16 * ((sh.C + 15) / 16); sh.T = p->n_iters;
   sh.fp64 = fp64 ? 1 : 0;
   sh.lrn = lrn ? 1 : 0;
+  sh.share = 0;
   pl.naive = p->proposal == DMALA_NAIVE;
   if (pl.naive) sh.pm = PM_NAIVE;
   else if (p->precision == DMALA_BF16) sh.pm = PM_BF16X1;

@@ -63,6 +63,7 @@ struct Shape {
   int cfg;         // sampler work layout (see sampler_impl.hpp launch_rt)
   int cbw;         // 16-chain blocks per workgroup for the one-wave layouts (1, 2 or 4)
   int lrn;         // 1: plain/learned kernel mixture (learned proposal network in the sampler)
+  int share;       // 1: launched beside other classes' kernels (an uneven batch's graph branches)
   size_t inst_bytes;   // per-instance setup block
   size_t frag_bytes;   // MFMA fragments (MFMA path)
   size_t state_bytes;  // per-instance sampler->estimator block

@@ -85,7 +85,9 @@ dmala_status class_plan(dmala_plan_s* P, ClassInfo& c) {
   dmala_params p = P->params;
   p.tile_config = c.tile_config;
   p.wg_chain_blocks = c.cbw;
-  return make_plan(c.count, c.shape.nt, c.shape.nr, c.shape.qam_order, &p, c.pl);
+  const dmala_status st = make_plan(c.count, c.shape.nt, c.shape.nr, c.shape.qam_order, &p, c.pl);
+  c.pl.sh.share = 1;
+  return st;
 }
 
 // Assign classes (already in decreasing cost order) to graph branches, each to the

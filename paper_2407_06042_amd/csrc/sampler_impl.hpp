@@ -929,15 +929,21 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
   const dim3 grid(a.n_inst, gy);
   const size_t lds = sampler_cfg_lds(sh, RTW, WD, MG, waves);
   // two waves per SIMD where the chain loop fits 256 registers without spilling: the learned
-  // two-tile layouts, and the plain four-tile layouts (the evaluation kernels keep the default)
+  // two-tile layouts, and the plain four-tile layouts except the naive proposal's four-wave one
+  // (the evaluation kernels keep the default).  The four-wave layout without the window table
+  // (Q <= 4) needs ~270 registers unbounded: bounded it is faster alone, but beside other
+  // classes' kernels (graph branches) the unbounded variant's spare registers serve them better
   constexpr bool kW2Eval = LRN && RTW == 2;
   constexpr bool kW2 = kW2Eval || (!LRN && RTW == 4 && !std::is_same<Real, double>::value && (WD < 4 || (WIN > 0 && PM != PM_NAIVE)));
+  constexpr bool kW2Alone = !LRN && RTW == 4 && !std::is_same<Real, double>::value && WD == 4 && WIN == 0 && PM != PM_NAIVE;
   void (*k)(SamplerArgs);
   if (eval) {
     if constexpr (kW2Eval) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, true, WIN, LRN>;
     else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN, LRN>;
   } else {
     if constexpr (kW2) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>;
+    else if constexpr (kW2Alone) k = sh.share ? sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>
+                                              : sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>;
     else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>;
   }
   if (lds > 65536) {
