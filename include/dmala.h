@@ -167,6 +167,26 @@ dmala_status dmala_detect(const void* H, const void* y, const void* sigma2,
                           const dmala_outputs* out, void* workspace, size_t workspace_bytes,
                           dmala_stream_t stream);
 
+/* ---- Detection without a caller workspace ----
+ * For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments, kernels
+ * and outputs as dmala_detect, with the workspace taken from a fixed device array
+ * of DMALA_STATIC_SCRATCH_BYTES bytes that the library keeps on every GPU it runs
+ * on until the process ends (the array's device address is looked up once per
+ * device, on the first call with that device current).  Calls no allocating
+ * routine.  Returns DMALA_ERR_WORKSPACE, before anything is enqueued, when the
+ * call's dmala_workspace_size() exceeds DMALA_STATIC_SCRATCH_BYTES.  The kernels
+ * write every scratch byte before reading it, so no clearing is needed between
+ * calls.  All calls on one GPU share its array: calls ordered on one stream are
+ * safe, calls that overlap on one GPU (different streams or host threads without
+ * ordering) race and give undefined results.  The stream must belong to the
+ * current device. */
+#define DMALA_STATIC_SCRATCH_BYTES (64u << 20)
+dmala_status dmala_detect_static(const void* H, const void* y, const void* sigma2,
+                                 int32_t n_inst, int32_t nt, int32_t nr, int32_t qam_order,
+                                 const float* constellation, const dmala_params* params,
+                                 const dmala_outputs* out, dmala_stream_t stream);
+
 /* Evaluate the chain's transition quantities for given state pairs with the
  * same device code as the sampler (tests build exact transition matrices from
  * it).  x_from, x_to: device int8 [n_inst][n_pairs][2 Nt] level indices.

@@ -19,6 +19,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp16": FP16}
 PROPOSALS = {"precond": PRECOND, "naive": NAIVE, "learned": LEARNED}
 MLP_PARAMS = 4932     # DMALA_MLP_PARAMS
 TRAIN_ROW = 12        # DMALA_TRAIN_ROW
+STATIC_SCRATCH_BYTES = 64 << 20   # DMALA_STATIC_SCRATCH_BYTES
 STATUS = {0: "DMALA_OK", -1: "DMALA_ERR_ARG", -2: "DMALA_ERR_UNSUPPORTED", -4: "DMALA_ERR_WORKSPACE", -5: "DMALA_ERR_HIP"}
 
 
@@ -63,6 +64,9 @@ def lib():
         L.dmala_detect.restype = ctypes.c_int
         L.dmala_detect.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, ctypes.POINTER(Params),
                                    ctypes.POINTER(Outputs), vp, sz, vp]
+        L.dmala_detect_static.restype = ctypes.c_int
+        L.dmala_detect_static.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, ctypes.POINTER(Params),
+                                          ctypes.POINTER(Outputs), vp]
         L.dmala_debug_eval.restype = ctypes.c_int
         L.dmala_debug_eval.argtypes = [vp, vp, vp, i32, i32, i32, i32, ctypes.POINTER(Params), vp, vp, i32, vp, vp, sz, vp]
         L.dmala_plan_create.restype = ctypes.c_int
@@ -91,7 +95,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ["dmala_workspace_size", "dmala_detect", "dmala_debug_eval", "dmala_plan_create", "dmala_plan_execute",
+EXPORTED = ["dmala_workspace_size", "dmala_detect", "dmala_detect_static", "dmala_debug_eval", "dmala_plan_create", "dmala_plan_execute",
             "dmala_plan_autotune", "dmala_plan_num_classes", "dmala_plan_class_info", "dmala_plan_destroy",
             "dmala_mlp_forward", "dmala_mlp_train_workspace_size", "dmala_mlp_train_step",
             "dmala_last_error", "dmala_version"]
@@ -183,19 +187,25 @@ class Detector:
         p = self.ws.data_ptr()
         return (p + 255) // 256 * 256
 
-    def __call__(self, Hcm, y, sigma2, stream=None, events=None):
+    def __call__(self, Hcm, y, sigma2, stream=None, events=None, static_scratch=False):
         """Enqueue detection on the current (or given) stream; returns the output dict.
 
         events: optional 4 raw hipEvent_t handles recorded around the three kernels.
+        static_scratch: run dmala_detect_static (the library's fixed device array as
+        workspace) instead of dmala_detect with this detector's workspace.
         """
         torch = self.torch
         self._check_inputs(Hcm, y, sigma2)
         s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
         for i in range(4):
             self._outs.stage_events[i] = events[i] if events is not None else None
-        st = lib().dmala_detect(Hcm.data_ptr(), y.data_ptr(), sigma2.data_ptr(), self.n_inst, self.nt, self.nr, self.M,
-                                None, ctypes.byref(self.params), ctypes.byref(self._outs), self._ws_ptr(),
-                                self.ws_bytes, s)
+        if static_scratch:
+            st = lib().dmala_detect_static(Hcm.data_ptr(), y.data_ptr(), sigma2.data_ptr(), self.n_inst, self.nt,
+                                           self.nr, self.M, None, ctypes.byref(self.params), ctypes.byref(self._outs), s)
+        else:
+            st = lib().dmala_detect(Hcm.data_ptr(), y.data_ptr(), sigma2.data_ptr(), self.n_inst, self.nt, self.nr,
+                                    self.M, None, ctypes.byref(self.params), ctypes.byref(self._outs), self._ws_ptr(),
+                                    self.ws_bytes, s)
         if st != 0:
             raise DmalaError(st, last_error())
         return self.out

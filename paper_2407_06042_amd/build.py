@@ -27,7 +27,7 @@ SOURCES = [
     "api.cpp", "plan.cpp", "setup.hip", "estimate.hip", "sampler.hip",
     "sampler_f64_naive.hip", "sampler_f64_pre.hip", "sampler_naive.hip",
     "sampler_f16x2.hip", "sampler_f16x1.hip", "sampler_bf16x1.hip",
-    "sampler_lrn_f16x2.hip", "sampler_lrn_f16x1.hip", "sampler_lrn_bf16x1.hip", "mlp.hip",
+    "sampler_lrn_f16x2.hip", "sampler_lrn_f16x1.hip", "sampler_lrn_bf16x1.hip", "mlp.hip", "static_ws.hip",
 ]
 
 

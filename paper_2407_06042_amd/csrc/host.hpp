@@ -22,6 +22,8 @@ extern thread_local std::string g_err;
 dmala_status fail(dmala_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 dmala_status hip_fail(hipError_t e, const char* what);
 size_t round_up(size_t v, size_t a);
+// Whether pts (M complex floats) is the canonical unit-energy square M-QAM.
+bool canonical_qam(const float* pts, int M);
 
 // Validate a uniform shape and compute its layout (workspace relative to 0).
 dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const dmala_params* p, Plan& pl);
