@@ -46,8 +46,10 @@ typedef struct ihipStream_t* dmala_stream_t; /* a hipStream_t; NULL = default st
 
 typedef enum {
   DMALA_OK = 0,
-  DMALA_ERR_ARG = -1,         /* invalid argument (shape, sigma^2 <= 0, NULL input, ...) */
+  DMALA_ERR_ARG = -1,         /* invalid argument (shape, NULL input, ...) */
   DMALA_ERR_UNSUPPORTED = -2, /* valid but not supported (non-square or unknown QAM, size limits) */
+  DMALA_ERR_NONFINITE = -3,   /* an instance has a non-finite entry in H or y, or sigma^2 is not
+                                 positive and finite (Lemma 1 needs sigma^2 > 0): see dmala_outputs.status */
   DMALA_ERR_WORKSPACE = -4,   /* workspace NULL or smaller than dmala_workspace_size() */
   DMALA_ERR_HIP = -5          /* a HIP runtime call failed (message has the HIP error) */
 } dmala_status;
@@ -73,7 +75,15 @@ typedef enum { DMALA_FP64 = 0, DMALA_FP32 = 1, DMALA_BF16 = 2, DMALA_FP16 = 3 } 
  * work, Section VI; admissibility follows from eq. acc_prob).  The kernel
  * choice uses the 24-bit uniform from the low bytes of words 4, 5, 6 of the
  * transition's random stream (plain iff u < mix_eps).  Not with DMALA_FP64. */
-typedef enum { DMALA_PRECOND = 0, DMALA_NAIVE = 1, DMALA_LEARNED = 2 } dmala_proposal;
+typedef enum { DMALA_PRECOND = 0, DMALA_NAIVE = 1, DMALA_LEARNED = 2, DMALA_MHGD = 3 } dmala_proposal;
+/* DMALA_MHGD is the baseline the paper compares against (Section III-A, the Remark
+ * on the visual comparison): the candidate is the continuous preconditioned
+ * Langevin step x + (alpha/2) M grad(f/tau)(x) + sqrt(alpha beta) w, w ~ N(0, I),
+ * mapped to the nearest lattice point per real dimension, and accepted with
+ * min(1, pi_a(x')/pi_a(x)) -- without the mapping's proposal probability, so the
+ * chain is biased (Section III-B).  w_n = Phi^-1(u_n) with u_n = (high 24 bits of
+ * word n + 1/2) 2^-24; MH uniform and initial state as for the other proposals.
+ * For comparisons only; not with the learned-network options. */
 
 /* Bit LLR estimator from the final samples (one per chain):
  *   IS   -- eq. llr_is in the log-sum-exp form of eq. llr_simple (the default);
@@ -128,6 +138,9 @@ typedef struct {
                                 LEARNED excludes layout 2; its defaults are layouts 0, 5, 6, 4 */
   double mix_eps;            /* LEARNED: probability of the PRECOND kernel per transition, in [0, 1] */
   dmala_llr_mode llr_mode;   /* bit LLR estimator (default IS) */
+  uint32_t counter_base;     /* instance b of the call draws from the random stream of instance
+                                counter_base + b (the counter's instance word); 0 by default.  A batch
+                                split over several calls keeps its chains with the offsets of the parts */
 } dmala_params;
 
 /* Device output buffers; any pointer may be NULL to skip that output. */
@@ -145,6 +158,12 @@ typedef struct {
   float* train_rows;         /* [n_inst][n_chains][Nt][DMALA_TRAIN_ROW] network training rows at the final
                                 state (PRECOND or LEARNED only); plans index rows as
                                 (sum_{j<b} Nt_j) * n_chains + chain * Nt_b + m */
+  int32_t* status;           /* [n_inst] input check of each instance, written by the first kernel:
+                                DMALA_OK, or DMALA_ERR_NONFINITE when H or y has a non-finite entry or
+                                sigma^2 is not positive and finite.  A flagged instance runs no chain:
+                                its symbols are -1, marginals, LLRs and best energy NaN, final states,
+                                accept counts, traces and training rows 0.  Read it after the stream
+                                has run, or let dmala_sync_status() do so. */
   void* stage_events[4];     /* optional hipEvent_t handles recorded on `stream` before the setup,
                                 sampler and estimator kernels and after the last one (profiling);
                                 NULL entries are skipped */
@@ -157,6 +176,10 @@ size_t dmala_workspace_size(int32_t n_inst, int32_t nt, int32_t nr, int32_t qam_
 
 /* Detect n_inst independent problems of one shape (Algorithm 2 per instance).
  *   H, y, sigma2: device inputs as described above; sigma2[b] > 0 (Lemma 1).
+ *     The inputs live on the device, so they are checked there: an instance with a
+ *     non-finite entry in H or y, or with sigma2[b] not positive and finite, is
+ *     flagged in out->status (see dmala_outputs) and skipped; the call itself still
+ *     returns DMALA_OK (it does not wait for the stream).
  *   constellation: NULL, or host array of M complex float points that must
  *     equal the canonical unit-energy QAM (validated; others are unsupported).
  *   Limits: 1 <= nt <= 128, 1 <= nr <= 4096, M in {4, 16, 64, 256}; FP64 needs nt <= 32.
@@ -166,6 +189,32 @@ dmala_status dmala_detect(const void* H, const void* y, const void* sigma2,
                           const float* constellation, const dmala_params* params,
                           const dmala_outputs* out, void* workspace, size_t workspace_bytes,
                           dmala_stream_t stream);
+
+/* Wait for `stream`, then read status[0..n_inst) (device, as written through
+ * dmala_outputs.status): DMALA_OK if no instance is flagged, otherwise
+ * DMALA_ERR_NONFINITE with the number of flagged instances and the first one in
+ * dmala_last_error().  Synchronises the stream; allocates nothing. */
+dmala_status dmala_sync_status(const int32_t* status, int32_t n_inst, dmala_stream_t stream);
+
+/* One problem with the defaults of Section IV-A (preconditioned proposal, tau = 2,
+ * alpha = sigma^2, beta = dmin^2 / sigma^2, gamma = sigma^2 / (2 dmin^2)), fp32-class
+ * arithmetic (DMALA_FP32), IS estimators; synchronous: returns when the outputs are
+ * written.
+ *   H: device complex float [Nt][Nr] (column-major), y: device complex float [Nr];
+ *   sigma2: host value; not positive and finite -> DMALA_ERR_NONFINITE before anything
+ *     is enqueued (Lemma 1 needs sigma^2 > 0);
+ *   constellation: host array of M complex float points, validated against the
+ *     canonical unit-energy square QAM (NULL: the canonical one);
+ *   symbols: device int32 [Nt] (hard decision), marginals: device float [Nt][M]
+ *     (may be NULL);
+ *   workspace: device, 256-byte aligned, dmala_detect_one_workspace_size() bytes.
+ * Returns DMALA_ERR_NONFINITE (outputs as for a flagged instance) when H or y has a
+ * non-finite entry. */
+size_t dmala_detect_one_workspace_size(int32_t nt, int32_t nr, int32_t qam_order, int32_t n_chains);
+dmala_status dmala_detect_one(const void* H, const void* y, float sigma2, int32_t nt, int32_t nr,
+                              const float* constellation, int32_t qam_order, int32_t n_chains,
+                              int32_t n_iters, uint64_t seed, int32_t* symbols, float* marginals,
+                              void* workspace, size_t workspace_bytes, dmala_stream_t stream);
 
 /* ---- Detection without a caller workspace ----
  * For callers that cannot allocate device memory: code under HIP graph capture,
@@ -192,13 +241,17 @@ dmala_status dmala_detect_static(const void* H, const void* y, const void* sigma
  * it).  x_from, x_to: device int8 [n_inst][n_pairs][2 Nt] level indices.
  * out: device double [n_inst][n_pairs][4] = (log q(x_to | x_from),
  * log q(x_from | x_to), f(x_to)/tau - f(x_from)/tau, log acceptance ratio),
- * natural logs, as the sampler computes them.  Workspace as for
+ * natural logs, as the sampler computes them.
+ * out_dim (optional, NULL to skip): device double [n_inst][n_pairs][2 Nt], the
+ * per-dimension terms log q_n(x_to,n | x_from) of the forward proposal (eq.
+ * dis_prop_fac1), whose sum is out[.][0].
+ * A flagged instance (see dmala_outputs.status) gives NaN.  Workspace as for
  * dmala_detect with n_chains = n_pairs. */
 dmala_status dmala_debug_eval(const void* H, const void* y, const void* sigma2,
                               int32_t n_inst, int32_t nt, int32_t nr, int32_t qam_order,
                               const dmala_params* params, const int8_t* x_from, const int8_t* x_to,
-                              int32_t n_pairs, double* out, void* workspace, size_t workspace_bytes,
-                              dmala_stream_t stream);
+                              int32_t n_pairs, double* out, double* out_dim, void* workspace,
+                              size_t workspace_bytes, dmala_stream_t stream);
 
 /* ---- Uneven batches: instances of different Nt, Nr, M in one graph launch ----
  * A plan groups the instances of a batch by shape class (Nt, Nr, M), orders the
@@ -208,8 +261,9 @@ dmala_status dmala_debug_eval(const void* H, const void* y, const void* sigma2,
  *   H of instance b at complex offset sum_{j<b} Nt_j Nr_j (column-major per instance),
  *   y at sum_{j<b} Nr_j, sigma2[b]; symbols at sum Nt_j; marginals and marginals_mc at
  *   sum Nt_j M_j; llrs at sum Nt_j log2 M_j; best_energy[b]; final_state at
- *   sum n_chains 2 Nt_j; accept_count at b * n_chains.  Trace outputs are not
- *   supported by plans (NULL required).
+ *   sum n_chains 2 Nt_j; accept_count at b * n_chains; status at b; trace_accept and
+ *   trace_hash as for dmala_detect with instance b (every instance has the same
+ *   n_chains and n_iters).
  * The per-instance random counters use the instance index b, so a plan and a
  * dmala_detect call over the same instances give identical chains.
  * The plan owns a small device table (hipMalloc at creation, freed by
@@ -269,6 +323,25 @@ dmala_status dmala_mlp_train_step(float* weights, float* adam_m, float* adam_v, 
                                   const float* rows, const int32_t* targets, int32_t n_rows,
                                   float* loss, float* grad, void* workspace, size_t workspace_bytes,
                                   dmala_stream_t stream);
+
+/* ---- Measurement: the gradient contraction alone ----
+ * Runs the chain's G.X stage -- the product of the packed preconditioned matrix with the
+ * chains' level vectors on MFMA, one bf16 (DMALA_BF16) or fp16 (DMALA_FP16) pass with fp32
+ * accumulation, 8 Nt^2 flops per chain -- n_loops times per chain, with a synthetic update
+ * between products (each level whose gradient entry is negative changes sign), to measure
+ * the stage's fraction of the MFMA peak apart from the rest of the transition.  Same
+ * fragments and lane layout as the sampler; the matrix stays in registers.
+ *   params: DMALA_PRECOND with DMALA_BF16 or DMALA_FP16 (others: DMALA_ERR_UNSUPPORTED);
+ *   run_setup: 1 runs the setup kernel first (packs the matrices into the workspace); 0
+ *     reuses the matrices an earlier call with the same inputs, shape and params left there;
+ *   sink: device float [dmala_gx_loop_sink_size(n_inst, nt, n_chains)] per-lane sums of the
+ *     last products (keeps the work observable);
+ *   workspace: as dmala_workspace_size() for the same shape and params. */
+size_t dmala_gx_loop_sink_size(int32_t n_inst, int32_t nt, int32_t n_chains);
+dmala_status dmala_gx_loop(const void* H, const void* y, const void* sigma2, int32_t n_inst, int32_t nt,
+                           int32_t nr, int32_t qam_order, const dmala_params* params, int32_t n_loops,
+                           int32_t run_setup, float* sink, void* workspace, size_t workspace_bytes,
+                           dmala_stream_t stream);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* dmala_last_error(void);

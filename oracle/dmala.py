@@ -204,8 +204,10 @@ def dmala_sample(prob, seed, instance, n_chains, n_iters, trace=False):
     Chains are independent (their random words differ by the chain counter); the
     loop is vectorised over chains only.  Returns a dict with the final level
     indices, best (minimum-residual) states and energies, accept counts and,
-    when trace=True, per-transition accept flags, state hashes and the decision
-    margins of every draw.
+    when trace is true, per-transition accept flags, state hashes, the energies of
+    the state after the transition and of the proposal, and the decision margins of
+    every draw; trace="states" also records the state before and the proposal of
+    every transition (int8 level indices) and the energy before.
     """
     N, Q, tau = prob.N, prob.Q, prob.tau
     chains = np.arange(n_chains)
@@ -225,7 +227,12 @@ def dmala_sample(prob, seed, instance, n_chains, n_iters, trace=False):
                   cat_margin=np.zeros((n_iters, n_chains)),
                   mh_margin=np.zeros((n_iters, n_chains)),
                   log_ratio=np.zeros((n_iters, n_chains)),
-                  init_hash=state_hash(k))
+                  E=np.zeros((n_iters, n_chains)), E_prop=np.zeros((n_iters, n_chains)),
+                  init_hash=state_hash(k), init_E=E.copy())
+        if trace == "states":
+            tr["k_from"] = np.zeros((n_iters, n_chains, N), np.int8)
+            tr["k_prop"] = np.zeros((n_iters, n_chains, N), np.int8)
+            tr["E_from"] = np.zeros((n_iters, n_chains))
     for t in range(1, n_iters + 1):
         w = philox.words(seed, instance, chains, t, N)
         u = philox.uniform24(w[:, :N])
@@ -245,6 +252,10 @@ def dmala_sample(prob, seed, instance, n_chains, n_iters, trace=False):
         u_mh = philox.low_byte_uniform(w, 0)
         acc = A > u_mh
         E_p = prob.energy(xp)
+        if trace == "states":
+            tr["k_from"][t - 1] = k
+            tr["k_prop"][t - 1] = kp
+            tr["E_from"][t - 1] = E
         k = np.where(acc[:, None], kp, k)
         f_x = np.where(acc, f_p, f_x)
         logq = np.where(acc[:, None, None], logq_p, logq)
@@ -262,6 +273,8 @@ def dmala_sample(prob, seed, instance, n_chains, n_iters, trace=False):
             tr["cat_margin"][t - 1] = np.min(cmarg, axis=-1)
             tr["mh_margin"][t - 1] = np.abs(R - lu)
             tr["log_ratio"][t - 1] = R
+            tr["E"][t - 1] = E
+            tr["E_prop"][t - 1] = E_p
     return dict(k=k, best_k=best_k, best_E=best_E, n_acc=n_acc, trace=tr)
 
 

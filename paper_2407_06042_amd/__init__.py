@@ -14,13 +14,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmala.so")
 
 FP64, FP32, BF16, FP16 = 0, 1, 2, 3
-PRECOND, NAIVE, LEARNED = 0, 1, 2
+PRECOND, NAIVE, LEARNED, MHGD = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp16": FP16}
-PROPOSALS = {"precond": PRECOND, "naive": NAIVE, "learned": LEARNED}
+PROPOSALS = {"precond": PRECOND, "naive": NAIVE, "learned": LEARNED, "mhgd": MHGD}
 MLP_PARAMS = 4932     # DMALA_MLP_PARAMS
 TRAIN_ROW = 12        # DMALA_TRAIN_ROW
 STATIC_SCRATCH_BYTES = 64 << 20   # DMALA_STATIC_SCRATCH_BYTES
-STATUS = {0: "DMALA_OK", -1: "DMALA_ERR_ARG", -2: "DMALA_ERR_UNSUPPORTED", -4: "DMALA_ERR_WORKSPACE", -5: "DMALA_ERR_HIP"}
+STATUS = {0: "DMALA_OK", -1: "DMALA_ERR_ARG", -2: "DMALA_ERR_UNSUPPORTED", -3: "DMALA_ERR_NONFINITE",
+          -4: "DMALA_ERR_WORKSPACE", -5: "DMALA_ERR_HIP"}
 
 
 class Params(ctypes.Structure):
@@ -28,7 +29,8 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int), ("proposal", ctypes.c_int), ("tau", ctypes.c_double),
                 ("alpha_mult", ctypes.c_double), ("beta_mult", ctypes.c_double), ("gamma_mult", ctypes.c_double),
                 ("tile_config", ctypes.c_int32), ("wg_chain_blocks", ctypes.c_int32),
-                ("mlp_weights", ctypes.c_void_p), ("mix_eps", ctypes.c_double), ("llr_mode", ctypes.c_int)]
+                ("mlp_weights", ctypes.c_void_p), ("mix_eps", ctypes.c_double), ("llr_mode", ctypes.c_int),
+                ("counter_base", ctypes.c_uint32)]
 
 
 class Shape(ctypes.Structure):
@@ -39,7 +41,7 @@ class Outputs(ctypes.Structure):
     _fields_ = [("symbols", ctypes.c_void_p), ("marginals", ctypes.c_void_p), ("llrs", ctypes.c_void_p),
                 ("best_energy", ctypes.c_void_p), ("final_state", ctypes.c_void_p), ("accept_count", ctypes.c_void_p),
                 ("marginals_mc", ctypes.c_void_p), ("trace_accept", ctypes.c_void_p), ("trace_hash", ctypes.c_void_p),
-                ("train_rows", ctypes.c_void_p), ("stage_events", ctypes.c_void_p * 4)]
+                ("train_rows", ctypes.c_void_p), ("status", ctypes.c_void_p), ("stage_events", ctypes.c_void_p * 4)]
 
 
 class DmalaError(RuntimeError):
@@ -68,7 +70,19 @@ def lib():
         L.dmala_detect_static.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, ctypes.POINTER(Params),
                                           ctypes.POINTER(Outputs), vp]
         L.dmala_debug_eval.restype = ctypes.c_int
-        L.dmala_debug_eval.argtypes = [vp, vp, vp, i32, i32, i32, i32, ctypes.POINTER(Params), vp, vp, i32, vp, vp, sz, vp]
+        L.dmala_debug_eval.argtypes = [vp, vp, vp, i32, i32, i32, i32, ctypes.POINTER(Params), vp, vp, i32, vp, vp, vp, sz,
+                                       vp]
+        L.dmala_gx_loop_sink_size.restype = sz
+        L.dmala_gx_loop_sink_size.argtypes = [i32, i32, i32]
+        L.dmala_gx_loop.restype = ctypes.c_int
+        L.dmala_gx_loop.argtypes = [vp, vp, vp, i32, i32, i32, i32, ctypes.POINTER(Params), i32, i32, vp, vp, sz, vp]
+        L.dmala_sync_status.restype = ctypes.c_int
+        L.dmala_sync_status.argtypes = [vp, i32, vp]
+        L.dmala_detect_one_workspace_size.restype = sz
+        L.dmala_detect_one_workspace_size.argtypes = [i32, i32, i32, i32]
+        L.dmala_detect_one.restype = ctypes.c_int
+        L.dmala_detect_one.argtypes = [vp, vp, ctypes.c_float, i32, i32, vp, i32, i32, i32, ctypes.c_uint64, vp, vp, vp,
+                                       sz, vp]
         L.dmala_plan_create.restype = ctypes.c_int
         L.dmala_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Shape), i32, ctypes.POINTER(Params),
                                         ctypes.POINTER(sz)]
@@ -95,7 +109,8 @@ def lib():
     return _lib
 
 
-EXPORTED = ["dmala_workspace_size", "dmala_detect", "dmala_detect_static", "dmala_debug_eval", "dmala_plan_create", "dmala_plan_execute",
+EXPORTED = ["dmala_workspace_size", "dmala_detect", "dmala_detect_static", "dmala_debug_eval", "dmala_sync_status",
+            "dmala_detect_one_workspace_size", "dmala_detect_one", "dmala_gx_loop_sink_size", "dmala_gx_loop", "dmala_plan_create", "dmala_plan_execute",
             "dmala_plan_autotune", "dmala_plan_num_classes", "dmala_plan_class_info", "dmala_plan_destroy",
             "dmala_mlp_forward", "dmala_mlp_train_workspace_size", "dmala_mlp_train_step",
             "dmala_last_error", "dmala_version"]
@@ -110,7 +125,7 @@ LLR_MODES = {"is": 0, "list": 1, "mc": 2}
 
 def make_params(n_chains, n_iters, seed, precision="fp32", proposal="precond", tau=2.0,
                 alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, tile_config=0, mlp_weights=None, mix_eps=0.0,
-                llr_mode="is"):
+                llr_mode="is", counter_base=0):
     """mlp_weights: device float32 tensor of MLP_PARAMS values (learned proposal only)."""
     w = None
     if mlp_weights is not None:
@@ -118,7 +133,7 @@ def make_params(n_chains, n_iters, seed, precision="fp32", proposal="precond", t
         w = mlp_weights.data_ptr()
     return Params(int(n_chains), int(n_iters), int(seed) & ((1 << 64) - 1), PRECISIONS[precision],
                   PROPOSALS[proposal], float(tau), float(alpha_mult), float(beta_mult), float(gamma_mult),
-                  int(tile_config), 0, w, float(mix_eps), LLR_MODES[llr_mode])
+                  int(tile_config), 0, w, float(mix_eps), LLR_MODES[llr_mode], int(counter_base))
 
 
 def _check_weights(w):
@@ -154,14 +169,14 @@ class Detector:
     def __init__(self, n_inst, nt, nr, M, n_chains, n_iters, seed=0, precision="fp32", proposal="precond",
                  tau=2.0, alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, device="cuda",
                  outputs=("symbols", "marginals", "llrs", "best_energy"), trace=False, tile_config=0,
-                 mlp_weights=None, mix_eps=0.0, llr_mode="is"):
+                 mlp_weights=None, mix_eps=0.0, llr_mode="is", counter_base=0):
         import torch
         self.torch = torch
         self.n_inst, self.nt, self.nr, self.M = n_inst, nt, nr, M
         self.precision = precision
         self.mlp_weights = mlp_weights  # keeps the tensor alive while the detector holds its pointer
         self.params = make_params(n_chains, n_iters, seed, precision, proposal, tau, alpha_mult, beta_mult,
-                                  gamma_mult, tile_config, mlp_weights, mix_eps, llr_mode)
+                                  gamma_mult, tile_config, mlp_weights, mix_eps, llr_mode, counter_base)
         self.ws_bytes = workspace_size(n_inst, nt, nr, M, self.params)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
         nb = int(round(np.log2(M)))
@@ -170,7 +185,8 @@ class Detector:
                       final_state=((n_inst, n_chains, 2 * nt), torch.int8),
                       accept_count=((n_inst, n_chains), torch.int32),
                       marginals_mc=((n_inst, nt, M), torch.float32),
-                      train_rows=((n_inst, n_chains, nt, TRAIN_ROW), torch.float32))
+                      train_rows=((n_inst, n_chains, nt, TRAIN_ROW), torch.float32),
+                      status=((n_inst,), torch.int32))
         want = set(outputs)
         if trace:
             want |= {"final_state", "accept_count"}
@@ -232,10 +248,11 @@ def detect(Hcm, y, sigma2, M, n_chains, n_iters, seed, **kw):
 
 
 def debug_eval(Hcm, y, sigma2, M, x_from, x_to, precision="fp32", proposal="precond", tau=2.0,
-               alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, tile_config=0, mlp_weights=None):
+               alpha_mult=1.0, beta_mult=1.0, gamma_mult=1.0, tile_config=0, mlp_weights=None, per_dim=False):
     """Transition quantities of the device chain for state pairs (see dmala_debug_eval).
 
-    With proposal="learned" the quantities are those of the learned kernel alone."""
+    With proposal="learned" the quantities are those of the learned kernel alone.  per_dim=True
+    returns (out, out_dim) with the per-dimension forward log q terms (n_inst, n_pairs, 2 Nt)."""
     import torch
     n_inst, nt, nr = Hcm.shape
     n_pairs = x_from.shape[1]
@@ -245,14 +262,73 @@ def debug_eval(Hcm, y, sigma2, M, x_from, x_to, precision="fp32", proposal="prec
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=Hcm.device)
     wp = (ws.data_ptr() + 255) // 256 * 256
     out = torch.empty((n_inst, n_pairs, 4), dtype=torch.float64, device=Hcm.device)
+    od = torch.empty((n_inst, n_pairs, 2 * nt), dtype=torch.float64, device=Hcm.device) if per_dim else None
     xf = x_from.to(torch.int8).contiguous()
     xt = x_to.to(torch.int8).contiguous()
     st = lib().dmala_debug_eval(Hcm.data_ptr(), y.data_ptr(), sigma2.data_ptr(), n_inst, nt, nr, M, ctypes.byref(p),
-                                xf.data_ptr(), xt.data_ptr(), n_pairs, out.data_ptr(), wp, ws_bytes,
+                                xf.data_ptr(), xt.data_ptr(), n_pairs, out.data_ptr(),
+                                od.data_ptr() if per_dim else None, wp, ws_bytes,
                                 torch.cuda.current_stream().cuda_stream)
     if st != 0:
         raise DmalaError(st, last_error())
-    return out
+    return (out, od) if per_dim else out
+
+
+class GxLoop:
+    """The gradient contraction alone, looped (dmala_gx_loop): bf16 or fp16, preconditioned matrices."""
+
+    def __init__(self, n_inst, nt, nr, M, n_chains, precision="bf16", device="cuda"):
+        import torch
+        self.torch = torch
+        self.n_inst, self.nt, self.nr, self.M, self.C = n_inst, nt, nr, M, n_chains
+        self.params = make_params(n_chains, 1, 0, precision, "precond")
+        self.ws_bytes = workspace_size(n_inst, nt, nr, M, self.params)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        self.sink = torch.zeros(lib().dmala_gx_loop_sink_size(n_inst, nt, n_chains), dtype=torch.float32,
+                                device=device)
+
+    def __call__(self, Hcm, y, sigma2, n_loops, run_setup=False):
+        wp = (self.ws.data_ptr() + 255) // 256 * 256
+        st = lib().dmala_gx_loop(Hcm.data_ptr(), y.data_ptr(), sigma2.data_ptr(), self.n_inst, self.nt, self.nr, self.M,
+                                 ctypes.byref(self.params), int(n_loops), 1 if run_setup else 0, self.sink.data_ptr(),
+                                 wp, self.ws_bytes, self.torch.cuda.current_stream().cuda_stream)
+        if st != 0:
+            raise DmalaError(st, last_error())
+        return self.sink
+
+
+def sync_status(status, stream=None):
+    """dmala_sync_status on a device int32 status tensor: raises DmalaError(DMALA_ERR_NONFINITE) if any
+    instance is flagged."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    st = lib().dmala_sync_status(status.data_ptr(), status.numel(), s)
+    if st != 0:
+        raise DmalaError(st, last_error())
+
+
+def detect_one(H, y, sigma2, M, n_chains, n_iters, seed, constellation=None, marginals=True):
+    """dmala_detect_one: one problem, H (Nt, Nr) complex64 device tensor (column-major), y (Nr,) complex64
+    device tensor, sigma2 a host float.  Synchronous; returns (symbols, marginals or None)."""
+    import torch
+    nt, nr = H.shape
+    need = lib().dmala_detect_one_workspace_size(nt, nr, M, n_chains)
+    if need == 0:
+        raise DmalaError(-1, last_error())
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=H.device)
+    wp = (ws.data_ptr() + 255) // 256 * 256
+    sym = torch.empty(nt, dtype=torch.int32, device=H.device)
+    marg = torch.empty((nt, M), dtype=torch.float32, device=H.device) if marginals else None
+    pts = None
+    if constellation is not None:
+        c = np.ascontiguousarray(np.asarray(constellation, dtype=np.complex64))
+        pts = c.ctypes.data_as(ctypes.c_void_p)
+    st = lib().dmala_detect_one(H.data_ptr(), y.data_ptr(), float(sigma2), nt, nr, pts, M, n_chains, n_iters,
+                                int(seed) & ((1 << 64) - 1), sym.data_ptr(), marg.data_ptr() if marginals else None,
+                                wp, need, torch.cuda.current_stream().cuda_stream)
+    if st != 0:
+        raise DmalaError(st, last_error())
+    return sym, marg
 
 
 def pack_uneven(H_list, y_list, sigma2, precision="fp32", device="cuda"):
@@ -294,7 +370,9 @@ class Plan:
         sizes = dict(symbols=(nt_sum, torch.int32), marginals=(marg, torch.float32), llrs=(llr, torch.float32),
                      best_energy=(n, torch.float32), final_state=(n_chains * 2 * nt_sum, torch.int8),
                      accept_count=(n * n_chains, torch.int32), marginals_mc=(marg, torch.float32),
-                     train_rows=(n_chains * nt_sum * TRAIN_ROW, torch.float32))
+                     train_rows=(n_chains * nt_sum * TRAIN_ROW, torch.float32), status=(n, torch.int32),
+                     trace_hash=(n * n_chains * max(1, n_iters), torch.int32),
+                     trace_accept=(n * n_chains * ((n_iters + 31) // 32), torch.int32))
         self.out = {k: torch.empty(sizes[k][0], dtype=sizes[k][1], device=device) for k in outputs}
         o = Outputs()
         for name, _ in Outputs._fields_[:-1]:

@@ -28,6 +28,7 @@ SOURCES = [
     "sampler_f64_naive.hip", "sampler_f64_pre.hip", "sampler_naive.hip",
     "sampler_f16x2.hip", "sampler_f16x1.hip", "sampler_bf16x1.hip",
     "sampler_lrn_f16x2.hip", "sampler_lrn_f16x1.hip", "sampler_lrn_bf16x1.hip", "mlp.hip", "static_ws.hip",
+    "sampler_mhgd_f64.hip", "sampler_mhgd_f16x2.hip", "sampler_mhgd_bf16x1.hip", "gx_loop.hip",
 ]
 
 

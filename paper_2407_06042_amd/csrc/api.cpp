@@ -9,6 +9,8 @@
 #include "common.hpp"
 #include "host.hpp"
 
+static_assert((int)DMALA_ERR_NONFINITE == dmala::kStatusNonfinite, "status code of a flagged instance");
+
 namespace dmala {
 namespace host {
 
@@ -34,9 +36,13 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
   if (p->n_chains < 1 || p->n_chains > 1024) return fail(DMALA_ERR_ARG, "n_chains must be in [1, 1024] (got %d)", p->n_chains);
   if (p->n_iters < 0 || p->n_iters > 65535) return fail(DMALA_ERR_ARG, "n_iters must be in [0, 65535] (got %d)", p->n_iters);
   if (p->precision < DMALA_FP64 || p->precision > DMALA_FP16) return fail(DMALA_ERR_ARG, "unknown precision %d", (int)p->precision);
-  if (p->proposal != DMALA_PRECOND && p->proposal != DMALA_NAIVE && p->proposal != DMALA_LEARNED)
+  if (p->proposal != DMALA_PRECOND && p->proposal != DMALA_NAIVE && p->proposal != DMALA_LEARNED &&
+      p->proposal != DMALA_MHGD)
     return fail(DMALA_ERR_ARG, "unknown proposal %d", (int)p->proposal);
   const bool lrn = p->proposal == DMALA_LEARNED;
+  const bool mhgd = p->proposal == DMALA_MHGD;
+  if (mhgd && p->precision == DMALA_FP16)
+    return fail(DMALA_ERR_UNSUPPORTED, "DMALA_MHGD runs with DMALA_FP64, DMALA_FP32 or DMALA_BF16");
   if (p->llr_mode < DMALA_LLR_IS || p->llr_mode > DMALA_LLR_MC) return fail(DMALA_ERR_ARG, "unknown llr_mode %d", (int)p->llr_mode);
   if (lrn) {
     if (p->precision == DMALA_FP64) return fail(DMALA_ERR_UNSUPPORTED, "DMALA_LEARNED is not available with DMALA_FP64");
@@ -60,6 +66,7 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
   sh.C = p->n_chains; sh.Cpad = 16 * ((sh.C + 15) / 16); sh.T = p->n_iters;
   sh.fp64 = fp64 ? 1 : 0;
   sh.lrn = lrn ? 1 : 0;
+  sh.mhgd = mhgd ? 1 : 0;
   sh.share = 0;
   pl.naive = p->proposal == DMALA_NAIVE;
   if (pl.naive) sh.pm = PM_NAIVE;
@@ -72,7 +79,7 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
   {
     const double am = p->alpha_mult > 0 ? p->alpha_mult : 1.0, bm = p->beta_mult > 0 ? p->beta_mult : 1.0;
     const double kL = 2.0 * 1.4426950408889634 / (am * bm);
-    sh.win = (!fp64 && !pl.naive && !lrn && Q >= 8 && kL * 12.0 >= 30.0 && kL <= 40.0) ? 3 : 0;
+    sh.win = (!fp64 && !pl.naive && !lrn && !mhgd && Q >= 8 && kL * 12.0 >= 30.0 && kL <= 40.0) ? 3 : 0;
   }
   if (fp64) {
     sh.frag_bytes = round_up((2 * (size_t)sh.Npad * sh.Npad + 2 * (size_t)sh.Npad) * 8, 16);
@@ -128,11 +135,14 @@ dmala_status hip_fail(hipError_t e, const char* what) {
 
 dmala_status enqueue(const void* H, const void* y, const void* sigma2, int32_t n_inst, const Plan& pl,
                      const dmala_params* p, const dmala_outputs* out, const InstDesc* desc, unsigned char* base,
-                     const int8_t* x_from, const int8_t* x_to, double* eval_out, hipStream_t stream) {
+                     const int8_t* x_from, const int8_t* x_to, double* eval_out, hipStream_t stream,
+                     double* eval_dim, double sigma2_val) {
   const Shape& sh = pl.sh;
   SetupArgs sa{};
   sa.desc = desc;
   sa.H = H; sa.y = y; sa.sigma2 = sigma2;
+  sa.sigma2_val = sigma2_val;
+  sa.status = (!eval_out && out) ? out->status : nullptr;
   sa.ws_inst = base + pl.inst_off; sa.inst_stride = sh.inst_bytes;
   sa.wscratch = base + pl.wscratch_off; sa.wscratch_stride = sh.wscratch_bytes;
   sa.n_inst = n_inst; sa.nt = sh.nt; sa.nr = sh.nr; sa.Q = sh.Q; sa.N = sh.N; sa.Npad = sh.Npad;
@@ -151,10 +161,11 @@ dmala_status enqueue(const void* H, const void* y, const void* sigma2, int32_t n
   ka.ws_state = base + pl.state_off; ka.state_stride = sh.state_bytes;
   ka.n_inst = n_inst; ka.N = sh.N; ka.Npad = sh.Npad; ka.C = sh.C; ka.Cpad = sh.Cpad; ka.T = sh.T;
   ka.key0 = (uint32_t)(p->seed & 0xFFFFFFFFu); ka.key1 = (uint32_t)(p->seed >> 32);
+  ka.ctr_base = p->counter_base;
   ka.frag_bytes = (int)sh.frag_bytes;
   const bool eval = eval_out != nullptr;
   if (eval) {
-    ka.x_from = x_from; ka.x_to = x_to; ka.eval_out = eval_out;
+    ka.x_from = x_from; ka.x_to = x_to; ka.eval_out = eval_out; ka.eval_dim = eval_dim;
   } else if (out) {
     ka.final_state = out->final_state; ka.accept_count = out->accept_count;
     ka.trace_accept = out->trace_accept; ka.trace_hash = out->trace_hash;
@@ -191,14 +202,15 @@ dmala_status enqueue(const void* H, const void* y, const void* sigma2, int32_t n
 
 dmala_status run(const void* H, const void* y, const void* sigma2, int32_t n_inst, const Plan& pl,
                  const dmala_params* p, const dmala_outputs* out, const int8_t* x_from, const int8_t* x_to,
-                 double* eval_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+                 double* eval_out, double* eval_dim, void* ws, size_t ws_bytes, hipStream_t stream) {
   if (!H || !y || !sigma2) return fail(DMALA_ERR_ARG, "H, y and sigma2 must be non-NULL");
   if (!ws) return fail(DMALA_ERR_WORKSPACE, "workspace is NULL");
   if (ws_bytes < pl.total) return fail(DMALA_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, pl.total);
   if (((uintptr_t)ws & 255) != 0) return fail(DMALA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-  if (out && out->train_rows && (pl.naive || pl.sh.fp64))
+  if (out && out->train_rows && (pl.naive || pl.sh.fp64 || pl.sh.mhgd))
     return fail(DMALA_ERR_UNSUPPORTED, "train_rows needs the PRECOND or LEARNED proposal without DMALA_FP64");
-  return enqueue(H, y, sigma2, n_inst, pl, p, out, nullptr, (unsigned char*)ws, x_from, x_to, eval_out, stream);
+  return enqueue(H, y, sigma2, n_inst, pl, p, out, nullptr, (unsigned char*)ws, x_from, x_to, eval_out, stream,
+                 eval_dim, 0.0);
 }
 
 }  // namespace host
@@ -224,7 +236,7 @@ dmala_status dmala_detect(const void* H, const void* y, const void* sigma2, int3
   if (st != DMALA_OK) return st;
   if (constellation && !canonical_qam(constellation, qam_order))
     return fail(DMALA_ERR_UNSUPPORTED, "constellation is not the canonical unit-energy square %d-QAM", qam_order);
-  st = run(H, y, sigma2, n_inst, pl, params, out, nullptr, nullptr, nullptr, workspace, workspace_bytes,
+  st = run(H, y, sigma2, n_inst, pl, params, out, nullptr, nullptr, nullptr, nullptr, workspace, workspace_bytes,
            (hipStream_t)stream);
   if (st == DMALA_OK) g_err.clear();
   return st;
@@ -232,7 +244,7 @@ dmala_status dmala_detect(const void* H, const void* y, const void* sigma2, int3
 
 dmala_status dmala_debug_eval(const void* H, const void* y, const void* sigma2, int32_t n_inst, int32_t nt, int32_t nr,
                               int32_t qam_order, const dmala_params* params, const int8_t* x_from, const int8_t* x_to,
-                              int32_t n_pairs, double* out, void* workspace, size_t workspace_bytes,
+                              int32_t n_pairs, double* out, double* out_dim, void* workspace, size_t workspace_bytes,
                               dmala_stream_t stream) {
   if (!params) return fail(DMALA_ERR_ARG, "params is NULL");
   if (!x_from || !x_to || !out) return fail(DMALA_ERR_ARG, "x_from, x_to and out must be non-NULL");
@@ -242,9 +254,83 @@ dmala_status dmala_debug_eval(const void* H, const void* y, const void* sigma2, 
   Plan pl;
   dmala_status st = make_plan(n_inst, nt, nr, qam_order, &p, pl);
   if (st != DMALA_OK) return st;
-  st = run(H, y, sigma2, n_inst, pl, &p, nullptr, x_from, x_to, out, workspace, workspace_bytes, (hipStream_t)stream);
+  st = run(H, y, sigma2, n_inst, pl, &p, nullptr, x_from, x_to, out, out_dim, workspace, workspace_bytes,
+           (hipStream_t)stream);
   if (st == DMALA_OK) g_err.clear();
   return st;
+}
+
+dmala_status dmala_sync_status(const int32_t* status, int32_t n_inst, dmala_stream_t stream) {
+  if (!status || n_inst < 1) return fail(DMALA_ERR_ARG, "status must be non-NULL and n_inst >= 1");
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  int32_t buf[1024];
+  int32_t flagged = 0, first = -1;
+  for (int32_t b0 = 0; b0 < n_inst; b0 += 1024) {
+    const int32_t n = n_inst - b0 < 1024 ? n_inst - b0 : 1024;
+    e = hipMemcpy(buf, status + b0, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "status copy");
+    for (int32_t i = 0; i < n; ++i)
+      if (buf[i] != DMALA_OK) {
+        ++flagged;
+        if (first < 0) first = b0 + i;
+      }
+  }
+  if (flagged)
+    return fail(DMALA_ERR_NONFINITE, "%d of %d instances have a non-finite entry in H or y, or sigma^2 not positive "
+                "and finite (first: instance %d)", flagged, n_inst, first);
+  g_err.clear();
+  return DMALA_OK;
+}
+
+namespace {
+dmala_params one_params(int32_t n_chains, int32_t n_iters, uint64_t seed) {
+  dmala_params p{};
+  p.n_chains = n_chains;
+  p.n_iters = n_iters;
+  p.seed = seed;
+  p.precision = DMALA_FP32;
+  p.proposal = DMALA_PRECOND;
+  p.llr_mode = DMALA_LLR_IS;
+  return p;
+}
+}  // namespace
+
+size_t dmala_detect_one_workspace_size(int32_t nt, int32_t nr, int32_t qam_order, int32_t n_chains) {
+  const dmala_params p = one_params(n_chains, 0, 0);
+  Plan pl;
+  if (make_plan(1, nt, nr, qam_order, &p, pl) != DMALA_OK) return 0;
+  g_err.clear();
+  return round_up(pl.total, 256) + 256;   // + the instance's status word
+}
+
+dmala_status dmala_detect_one(const void* H, const void* y, float sigma2, int32_t nt, int32_t nr,
+                              const float* constellation, int32_t qam_order, int32_t n_chains, int32_t n_iters,
+                              uint64_t seed, int32_t* symbols, float* marginals, void* workspace,
+                              size_t workspace_bytes, dmala_stream_t stream) {
+  const dmala_params p = one_params(n_chains, n_iters, seed);
+  Plan pl;
+  dmala_status st = make_plan(1, nt, nr, qam_order, &p, pl);
+  if (st != DMALA_OK) return st;
+  if (constellation && !canonical_qam(constellation, qam_order))
+    return fail(DMALA_ERR_UNSUPPORTED, "constellation is not the canonical unit-energy square %d-QAM", qam_order);
+  if (!H || !y || !symbols) return fail(DMALA_ERR_ARG, "H, y and symbols must be non-NULL");
+  if (!(sigma2 > 0.f) || !std::isfinite(sigma2))
+    return fail(DMALA_ERR_NONFINITE, "sigma^2 must be positive and finite (got %g)", (double)sigma2);
+  const size_t status_off = round_up(pl.total, 256);
+  if (!workspace) return fail(DMALA_ERR_WORKSPACE, "workspace is NULL");
+  if (workspace_bytes < status_off + 256)
+    return fail(DMALA_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", workspace_bytes, status_off + 256);
+  if (((uintptr_t)workspace & 255) != 0) return fail(DMALA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  dmala_outputs o{};
+  o.symbols = symbols;
+  o.marginals = marginals;
+  o.status = (int32_t*)((unsigned char*)workspace + status_off);
+  hipStream_t s = (hipStream_t)stream;
+  st = enqueue(H, y, nullptr, 1, pl, &p, &o, nullptr, (unsigned char*)workspace, nullptr, nullptr, nullptr, s, nullptr,
+               (double)sigma2);
+  if (st != DMALA_OK) return st;
+  return dmala_sync_status(o.status, 1, stream);
 }
 
 const char* dmala_last_error(void) { return g_err.c_str(); }

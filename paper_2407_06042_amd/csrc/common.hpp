@@ -38,11 +38,14 @@ struct InstParams {
   double tau;
   float scaleP;    // 2^-e of the packed proposal matrix
   float scaleE;    // 2^-e of the packed energy matrix
-  int32_t nonfinite;
+  int32_t nonfinite;  // 1: H or y has a non-finite entry, or sigma^2 is not positive and finite (Lemma 1
+                      // needs sigma^2 > 0); the sampler and the estimator then skip the instance
   int32_t pad_[3];
 };
 static_assert(sizeof(InstParams) <= 256, "params block");
 constexpr int kParamBytes = 256;
+// Per-instance status written by the setup kernel for a flagged instance (the C ABI's DMALA_ERR_NONFINITE).
+constexpr int32_t kStatusNonfinite = -3;
 
 // Floats per exported training row: 7 network features, the plain centre (Re, Im),
 // the plain precision (natural-log units), Q, 0.
@@ -64,6 +67,7 @@ struct Shape {
   int cbw;         // 16-chain blocks per workgroup for the one-wave layouts (1, 2 or 4)
   int lrn;         // 1: plain/learned kernel mixture (learned proposal network in the sampler)
   int share;       // 1: launched beside other classes' kernels (an uneven batch's graph branches)
+  int mhgd;        // 1: the MHGD baseline kernel (nearest-point candidate, MH without the proposal ratio)
   size_t inst_bytes;   // per-instance setup block
   size_t frag_bytes;   // MFMA fragments (MFMA path)
   size_t state_bytes;  // per-instance sampler->estimator block
@@ -117,6 +121,8 @@ __host__ __device__ inline InstDesc inst_desc(const InstDesc* d, int b, int nt, 
 struct SetupArgs {
   const InstDesc* desc;
   const void* H; const void* y; const void* sigma2;
+  double sigma2_val;   // the noise variance of every instance when sigma2 is NULL
+  int32_t* status;     // optional [caller's instance index]: 0, or DMALA_ERR_NONFINITE for a flagged instance
   unsigned char* ws_inst; size_t inst_stride;
   unsigned char* wscratch; size_t wscratch_stride;  // per-instance working matrix when nt > 32
   int n_inst, nt, nr, Q, N, Npad, RT, KB, fp64, pm, naive;
@@ -129,6 +135,7 @@ struct SamplerArgs {
   unsigned char* ws_state; size_t state_stride;
   int n_inst, N, Npad, C, Cpad, T;
   uint32_t key0, key1;
+  uint32_t ctr_base;      // the random counter's instance word is ctr_base + the caller's instance index
   int frag_bytes;
   int8_t* final_state; int32_t* accept_count; uint32_t* trace_accept; uint32_t* trace_hash;
   int trace_words;
@@ -138,6 +145,7 @@ struct SamplerArgs {
   float* train_rows;      // [sum Nt][n_chains] rows of kTrainRow floats at the final state
   // debug-eval mode
   const int8_t* x_from; const int8_t* x_to; double* eval_out;
+  double* eval_dim;       // optional per-dimension forward log q terms [n_inst][n_pairs][N]
 };
 
 struct EstArgs {

@@ -71,6 +71,21 @@ void estimate_kernel(EstArgs a) {
   const R* Hg = (const R*)a.H + 2 * dsc.h_off;
   const R* y = (const R*)a.y + 2 * dsc.y_off;
   const InstParams ip = *(const InstParams*)(a.ws_inst + (size_t)b * a.inst_stride);
+  if (ip.nonfinite) {
+    // a flagged instance (see the setup kernel): no samples to estimate from; symbols -1,
+    // every other output NaN (the whole workgroup leaves here)
+    const float nan = __builtin_nanf("");
+    for (int m = tid; m < nt; m += nth)
+      if (a.symbols) a.symbols[dsc.sym_off + m] = -1;
+    for (int e = tid; e < nt * M; e += nth) {
+      if (a.marginals) a.marginals[dsc.marg_off + e] = nan;
+      if (a.marginals_mc) a.marginals_mc[dsc.marg_off + e] = nan;
+    }
+    for (int e = tid; e < nt * 2 * NB; e += nth)
+      if (a.llrs) a.llrs[dsc.llr_off + e] = nan;
+    if (a.best_energy && tid == 0) a.best_energy[dsc.orig] = nan;
+    return;
+  }
   const R s = (R)ip.s, tau = (R)ip.tau;
   const R inv_s2 = R(1) / (R)ip.sigma2, inv_tau = R(1) / tau;
   const R cw = (tau - R(1)) * inv_tau;

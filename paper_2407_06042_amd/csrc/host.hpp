@@ -31,9 +31,12 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
 // Enqueue setup, sampler and estimator for n_inst instances of one class whose
 // workspace region starts at base (256-byte aligned); desc (device, may be NULL)
 // maps the instances to the caller's buffers.
+// sigma2 NULL: every instance has noise variance sigma2_val.  eval_dim: per-dimension forward
+// log q terms of the evaluation mode (may be NULL).
 dmala_status enqueue(const void* H, const void* y, const void* sigma2, int32_t n_inst, const Plan& pl,
                      const dmala_params* p, const dmala_outputs* out, const InstDesc* desc, unsigned char* base,
-                     const int8_t* x_from, const int8_t* x_to, double* eval_out, hipStream_t stream);
+                     const int8_t* x_from, const int8_t* x_to, double* eval_out, hipStream_t stream,
+                     double* eval_dim = nullptr, double sigma2_val = 0.0);
 
 }  // namespace host
 }  // namespace dmala

@@ -270,8 +270,8 @@ dmala_status dmala_plan_execute(dmala_plan P, const void* H, const void* y, cons
                                 void* workspace, size_t workspace_bytes, dmala_stream_t stream) {
   if (!P || !out) return fail(DMALA_ERR_ARG, "NULL plan or outputs");
   if (!H || !y || !sigma2) return fail(DMALA_ERR_ARG, "H, y and sigma2 must be non-NULL");
-  if (out->trace_accept || out->trace_hash) return fail(DMALA_ERR_UNSUPPORTED, "plans do not record traces");
-  if (out->train_rows && (P->params.proposal == DMALA_NAIVE || P->params.precision == DMALA_FP64))
+  if (out->train_rows && (P->params.proposal == DMALA_NAIVE || P->params.proposal == DMALA_MHGD ||
+                          P->params.precision == DMALA_FP64))
     return fail(DMALA_ERR_UNSUPPORTED, "train_rows needs the PRECOND or LEARNED proposal without DMALA_FP64");
   if (!workspace) return fail(DMALA_ERR_WORKSPACE, "workspace is NULL");
   if (workspace_bytes < P->ws_total)
@@ -279,7 +279,7 @@ dmala_status dmala_plan_execute(dmala_plan P, const void* H, const void* y, cons
   if (((uintptr_t)workspace & 255) != 0) return fail(DMALA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   const std::vector<const void*> key = {H, y, sigma2, out->symbols, out->marginals, out->llrs, out->best_energy,
                                         out->final_state, out->accept_count, out->marginals_mc, out->train_rows,
-                                        workspace};
+                                        out->status, out->trace_accept, out->trace_hash, workspace};
   if (!P->exec || key != P->key) {
     const dmala_status st = build_graph(P, H, y, sigma2, out, (unsigned char*)workspace);
     if (st != DMALA_OK) return st;

@@ -14,6 +14,9 @@ hipError_t launch_sampler_bf16x1(const Shape&, const SamplerArgs&, bool, hipStre
 hipError_t launch_sampler_lrn_f16x2(const Shape&, const SamplerArgs&, bool, hipStream_t);
 hipError_t launch_sampler_lrn_f16x1(const Shape&, const SamplerArgs&, bool, hipStream_t);
 hipError_t launch_sampler_lrn_bf16x1(const Shape&, const SamplerArgs&, bool, hipStream_t);
+hipError_t launch_sampler_mhgd_f64(const Shape&, const SamplerArgs&, bool, hipStream_t);
+hipError_t launch_sampler_mhgd_f16x2(const Shape&, const SamplerArgs&, bool, hipStream_t);
+hipError_t launch_sampler_mhgd_bf16x1(const Shape&, const SamplerArgs&, bool, hipStream_t);
 
 size_t sampler_lds_bytes(const Shape& sh) {
   if (sh.fp64) {
@@ -54,6 +57,12 @@ int sampler_default_cfg(const Shape& sh) {
 }
 
 hipError_t launch_sampler(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+  if (sh.mhgd) {
+    if (sh.fp64) return launch_sampler_mhgd_f64(sh, a, eval, s);
+    if (sh.pm == PM_F16X2) return launch_sampler_mhgd_f16x2(sh, a, eval, s);
+    if (sh.pm == PM_BF16X1) return launch_sampler_mhgd_bf16x1(sh, a, eval, s);
+    return hipErrorInvalidValue;
+  }
   if (sh.fp64) return sh.pm == PM_NAIVE ? launch_sampler_f64_naive(sh, a, eval, s) : launch_sampler_f64_pre(sh, a, eval, s);
   if (sh.lrn) {
     switch (sh.pm) {

@@ -46,6 +46,38 @@ __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x)
 __device__ __forceinline__ float lg2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ double ex2(double x) { return exp2(x); }
 __device__ __forceinline__ double lg2(double x) { return log2(x); }
+// Inverse of the standard normal CDF (the device math library's).
+__device__ __forceinline__ float ncdf_inv(float u) { return normcdfinvf(u); }
+__device__ __forceinline__ double ncdf_inv(double u) { return normcdfinv(u); }
+__device__ __forceinline__ float erfc_(float x) { return erfcf(x); }
+__device__ __forceinline__ double erfc_(double x) { return erfc(x); }
+
+// Standard normal deviate Phi^-1(u) of a random word, u = (x + 1/2) 2^-24 with x its high 24 bits.
+// The upper half uses Phi^-1(u) = -Phi^-1(1 - u), so that the argument (x + 1/2 or 2^24 - x - 1/2,
+// times 2^-24) is exact in fp32 as well.
+template <typename R>
+__device__ __forceinline__ R gauss_of_word(uint32_t w) {
+  const uint32_t x = w >> 8;
+  const bool up = x >= (1u << 23);
+  const R a = up ? R((1u << 24) - x) - R(0.5) : R(x) + R(0.5);
+  const R z = ncdf_inv(a * R(5.9604644775390625e-08));
+  return up ? -z : z;
+}
+
+// MHGD candidate law of one dimension: log2 of the probability that the nearest level
+// of N(mu, sig^2) (index units, levels 0..Q-1, edge cells unbounded) is j.  Each cell
+// is integrated on the tail side away from mu, where erfc keeps small cells accurate.
+template <int Q, typename R>
+__device__ __forceinline__ R mhgd_log2_cell(int j, R mu, R sig) {
+  const R r2 = R(0.70710678118654752440) / sig;
+  const R lo = (R(j) - R(0.5) - mu) * r2, hi = (R(j) + R(0.5) - mu) * r2;
+  const bool first = j == 0, last = j == Q - 1;
+  R p;
+  if (!first && lo > R(0)) p = R(0.5) * (erfc_(lo) - (last ? R(0) : erfc_(hi)));
+  else if (!last && hi < R(0)) p = R(0.5) * (erfc_(-hi) - (first ? R(0) : erfc_(-lo)));
+  else p = R(1) - R(0.5) * ((first ? R(0) : erfc_(-lo)) + (last ? R(0) : erfc_(hi)));
+  return lg2(p);
+}
 
 // Mode of the discretised Gaussian exp2(-kL (j - mu)^2) over j in [0, Q).
 template <int Q, typename R>
@@ -284,11 +316,14 @@ struct Red {
 // chain block splitting the dimensions (RT = RTW * WD tiles in all), MG = the
 // packed matrices are read from the instance block in global memory (L2) instead
 // of being staged in LDS.
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int LRN>
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND>
 __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   constexpr bool F64 = std::is_same<Real, double>::value;
+  constexpr bool LRN = KND == 1;   // plain/learned kernel mixture
+  constexpr bool MHG = KND == 2;   // the MHGD baseline (nearest-point candidate, MH without the proposal ratio)
   static_assert(!F64 || (WD == 1 && !MG), "the float64 path uses one wave per chain block and LDS matrices");
   static_assert(!LRN || (!F64 && PM != PM_NAIVE && WIN == 0 && RTW <= 4), "learned variant: float, preconditioned, no window");
+  static_assert(!MHG || (PM != PM_NAIVE && WIN == 0), "MHGD: the preconditioned gradient step, no proposal window");
   static_assert(WD == 1 || RTW % 2 == 0, "dimension-split waves own whole K blocks");
   constexpr int RT = RTW * WD;
   constexpr int D = 4 * RTW;
@@ -307,6 +342,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   const unsigned char* blk = a.ws_inst + (size_t)inst * a.inst_stride;
   // the caller's instance index (RNG counter, per-instance outputs) and final-state offset
   const uint32_t rid = a.desc ? (uint32_t)a.desc[inst].orig : (uint32_t)inst;
+  const uint32_t rctr = rid + a.ctr_base;                 // instance word of the random counter
   const size_t fs_base = a.desc ? (size_t)a.desc[inst].fs_off : (size_t)inst * a.C * N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int cl = lane & 15, h = lane >> 4;
@@ -315,6 +351,36 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   const int chain = cblock * 16 + cl;
   const bool live = chain < a.C;
   const int rt0 = wd * RTW;                               // first row tile owned
+
+  // A flagged instance (a non-finite entry in H or y, or sigma^2 not positive and finite):
+  // no chain runs; the optional per-chain outputs are written as zeros (evaluation: NaN).
+  // The flag belongs to the workgroup's one instance, so every thread leaves here.
+  if (((const InstParams*)blk)->nonfinite) {
+    if (live && h == 0 && wd == 0) {
+      if constexpr (EVAL) {
+        double* o = a.eval_out + ((size_t)inst * a.C + chain) * 4;
+        for (int i = 0; i < 4; ++i) o[i] = __builtin_nan("");
+        if (a.eval_dim)
+          for (int n = 0; n < N; ++n) a.eval_dim[((size_t)inst * a.C + chain) * N + n] = __builtin_nan("");
+      } else {
+        const size_t trow = (size_t)rid * a.C + chain;
+        if (a.accept_count) a.accept_count[trow] = 0;
+        if (a.final_state)
+          for (int n = 0; n < N; ++n) a.final_state[fs_base + (size_t)chain * N + n] = 0;
+        if (a.trace_accept)
+          for (int w = 0; w < a.trace_words; ++w) a.trace_accept[trow * a.trace_words + w] = 0u;
+        if (a.trace_hash)
+          for (int t = 0; t < a.T; ++t) a.trace_hash[trow * a.T + t] = 0u;
+        if (a.train_rows) {
+          const int Nt = N >> 1;
+          const int64_t sym0 = a.desc ? a.desc[inst].sym_off : (int64_t)inst * Nt;
+          float* row = a.train_rows + ((size_t)sym0 * a.C + (size_t)chain * Nt) * kTrainRow;
+          for (int i = 0; i < Nt * kTrainRow; ++i) row[i] = 0.f;
+        }
+      }
+    }
+    return;
+  }
 
   // stage the instance's packed matrices and vectors in LDS
   const size_t mat_bytes = F64 ? 0 : (size_t)(NPP + kEPasses) * RT * KB * 1024;
@@ -341,6 +407,9 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
 
   const Real kL = (Real)ip.kL;
   const Real rho = (Real)ip.rho;
+  // MHGD: standard deviation of the random walk in index units, sqrt(alpha beta) / (2 s)
+  // = sqrt(log2(e) / (2 kL))
+  const Real msig = (Real)sqrt(kLog2e / (2.0 * ip.kL));
   const Real sP = (Real)ip.scaleP, sE = (Real)ip.scaleE;
   const Real* pbv;
   const Real* ezv;
@@ -627,7 +696,24 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
     }
     Real lqf = 0, lqr = 0, T2 = 0;
     Real mup[D], lzp[D], egp[D];
-    if constexpr (LRN) {
+    // per-dimension forward terms (log2 units) for the optional per-dimension output
+    auto dim_out = [&](int d, Real v) {
+      if (a.eval_dim && live && valid[d])
+        a.eval_dim[((size_t)inst * a.C + chain) * N + dim_of(d)] = (double)v * (1.0 / kLog2e);
+    };
+    if constexpr (MHG) {
+      grad_at(kc, mu, eg, nohook);
+      grad_at(kt, mup, egp, nohook);
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+        if (valid[d]) {
+          const Real fd = mhgd_log2_cell<Q>(kt[d], mu[d], msig);
+          lqf += fd;
+          lqr += mhgd_log2_cell<Q>(kc[d], mup[d], msig);
+          T2 -= Real(kt[d] - kc[d]) * (eg[d] + egp[d]);
+          dim_out(d, fd);
+        }
+    } else if constexpr (LRN) {
       // the learned kernel alone (the mixture's other component is the plain kernel)
       Real muL[D], kLL[D], muLp[D], kLLp[D];
       grad_at(kc, mu, eg, nohook);
@@ -638,15 +724,21 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
       for (int d = 0; d < D; ++d)
         if (valid[d]) {
           const Real tf = Real(kt[d]) - muL[d], tr = Real(kc[d]) - muLp[d];
-          lqf += -kLL[d] * tf * tf - log2_norm<Q, 0, W, false>(muL[d], kLL[d], wc);
+          const Real fd = -kLL[d] * tf * tf - log2_norm<Q, 0, W, false>(muL[d], kLL[d], wc);
+          lqf += fd;
           lqr += -kLLp[d] * tr * tr - log2_norm<Q, 0, W, false>(muLp[d], kLLp[d], wc);
           T2 -= Real(kt[d] - kc[d]) * (eg[d] + egp[d]);
+          dim_out(d, fd);
         }
     } else {
       proposal_at(kc, mu, lz, eg);
 #pragma unroll
       for (int d = 0; d < D; ++d)
-        if (valid[d]) lqf += lq(kt[d], mu[d], lz[d]);
+        if (valid[d]) {
+          const Real fd = lq(kt[d], mu[d], lz[d]);
+          lqf += fd;
+          dim_out(d, fd);
+        }
       proposal_at(kt, mup, lzp, egp);
 #pragma unroll
       for (int d = 0; d < D; ++d)
@@ -667,7 +759,8 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
       o[0] = (double)lqf * ln2;
       o[1] = (double)lqr * ln2;
       o[2] = (double)T2 * ln2;
-      o[3] = ((double)T2 + (double)lqr - (double)lqf) * ln2;
+      // MHGD's test leaves the proposal ratio out
+      o[3] = (MHG ? (double)T2 : ((double)T2 + (double)lqr - (double)lqf)) * ln2;
     }
     return;
   } else {
@@ -675,7 +768,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
     // initial state from the t = 0 words
 #pragma unroll
     for (int rt = 0; rt < RTW; ++rt) {
-      uint32_t c[4] = {(uint32_t)(4 * (rt0 + rt) + h), 0u, (uint32_t)chain, rid};
+      uint32_t c[4] = {(uint32_t)(4 * (rt0 + rt) + h), 0u, (uint32_t)chain, rctr};
       philox4x32_10<PIPE>(c, key0, key1);
 #pragma unroll
       for (int i = 0; i < 4; ++i) kc[rt * 4 + i] = (int)(((uint64_t)(c[i] >> 8) * Q) >> 24);
@@ -687,8 +780,10 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
       learned_at(kc, mu, muL, kLL);
     } else {
       grad_at(kc, mu, eg, nohook);
+      if constexpr (KND == 0) {
 #pragma unroll
-      for (int d = 0; d < D; ++d) lzs += log2_norm<Q, WIN, W, TAB>(mu[d], kL, wc);
+        for (int d = 0; d < D; ++d) lzs += log2_norm<Q, WIN, W, TAB>(mu[d], kL, wc);
+      }
     }
     // E(x) = ||y||^2 + x^T g - z^T x = ||y||^2 + (eunit/2) sum_n lv_n (eg_n - ez_n)
     Real ep = 0;
@@ -716,7 +811,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
     // the registers they would hold meanwhile are not free).
     uint32_t w[RTW][4];
     auto word_block = [&](int rt, int tt) {
-      w[rt][0] = (uint32_t)(4 * (rt0 + rt) + h); w[rt][1] = (uint32_t)tt; w[rt][2] = (uint32_t)chain; w[rt][3] = rid;
+      w[rt][0] = (uint32_t)(4 * (rt0 + rt) + h); w[rt][1] = (uint32_t)tt; w[rt][2] = (uint32_t)chain; w[rt][3] = rctr;
       philox4x32_10<PIPE>(w[rt], key0, key1);
     };
     if constexpr (PIPE) {
@@ -733,7 +828,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
       // regenerates block 1 of the stream, so no lane has to broadcast it
       bool useL = false;
       if constexpr (LRN) {
-        uint32_t wm[4] = {1u, (uint32_t)t, (uint32_t)chain, rid};
+        uint32_t wm[4] = {1u, (uint32_t)t, (uint32_t)chain, rctr};
         philox4x32_10<PIPE>(wm, key0, key1);
         useL = low_bytes24(wm[0], wm[1], wm[2]) >= a.mix_thr;
       }
@@ -746,7 +841,11 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
         Real u;
         if constexpr (F64) u = u24d(w[d >> 2][d & 3]);
         else u = u24f(w[d >> 2][d & 3]);
-        if constexpr (LRN) {
+        if constexpr (MHG) {
+          // gradient step + Gaussian random walk, mapped to the nearest level (rint, clamped)
+          const int kd = (int)mode_of<Q>(mu[d] + msig * gauss_of_word<Real>(w[d >> 2][d & 3]));
+          kp[d] = valid[d] ? kd : kc[d];
+        } else if constexpr (LRN) {
           const float ms = useL ? muL[d] : mu[d], ks = useL ? kLL[d] : (float)kL;
           float lzf;
           const int kd = draw_level_lz<Q>(ms, ks, u, lzf);
@@ -760,7 +859,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
           tq += t0 * t0;
         }
       }
-      if constexpr (!LRN) S = kL * tq + lzs;
+      if constexpr (KND == 0) S = kL * tq + lzs;
       // the MH word is held by the lanes that own dimensions 0..3 (h = 0 of the first slice)
       const uint32_t um = low_bytes24(w[0][0], w[0][1], w[0][2]);
       auto next_words = [&](int rt) {
@@ -776,7 +875,11 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
       Real mup[D], egp[D], lzps = 0;
       Real muLp[D], kLLp[D];
       Real T2 = 0;
-      if constexpr (LRN) {
+      if constexpr (MHG) {
+        grad_at(kp, mup, egp, next_words);
+#pragma unroll
+        for (int d = 0; d < D; ++d) T2 -= (Real(kp[d]) - Real(kc[d])) * (eg[d] + egp[d]);
+      } else if constexpr (LRN) {
         grad_at(kp, mup, egp, next_words);
         learned_at(kp, mup, muLp, kLLp);
 #pragma unroll
@@ -833,7 +936,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
           kLL[d] = acc ? kLLp[d] : kLL[d];
         }
       }
-      if constexpr (!LRN) lzs = acc ? lzps : lzs;
+      if constexpr (KND == 0) lzs = acc ? lzps : lzs;
       E = acc ? E - T2 * eunit : E;
       nacc += acc ? 1 : 0;
       if (E < Ebest) {
@@ -891,16 +994,16 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   }
 }
 
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int LRN>
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND>
 __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
-  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, LRN>(a);
+  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND>(a);
 }
 
 // The same kernel held to two waves per SIMD (at most 256 registers): the
 // learned variant with two row tiles per wave fits without spilling.
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int LRN>
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sampler_kernel_w2(SamplerArgs a) {
-  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, LRN>(a);
+  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND>(a);
 }
 
 // LDS bytes of a configuration.
@@ -916,8 +1019,9 @@ inline size_t sampler_cfg_lds(const Shape& sh, int rtw, int wd, bool mg, int wav
   return staged;
 }
 
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, int WIN, int LRN = 0>
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, int WIN, int KND = 0>
 hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+  constexpr bool LRN = KND == 1;
   const int chain_blocks = sh.Cpad / 16;
   int waves, gy;
   if (WD > 1) { waves = WD; gy = chain_blocks; }
@@ -938,13 +1042,13 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
   constexpr bool kW2Alone = !LRN && RTW == 4 && !std::is_same<Real, double>::value && WD == 4 && WIN == 0 && PM != PM_NAIVE;
   void (*k)(SamplerArgs);
   if (eval) {
-    if constexpr (kW2Eval) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, true, WIN, LRN>;
-    else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN, LRN>;
+    if constexpr (kW2Eval) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, true, WIN, KND>;
+    else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN, KND>;
   } else {
-    if constexpr (kW2) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>;
-    else if constexpr (kW2Alone) k = sh.share ? sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>
-                                              : sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>;
-    else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, LRN>;
+    if constexpr (kW2) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, KND>;
+    else if constexpr (kW2Alone) k = sh.share ? sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, KND>
+                                              : sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, KND>;
+    else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, KND>;
   }
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -989,6 +1093,37 @@ hipError_t launch_rt(const Shape& sh, const SamplerArgs& a, bool eval, hipStream
     }
     return hipErrorInvalidValue;
   }
+}
+
+// The MHGD baseline on the plain layouts (every Q weighted directly: there is no window).
+template <typename Real, int RTW, int WD, bool MG, int PM>
+hipError_t launch_q_mhg(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+  switch (sh.Q) {
+    case 2: return launch_t<Real, RTW, WD, MG, 2, PM, 0, 2>(sh, a, eval, s);
+    case 4: return launch_t<Real, RTW, WD, MG, 4, PM, 0, 2>(sh, a, eval, s);
+    case 8: return launch_t<Real, RTW, WD, MG, 8, PM, 0, 2>(sh, a, eval, s);
+    case 16: return launch_t<Real, RTW, WD, MG, 16, PM, 0, 2>(sh, a, eval, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename Real, int PM>
+hipError_t launch_rt_mhg(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+  if constexpr (std::is_same<Real, double>::value) {
+    switch (sh.RT) {
+      case 2: return launch_q_mhg<Real, 2, 1, false, PM>(sh, a, eval, s);
+      case 4: return launch_q_mhg<Real, 4, 1, false, PM>(sh, a, eval, s);
+    }
+  } else {
+    switch (sh.cfg) {
+      case 0: return launch_q_mhg<Real, 2, 1, false, PM>(sh, a, eval, s);
+      case 1: return launch_q_mhg<Real, 4, 1, false, PM>(sh, a, eval, s);
+      case 2: return launch_q_mhg<Real, 8, 1, false, PM>(sh, a, eval, s);
+      case 3: return launch_q_mhg<Real, 4, 2, true, PM>(sh, a, eval, s);
+      case 4: return launch_q_mhg<Real, 4, 4, true, PM>(sh, a, eval, s);
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 // Learned-mixture instances: layouts with at most 4 row tiles per wave (cfg 0, 1, 3, 4) and the

@@ -1,0 +1,8 @@
+// Sampler instances: the MHGD baseline, float arithmetic, proposal mode PM_F16X2.
+#include "sampler_impl.hpp"
+
+namespace dmala {
+hipError_t launch_sampler_mhgd_f16x2(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+  return launch_rt_mhg<float, PM_F16X2>(sh, a, eval, s);
+}
+}  // namespace dmala

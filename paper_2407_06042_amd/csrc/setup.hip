@@ -150,7 +150,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 
   const InstDesc dsc = inst_desc(a.desc, b, nt, nr, a.Q * a.Q, 1);
   const TIn* Hg = (const TIn*)a.H + 2 * dsc.h_off;
   const TIn* y = (const TIn*)a.y + 2 * dsc.y_off;
-  const double sigma2 = (double)((const TIn*)a.sigma2)[dsc.orig];
+  const double sigma2 = a.sigma2 ? (double)((const TIn*)a.sigma2)[dsc.orig] : a.sigma2_val;
   extern __shared__ double smem_setup[];
   // nt x ld working matrix: in LDS, or (large nt) in this instance's slice of the workspace
   cd* W;
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 
   }
   __syncthreads();
   yy = block_reduce(yy, red, false);
-  if (!isfinite(yy) || !(sigma2 > 0.0)) nonfinite = 1.0;
+  if (!isfinite(yy) || !(sigma2 > 0.0) || !isfinite(sigma2)) nonfinite = 1.0;
   nonfinite = block_reduce(nonfinite, red, true);
 
   const double cE = 2.0 * s * s * kLog2e / (tau * sigma2);
@@ -435,6 +435,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 
     ip.nonfinite = nonfinite > 0.0 ? 1 : 0;
     ip.pad_[0] = ip.pad_[1] = ip.pad_[2] = 0;
     *(InstParams*)blk = ip;
+    if (a.status) a.status[dsc.orig] = ip.nonfinite ? kStatusNonfinite : 0;
   }
 }
 

@@ -63,7 +63,7 @@ extern "C" dmala_status dmala_detect_static(const void* H, const void* y, const 
                 "(use dmala_detect with a caller workspace, or fewer instances per call)",
                 pl.total, (size_t)DMALA_STATIC_SCRATCH_BYTES);
   if (!H || !y || !sigma2) return fail(DMALA_ERR_ARG, "H, y and sigma2 must be non-NULL");
-  if (out && out->train_rows && (pl.naive || pl.sh.fp64))
+  if (out && out->train_rows && (pl.naive || pl.sh.fp64 || pl.sh.mhgd))
     return fail(DMALA_ERR_UNSUPPORTED, "train_rows needs the PRECOND or LEARNED proposal without DMALA_FP64");
   unsigned char* base = nullptr;
   st = scratch_for_current_device(&base);

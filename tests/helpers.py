@@ -37,16 +37,45 @@ def run_oracle(b, i, n_chains, n_iters, seed, proposal="precond", tau=2.0, trace
                       variant=proposal, tau=tau, trace=trace, estimators=estimators, **kw)
 
 
+# Near-tie thresholds of the chain-identity tests (oracle decision margins below which the GPU may
+# decide a draw differently).  float64 path: a few ulps.  fp32 path: from the errors measured by
+# tests/test_gpu_near_ties.py on real trajectories (32x32 64-QAM at 16/22/28 dB, 128x128 256-QAM
+# rho 0.5 at 30 dB), kept at least EPS32_SAFETY times above the maxima:
+#   categorical draws: per-dimension |log q_fp32 - log q_fp64| <= 6.0e-6 (preconditioned),
+#     2.6e-5 (naive, 28 dB); an error delta in every log-probability moves each CDF value by at
+#     most about delta, so margins below 1.2e-4 are near-ties;
+#   MH test: |log A_fp32 - log A_fp64| <= 1.9e-7 (E + E') / (tau sigma^2) (up to 8.5e-3 in absolute
+#     terms at 128x128, 30 dB), so the threshold is max(2e-3, 2^-20 (E + E') / (tau sigma^2)).
+EPS64 = (1e-9, 1e-9)
+EPS32 = (1.2e-4, 2e-3)
+EPS32_REL = 2.0 ** -20
+EPS32_SAFETY = 4.0
+
+
+def eps32_mh(scale):
+    """fp32 MH near-tie threshold for tempered energy scale (E + E') / (tau sigma^2)."""
+    return np.maximum(EPS32[1], EPS32_REL * np.asarray(scale))
+
+
+def mh_scale(orc):
+    """(E + E') / (tau sigma^2) of every transition of an oracle trace, shape (T, C)."""
+    tr, prob = orc["trace"], orc["problem"]
+    E_before = np.concatenate([tr["init_E"][None], tr["E"][:-1]], axis=0)
+    return (E_before + tr["E_prop"]) / (prob.tau * prob.sigma2)
+
+
 def compare_chains(gpu_hash, orc, eps_cat, eps_mh):
     """Per-chain agreement of a GPU trajectory with the oracle's.
 
     gpu_hash: (C, T) state fingerprints after each transition.  A chain passes
     if its first disagreement is at or after its first near-tie draw (oracle
-    margin below eps).  Returns (n_identical, n_flagged_diverged, bad_chains).
+    margin below eps; eps_mh may be a function of the transition's tempered
+    energy scale, see eps32_mh).  Returns (n_identical, n_flagged_diverged, bad_chains).
     """
     tr = orc["trace"]
     T, C = tr["hash"].shape
-    flag = (tr["cat_margin"] < eps_cat) | (tr["mh_margin"] < eps_mh)
+    emh = eps_mh(mh_scale(orc)) if callable(eps_mh) else eps_mh
+    flag = (tr["cat_margin"] < eps_cat) | (tr["mh_margin"] < emh)
     n_id, n_fd, bad = 0, 0, []
     for c in range(C):
         f = np.nonzero(flag[:, c])[0]

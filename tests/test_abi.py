@@ -131,3 +131,42 @@ def test_llr_mode_validation():
     with pytest.raises(dm.DmalaError) as e:
         dm.workspace_size(2, 4, 4, 16, p)
     assert "llr_mode" in str(e.value)
+
+
+def test_detect_one_checks_sigma2_and_arguments_on_the_host():
+    """dmala_detect_one refuses sigma^2 <= 0 or non-finite with DMALA_ERR_NONFINITE before any launch
+    (Lemma 1 needs sigma^2 > 0), and validates the constellation and the workspace."""
+    L = dm.lib()
+    need = L.dmala_detect_one_workspace_size(4, 4, 16, 16)
+    assert need >= dm.workspace_size(1, 4, 4, 16, dm.make_params(16, 10, 1)) + 256
+    assert L.dmala_detect_one_workspace_size(4, 4, 8, 16) == 0
+    f = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x10000)
+    for s2 in (0.0, -1.0, float("nan"), float("inf")):
+        st = L.dmala_detect_one(f, f, s2, 4, 4, None, 16, 16, 10, 1, f, None, ws, need, None)
+        assert st == -3 and "sigma" in dm.last_error(), s2
+    bad = (ctypes.c_float * 32)(*([0.5] * 32))
+    assert L.dmala_detect_one(f, f, 0.1, 4, 4, bad, 16, 16, 10, 1, f, None, ws, need, None) == -2
+    assert L.dmala_detect_one(f, f, 0.1, 4, 4, None, 16, 16, 10, 1, None, None, ws, need, None) == -1
+    assert L.dmala_detect_one(f, f, 0.1, 4, 4, None, 16, 16, 10, 1, f, None, ws, need - 1, None) == -4
+    assert L.dmala_detect_one(f, f, 0.1, 4, 4, None, 16, 16, 10, 1, f, None, ctypes.c_void_p(0x10010), need, None) == -4
+    assert L.dmala_sync_status(None, 4, None) == -1
+    assert L.dmala_sync_status(f, 0, None) == -1
+
+
+def test_mhgd_proposal_validation():
+    assert dm.workspace_size(2, 8, 8, 16, dm.make_params(16, 10, 1, proposal="mhgd")) > 0
+    assert dm.workspace_size(2, 8, 8, 16, dm.make_params(16, 10, 1, proposal="mhgd", precision="bf16")) > 0
+    assert dm.workspace_size(2, 8, 8, 16, dm.make_params(16, 10, 1, proposal="mhgd", precision="fp64")) > 0
+    with pytest.raises(dm.DmalaError) as e:
+        dm.workspace_size(2, 8, 8, 16, dm.make_params(16, 10, 1, proposal="mhgd", precision="fp16"))
+    assert "MHGD" in str(e.value)
+    L = dm.lib()
+    p = dm.make_params(16, 10, 1, proposal="mhgd")
+    o = dm.Outputs()
+    o.train_rows = 0x3000
+    fake = ctypes.c_void_p(0x1000)
+    need = dm.workspace_size(2, 4, 4, 16, p)
+    st = L.dmala_detect(fake, fake, fake, 2, 4, 4, 16, None, ctypes.byref(p), ctypes.byref(o), ctypes.c_void_p(0x10000),
+                        need, None)
+    assert st == -2 and "train_rows" in dm.last_error()
