@@ -1,16 +1,29 @@
 #!/usr/bin/env python
-"""Throughput of the DMALA detector on one MI355X.
+"""Throughput of the DMALA detector on one MI355X, at matched symbol error rate.
 
-Workload (default): 32x32 MIMO, 64-QAM (unit energy), i.i.d. Rayleigh CN(0, 1/Nr),
-SNR 16..28 dB in 2 dB steps with 1024 realisations per SNR (7168 detection
-problems), 32 chains x 100 MH transitions each, float32-class arithmetic,
-preconditioned proposal, tau = 2.  One step = one dmala_detect call over the
-whole batch (setup, sampler and estimator kernels), inputs resident in HBM.
+Headline workload (the learned-proposal evaluation configuration, where the metric's
+plain / BF16 / learned comparison is defined): 64x64 MIMO, 64-QAM (unit energy), i.i.d.
+Rayleigh CN(0, 1/Nr), SNR 20, 22, 24, 26 dB with 2048 realisations each (8192 detection
+problems), 32 chains per problem, preconditioned DMALA, tau = 2.  `value` is the plain
+fp32-class form at 100 MH transitions: one step = one dmala_detect call over the whole
+batch (setup, sampler and estimator kernels), inputs resident in HBM, chain-iterations/s.
 
-Prints one JSON line: chain-iterations/s (value), detected vectors/s, SER per
-SNR, the BF16-gradient form's throughput and SER, the sampler kernel's
-roofline figures measured with HIP events around that kernel, and the float64
-oracle timed on the host cores on a bounded sample of the same workload.
+The same JSON line carries:
+* matched SER: every form (fp32, BF16 gradient, BF16 + learned proposal) swept over the
+  number of transitions; for each form the fastest setting whose SER is not worse than the
+  fp32 form at 100 transitions within a paired 95 % confidence interval, with its detected
+  vectors/s and its speed-up; the learned network is first trained on the GPU (own kernels)
+  on 32x32 64-QAM and 128x128 256-QAM chains;
+* the same comparison on 8x8 64-QAM at 22-26 dB, where the detector beats linear MMSE
+  (the SER of an MMSE detector on the same inputs is reported beside both workloads);
+* timed extra workloads: the 32x32 64-QAM SNR sweep (7168 problems, 32 x 100), the
+  4096-problem uneven batch in one plan launch (32 x 100), the 128x128 256-QAM Kronecker
+  system (256 problems, 64 x 200); per form: ms, stage times, chain-iterations/s, vectors/s, SER;
+* roofline of the dominant kernel (the sampler of the headline step) against the VALU
+  lane-operation peak, and the G.X stage alone (dmala_gx_loop) against the bf16 MFMA peak at
+  the 32x32, 64x64 and 128x128 shapes;
+* the float64 oracle timed on the host cores (16 worker processes, the GPU machine's CPU share,
+  and one core) on a bounded sample of the headline workload.
 """
 import argparse
 import ctypes
@@ -28,44 +41,49 @@ sys.path.insert(0, ROOT)
 import workloads as W  # noqa: E402
 
 METRIC = "chain-iterations/s and detected vectors/s at matched SER (plain vs BF16/learned)"
-NT = NR = 32
-M = 64
-CHAINS, ITERS = 32, 100
-SNRS = (16, 18, 20, 22, 24, 26, 28)
-SEED = 0x240706042002
+SEED = 0x240706042005
+C5_NT, C5_M, C5_C, C5_T = 64, 64, 32, 100
+C5_SNRS = (20, 22, 24, 26)
 
 # MI355X published peaks
-PEAK_FP32_VECTOR = 157.3e12          # published: packed fp32 FMA, 256 flop/clk/CU
-# ALU roofline of the sampler: one VALU lane operation per lane per clock, non-packed
-# (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz); the build disables packed fp32 and most of the
-# chain's operations are not FMAs (compares, selects, exponentials, integer multiplies).
+PEAK_FP32_VECTOR = 157.3e12          # packed fp32 FMA, 256 flop/clk/CU
+PEAK_BF16_MFMA = 2.5e15              # dense bf16 / fp16 matrix
+# VALU lane-operation roof of the chain kernel: one non-packed lane operation per lane per clock,
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (the build disables packed fp32; the chain's operations
+# are mostly compares, selects, exponentials and integer multiplies, not FMAs)
 PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9
-PEAK_BF16_MFMA = 2.5e15
+CPU_WORKERS = 16                     # the GPU machine's host-CPU share for one GPU
 
 
-def algorithmic_ops_per_chain_iter(nt, nr, M):
-    """VALU work of one chain-iteration that the method must do (per-unit figure).
+def progress(msg):
+    """Phase marker on stderr (the JSON line is the only stdout output)."""
+    print("[bench %.1fs] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
 
-    Counts: logits + CDF 6 N Q, exponentials N Q, logarithms N, Philox
-    ceil((N+2)/4) blocks of 10 rounds x 6 ops, energy and MH terms 4 Nr + 2 N
-    (N = 2 Nt real dimensions, Q = sqrt(M)).  The G.x contraction (8 Nt^2
-    flops) runs on MFMA and is reported separately.
-    """
+
+_T0 = time.perf_counter()
+
+
+def valu_ops_per_chain_iter(nt, M):
+    """Algorithmic VALU lane operations of one chain-transition (per-unit work, N = 2 Nt, Q = sqrt M):
+    logits and CDF 6 N Q, two exponentials per dimension (the quadratic-logit recurrence), one
+    logarithm (the product of the normaliser sums), Philox ceil((N+2)/4) blocks x 10 rounds x 6,
+    energy difference and MH sums 2 N.  The G.x contraction (8 Nt^2 flops) runs on MFMA."""
     N, Q = 2 * nt, int(round(np.sqrt(M)))
-    return 6 * N * Q + N * Q + N + 60 * ((N + 2 + 3) // 4) + 4 * nr + 2 * N
+    return 6 * N * Q + 2 * N + 1 + 60 * ((N + 2 + 3) // 4) + 2 * N
 
 
-def gx_flops_per_chain_iter(nt):
-    return 8 * nt * nt
-
-
-def source_hash():
+def source_hash(files):
     h = hashlib.sha256()
-    for f in ("common.hpp", "sampler_impl.hpp", "sampler_f16x2.hip"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2407_06042_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
+
+SAMPLER_SOURCES = ("common.hpp", "sampler_impl.hpp", "mlp_device.hpp", "sampler_f16x2.hip")
+
+
+# ---------------------------------------------------------------- CPU baseline (the oracle)
 
 def _oracle_worker(args):
     import threadpoolctl
@@ -73,33 +91,54 @@ def _oracle_worker(args):
     from oracle import dmala as odm
     H, y, s2, inst = args
     t = time.perf_counter()
-    r = odm.detect(H, y, s2, M, CHAINS, ITERS, SEED, instance=inst)
-    return time.perf_counter() - t, r["symbols"]
+    odm.detect(H, y, s2, C5_M, C5_C, C5_T, SEED, instance=inst)
+    return time.perf_counter() - t
 
 
-def cpu_baseline(batch, per_snr):
-    """Time the float64 oracle (sampling + estimators) on a bounded sample, all host cores."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(batch, per_snr, one_core):
+    """The float64 oracle (sampling + estimators) on a bounded sample of the headline workload."""
     import multiprocessing as mp
     try:
-        cores = len(os.sched_getaffinity(0))
+        avail = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
-    idx = np.concatenate([np.arange(k * 1024, k * 1024 + per_snr) for k in range(len(SNRS))])
+        avail = os.cpu_count() or 1
+    workers = max(1, min(avail, CPU_WORKERS))
+    n_snr = len(C5_SNRS)
+    per = len(batch.sigma2) // n_snr
+    idx = np.concatenate([np.arange(k * per, k * per + per_snr) for k in range(n_snr)])
     work = [(batch.H[i], batch.y[i], batch.sigma2[i], int(i)) for i in idx]
     ctx = mp.get_context("spawn")
-    t0 = time.perf_counter()
-    with ctx.Pool(cores) as pool:
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_worker, work[:workers], chunksize=1)          # warm the workers (imports)
+        t0 = time.perf_counter()
         res = pool.map(_oracle_worker, work, chunksize=1)
-    wall = time.perf_counter() - t0
-    cpu = sum(r[0] for r in res)
+        wall = time.perf_counter() - t0
+    cpu = float(sum(res))
+    t1 = time.perf_counter()
+    for w in work[:one_core]:
+        _oracle_worker(w)
+    wall1 = time.perf_counter() - t1
     n = len(idx)
-    return dict(value=n * CHAINS * ITERS / wall, unit="chain-iterations/s", cores=cores, kind="oracle",
-                sample="%d of the 7168 problems (%d per SNR), %d chains x %d transitions + estimators, "
+    return dict(value=n * C5_C * C5_T / wall, unit="chain-iterations/s", cores=workers, kind="oracle",
+                sample="%d of the 8192 headline problems (%d per SNR), %d chains x %d transitions + estimators, "
                        "float64 numpy oracle, one process per core; %.1f s CPU in %.1f s wall"
-                       % (n, per_snr, CHAINS, ITERS, cpu, wall),
-                vectors_per_s=n / wall)
+                       % (n, per_snr, C5_C, C5_T, cpu, wall),
+                vectors_per_s=n / wall, nproc=os.cpu_count(), cpu_model=cpu_model(),
+                one_core=dict(value=one_core * C5_C * C5_T / wall1, unit="chain-iterations/s",
+                              sample="%d problems sequentially, %.1f s" % (one_core, wall1)))
 
+
+# ---------------------------------------------------------------- timing helpers
 
 class HipEvents:
     def __init__(self, n):
@@ -113,7 +152,8 @@ class HipEvents:
 
     def record(self, i):
         import torch
-        if self.hip.hipEventRecord(ctypes.c_void_p(self.ev[i]), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)) != 0:
+        s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        if self.hip.hipEventRecord(ctypes.c_void_p(self.ev[i]), s) != 0:
             raise RuntimeError("hipEventRecord failed")
 
     def elapsed_ms(self, a, b):
@@ -123,149 +163,189 @@ class HipEvents:
         return ms.value
 
 
-def run_form(dm, torch, b, precision, steps, warmup):
-    Hcm, y, s2 = dm.device_inputs(b.H, b.y, b.sigma2, precision)
-    B = len(b.sigma2)
-    det = dm.Detector(B, NT, NR, M, CHAINS, ITERS, SEED, precision, "precond")
+def time_detector(det, args_, steps, warmup):
+    """Mean step and stage times (HIP events on the launch stream) of a Detector over `steps` calls."""
+    import torch
     ev = HipEvents(4 * steps)
     for _ in range(warmup):
-        det(Hcm, y, s2)
+        det(*args_)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        out = det(Hcm, y, s2, events=ev.ev[4 * k: 4 * k + 4])
+        out = det(*args_, events=ev.ev[4 * k: 4 * k + 4])
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    step_ms = [ev.elapsed_ms(4 * k, 4 * k + 3) for k in range(steps)]
-    samp_ms = [ev.elapsed_ms(4 * k + 1, 4 * k + 2) for k in range(steps)]
-    setup_ms = [ev.elapsed_ms(4 * k, 4 * k + 1) for k in range(steps)]
-    est_ms = [ev.elapsed_ms(4 * k + 2, 4 * k + 3) for k in range(steps)]
-    sym = out["symbols"].cpu().numpy()
-    err = (sym != b.x_idx)
-    ser = {str(s): float(err[k * 1024:(k + 1) * 1024].mean()) for k, s in enumerate(SNRS)}
-    return dict(wall_ms=wall * 1e3 / steps, step_ms=float(np.mean(step_ms)), sampler_ms=float(np.mean(samp_ms)),
-                setup_ms=float(np.mean(setup_ms)), estimator_ms=float(np.mean(est_ms)), ser=ser)
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    st = lambda a, b: float(np.mean([ev.elapsed_ms(4 * k + a, 4 * k + b) for k in range(steps)]))  # noqa: E731
+    return out, dict(step_ms=st(0, 3), setup_ms=st(0, 1), sampler_ms=st(1, 2), estimator_ms=st(2, 3), wall_ms=wall)
 
 
-def learned_comparison(dm, torch, reps=3):
-    """64x64 64-QAM at 20..26 dB (2048 problems per SNR), 32 chains: symbol error rate and time of
-    the plain fp32 form, the BF16 form and the BF16 form with the learned proposal (mixture, eps 0.1)
-    over a sweep of transitions; the network is first trained on the GPU on the method's own
-    32x32 64-QAM and 128x128 256-QAM chains (training time reported separately)."""
+def mmse_ser(b):
+    """Symbol error rate of a linear MMSE detector on the same inputs (numpy reference, not timed)."""
+    pts = W.qam_points(b.M)
+    H = b.H
+    Hh = np.conj(np.transpose(H, (0, 2, 1)))
+    A = Hh @ H + b.sigma2[:, None, None] * np.eye(b.nt)[None]
+    x = np.linalg.solve(A, (Hh @ b.y[..., None]))[..., 0]
+    d = np.argmin(np.abs(x[..., None] - pts[None, None, :]), axis=-1)
+    return float(np.mean(d != b.x_idx))
+
+
+# ---------------------------------------------------------------- the learned proposal
+
+def train_network(dm, torch, sources, data):
+    """Train the per-antenna network on the method's own chains: sources = [(batch, C, feature_iters, seed)],
+    targets = the same chain 20 transitions later (learned.collect)."""
     from paper_2407_06042_amd import learned as L
-    ev0 = HipEvents(2)
-    hip_t0 = time.perf_counter()
-    ev0.record(0)
-    b = W.c2_snr_sweep(n_per_snr=128, seed=102).as_precision(np.float32)
-    H, y, s2 = dm.device_inputs(b.H, b.y, b.sigma2)
-    rows, tg = L.collect(H, y, s2, 32, 32, 64, 32, [0, 5, 10, 20, 40, 80], 20, 11)
-    b4 = W.c4_correlated(n_inst=48, seed=104).as_precision(np.float32)
-    H4, y4, s4 = dm.device_inputs(b4.H, b4.y, b4.sigma2)
-    r4, t4 = L.collect(H4, y4, s4, 128, 128, 256, 32, [0, 10, 40], 20, 12)
-    rows, tg = torch.cat([rows, r4]), torch.cat([tg, t4])
+    ev = HipEvents(2)
+    ev.record(0)
+    rows, tg = [], []
+    for b, C, its, sd in sources:
+        b = b.as_precision(np.float32)
+        H, y, s2 = dm.device_inputs(b.H, b.y, b.sigma2)
+        r, t = L.collect(H, y, s2, b.nt, b.nr, b.M, C, its, 20, sd)
+        rows.append(r)
+        tg.append(t)
+    rows, tg = torch.cat(rows), torch.cat(tg)
     w = L.init_weights(1)
     hist = L.train(w, rows, tg, 400, batch=65536, lr=3e-3, lr_final=2e-4, log_every=399)
-    ev0.record(1)
+    ev.record(1)
     torch.cuda.synchronize()
-    train_ms = ev0.elapsed_ms(0, 1)
-    ev = W.c5_learned_eval().as_precision(np.float32)
-    He, ye, se = dm.device_inputs(ev.H, ev.y, ev.sigma2)
-    B = len(ev.sigma2)
-    runs = []
-    sweep = [("fp32", "precond", (25, 50, 100, 200)), ("bf16", "precond", (25, 50, 100, 200)),
-             ("bf16", "learned", (10, 25, 50, 100))]
-    for prec, prop, Ts in sweep:
+    return w, dict(ms=ev.elapsed_ms(0, 1), rows=int(rows.shape[0]), steps=400, final_loss=hist[-1][1], data=data)
+
+
+def matched_ser_sweep(dm, torch, b, w, sweep, ref_T, reps):
+    """Time and SER of every (form, T); the matched setting per form under the paired 95 % CI rule."""
+    Hc, yc, sc = dm.device_inputs(b.H, b.y, b.sigma2)
+    B, nt, M = len(b.sigma2), b.nt, b.M
+    runs, errs = [], {}
+    for form, Ts in sweep:
+        prec, prop = ("bf16", "learned") if form == "bf16+learned" else (form, "precond")
         for T in Ts:
             kw = dict(mlp_weights=w, mix_eps=0.1) if prop == "learned" else {}
-            det = dm.Detector(B, 64, 64, 64, 32, T, SEED, prec, prop, outputs=("symbols", "accept_count"), **kw)
-            det(He, ye, se)
-            e = HipEvents(4 * reps)
-            for k in range(reps):
-                out = det(He, ye, se, events=e.ev[4 * k: 4 * k + 4])
-            torch.cuda.synchronize()
-            ms = float(np.mean([e.elapsed_ms(4 * k, 4 * k + 3) for k in range(reps)]))
+            det = dm.Detector(B, nt, nt, M, C5_C, T, SEED, prec, prop, outputs=("symbols", "accept_count"), **kw)
+            out, tm = time_detector(det, (Hc, yc, sc), reps, 1)
             sym = out["symbols"].cpu().numpy()
-            runs.append(dict(form=prec + ("+learned" if prop == "learned" else ""), T=T, ms=ms,
-                             ser=float(np.mean(sym != ev.x_idx)),
+            errs[(form, T)] = (sym != b.x_idx).reshape(-1).astype(np.float64)
+            runs.append(dict(form=form, T=T, ms=tm["step_ms"], sampler_ms=tm["sampler_ms"],
+                             ser=float(errs[(form, T)].mean()),
                              accept=float(out["accept_count"].float().mean().item()) / T,
-                             chain_iters_per_s=B * 32 * T / (ms * 1e-3)))
-    ref = next(r for r in runs if r["form"] == "fp32" and r["T"] == 100)
+                             chain_iters_per_s=B * C5_C * T / (tm["step_ms"] * 1e-3),
+                             vectors_per_s=B / (tm["step_ms"] * 1e-3)))
+    ref_err = errs[("fp32", ref_T)]
+    ref = next(r for r in runs if r["form"] == "fp32" and r["T"] == ref_T)
     matched = {}
-    for form in ("fp32", "bf16", "bf16+learned"):
-        ok = [r for r in runs if r["form"] == form and r["ser"] <= ref["ser"]]
+    for form, _ in sweep:
+        ok = []
+        for r in runs:
+            if r["form"] != form:
+                continue
+            d = errs[(form, r["T"])] - ref_err
+            hw = 1.96 * d.std(ddof=1) / np.sqrt(d.size)
+            r["ser_diff_vs_ref"] = float(d.mean())
+            r["ser_diff_ci95"] = float(hw)
+            if d.mean() <= hw:                      # not worse than the reference within the paired CI
+                ok.append(r)
         if ok:
             best = min(ok, key=lambda r: r["ms"])
-            matched[form] = dict(T=best["T"], ms=best["ms"], ser=best["ser"], speedup_vs_fp32_T100=ref["ms"] / best["ms"])
+            matched[form] = dict(T=best["T"], ms=best["ms"], ser=best["ser"], vectors_per_s=best["vectors_per_s"],
+                                 chain_iters_per_s=best["chain_iters_per_s"], speedup_vs_fp32_ref=ref["ms"] / best["ms"])
         else:
             matched[form] = None
-    return dict(workload="64x64 64-QAM i.i.d. Rayleigh CN(0,1/Nr), SNR 20:2:26 dB x 2048 (8192 problems), "
-                         "32 chains, swept transitions; learned = BF16 with the trained network, plain kernel "
-                         "with probability 0.1 per transition",
-                training=dict(ms=train_ms, rows=int(rows.shape[0]), steps=400, final_loss=hist[-1][1],
-                              data="32x32 64-QAM (896 problems) and 128x128 256-QAM rho=0.5 (48 problems) "
-                                   "chains, targets = the same chain 20 transitions later"),
-                runs=runs, reference="fp32 plain, 100 transitions", matched_ser=matched)
+    return runs, matched, ref
 
 
-def bench_uneven(args):
-    """4096 uneven problems: Nt in {16,32,64,128}, Nr in {Nt,2Nt}, M in {4,16,64}, SNR U(10,30) dB,
-    32 chains x 100 transitions, BF16 gradient with fp32 acceptance, one plan (graph) launch per step."""
-    import torch
-    import paper_2407_06042_amd as dm
+# ---------------------------------------------------------------- extra workloads
+
+def extra_uniform(dm, torch, b, C, T, forms, steps, warmup, snr_split=None):
+    Hc, yc, sc = dm.device_inputs(b.H, b.y, b.sigma2)
+    B = len(b.sigma2)
+    res = {}
+    for f in forms:
+        det = dm.Detector(B, b.nt, b.nr, b.M, C, T, SEED, f, "precond", outputs=("symbols",))
+        out, tm = time_detector(det, (Hc, yc, sc), steps, warmup)
+        err = out["symbols"].cpu().numpy() != b.x_idx
+        r = dict(tm, chain_iters_per_s=B * C * T / (tm["step_ms"] * 1e-3), vectors_per_s=B / (tm["step_ms"] * 1e-3),
+                 ser=float(err.mean()))
+        if snr_split:
+            n = B // len(snr_split)
+            r["ser_per_snr"] = {str(s): float(err[k * n:(k + 1) * n].mean()) for k, s in enumerate(snr_split)}
+        res[f] = r
+    return res
+
+
+def extra_uneven(dm, torch, forms, steps, warmup, autotune=None):
     d = W.c3_uneven()
     shapes = d["shapes"]
     H, y, sig = dm.pack_uneven(d["H"], d["y"], d["sigma2"])
     C, T = 32, 100
-    forms = [f for f in args.forms.split(",") if f] if args.forms != "fp32,bf16" else ["bf16", "fp32"]
     truth = np.concatenate(d["x_idx"])
     res = {}
     for f in forms:
         plan = dm.Plan(shapes, C, T, SEED, precision=f, outputs=("symbols",))
-        if args.autotune:
-            plan.autotune(H, y, sig, args.autotune)
-        ev = HipEvents(4 * args.steps)
-        for _ in range(args.warmup):
+        if autotune:
+            plan.autotune(H, y, sig, autotune)
+        ev = HipEvents(2 * steps)
+        for _ in range(warmup):
             plan(H, y, sig)
         torch.cuda.synchronize()
-        for k in range(args.steps):
-            out = plan(H, y, sig, events=[ev.ev[4 * k], None, None, ev.ev[4 * k + 3]])
+        for k in range(steps):
+            out = plan(H, y, sig, events=[ev.ev[2 * k], None, None, ev.ev[2 * k + 1]])
         torch.cuda.synchronize()
-        ms = float(np.mean([ev.elapsed_ms(4 * k, 4 * k + 3) for k in range(args.steps)]))
-        ser = float(np.mean(out["symbols"].cpu().numpy() != truth))
-        res[f] = dict(ms_per_step=ms, chain_iters_per_s=len(shapes) * C * T / (ms * 1e-3), ser=ser,
-                      classes=plan.classes())
-    r = res[forms[0]]
-    line = {"metric": METRIC, "value": r["chain_iters_per_s"], "unit": "chain-iterations/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": forms[0], "data": "synthetic",
-            "config": {"workload": "4096 uneven problems: Nt in {16,32,64,128}, Nr in {Nt,2Nt}, M in {4,16,64}, "
-                                   "SNR U(10,30) dB, 32 chains x 100 transitions, one graph launch",
-                       "instances": len(shapes)},
-            "vectors_per_s": len(shapes) / (r["ms_per_step"] * 1e-3), "ser": r["ser"],
-            "forms": {f: {k: v for k, v in res[f].items() if k != "classes"} for f in forms},
-            "classes": r["classes"]}
-    print(json.dumps(line))
+        ms = float(np.mean([ev.elapsed_ms(2 * k, 2 * k + 1) for k in range(steps)]))
+        res[f] = dict(step_ms=ms, chain_iters_per_s=len(shapes) * C * T / (ms * 1e-3),
+                      vectors_per_s=len(shapes) / (ms * 1e-3),
+                      ser=float(np.mean(out["symbols"].cpu().numpy() != truth)), classes=len(plan.classes()))
+    return res
+
+
+def gx_stage(dm, torch, loops):
+    """The G.X stage alone (dmala_gx_loop, bf16) at the 32x32, 64x64 and 128x128 shapes: fraction of the
+    dense bf16 MFMA peak, counting 8 Nt^2 flops per chain and loop."""
+    out = {}
+    for name, b, C in (("32x32 64-QAM, 7168 problems x 32 chains", W.c2_snr_sweep(n_per_snr=1024), 32),
+                       ("64x64 64-QAM, 8192 problems x 32 chains", W.c5_learned_eval(), 32),
+                       ("128x128 256-QAM, 256 problems x 64 chains", W.c4_correlated(), 64)):
+        b = b.as_precision(np.float32)
+        Hc, yc, sc = dm.device_inputs(b.H, b.y, b.sigma2)
+        B = len(b.sigma2)
+        g = dm.GxLoop(B, b.nt, b.nr, b.M, C, "bf16")
+        g(Hc, yc, sc, 1, run_setup=True)
+        n_loops = loops
+        ev = HipEvents(2)
+        g(Hc, yc, sc, n_loops)
+        torch.cuda.synchronize()
+        ev.record(0)
+        g(Hc, yc, sc, n_loops)
+        ev.record(1)
+        torch.cuda.synchronize()
+        ms = ev.elapsed_ms(0, 1)
+        flops = 8.0 * b.nt * b.nt * C * n_loops * B
+        out[name] = dict(ms=ms, loops=n_loops, tflops=flops / (ms * 1e-3) / 1e12,
+                         frac=flops / (ms * 1e-3) / PEAK_BF16_MFMA)
+        del g
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-per-snr", type=int, default=24)
-    ap.add_argument("--forms", default="fp32,bf16", help="comma list; the first is the reported value")
+    ap.add_argument("--cpu-one-core", type=int, default=12)
+    ap.add_argument("--no-extras", action="store_true", help="skip the 32x32, uneven and 128x128 workloads")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the matched-SER sweeps (headline form only)")
+    ap.add_argument("--gx-loops", type=int, default=400)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference kernel for HBM counters)")
-    ap.add_argument("--workload", default="c2", choices=("c2", "uneven"),
-                    help="c2: the default 32x32 64-QAM sweep; uneven: 4096 mixed-shape problems in one plan")
+    ap.add_argument("--only", default=None, choices=("c5", "c2", "c4", "uneven", "gx"),
+                    help="profiling: run one workload's timed steps only and print its timing")
     ap.add_argument("--autotune", default=None, help="uneven workload: autotune cache path (JSON)")
-    ap.add_argument("--no-learned", action="store_true",
-                    help="skip the 64x64 64-QAM plain / BF16 / learned-proposal comparison")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the detector has no multi-GPU path to time "
-              "(instances shard across GPUs with no communication); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: problems shard across GPUs with no communication, and this "
+              "build times one GPU's share only; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:
@@ -278,37 +358,102 @@ def main():
         print(json.dumps(dict(copy_bytes=1 << 30, reps=3)))
         return
 
-    if args.workload == "uneven":
-        return bench_uneven(args)
-
-    batch = W.c2_snr_sweep(n_per_snr=1024).as_precision(np.float32)
+    progress("inputs")
+    c5 = W.c5_learned_eval().as_precision(np.float32)
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(batch, args.cpu_per_snr)   # before any GPU work in this process
+    if not args.no_cpu_baseline and args.only is None:
+        progress("cpu baseline")
+        cpu = cpu_baseline(c5, args.cpu_per_snr, args.cpu_one_core)   # before any GPU work in this process
 
     import torch
     import paper_2407_06042_amd as dm
     dm.lib()  # raises if the HIP library is not built
-    forms = [f for f in args.forms.split(",") if f]
-    res = {}
-    for f in forms:
-        res[f] = run_form(dm, torch, batch, f, args.steps, args.warmup)
 
-    learned = None if args.no_learned else learned_comparison(dm, torch)
+    if args.only:
+        if args.only == "c5":
+            r = extra_uniform(dm, torch, c5, C5_C, C5_T, ["fp32", "bf16"], args.steps, args.warmup)
+        elif args.only == "c2":
+            r = extra_uniform(dm, torch, W.c2_snr_sweep().as_precision(np.float32), 32, 100, ["fp32", "bf16"],
+                              args.steps, args.warmup)
+        elif args.only == "c4":
+            r = extra_uniform(dm, torch, W.c4_correlated().as_precision(np.float32), 64, 200,
+                              ["fp32", "bf16", "fp16"], args.steps, args.warmup)
+        elif args.only == "uneven":
+            r = extra_uneven(dm, torch, ["bf16"], args.steps, args.warmup, args.autotune)
+        else:
+            r = gx_stage(dm, torch, args.gx_loops)
+        print(json.dumps({"only": args.only, "result": r}))
+        return
 
-    main_form = forms[0]
-    r = res[main_form]
-    B = len(batch.sigma2)
-    ci = B * CHAINS * ITERS
-    value = ci / (r["step_ms"] * 1e-3)
-    ops = algorithmic_ops_per_chain_iter(NT, NR, M) * ci
-    achieved = ops / (r["sampler_ms"] * 1e-3)
+    progress("headline")
+    # headline: plain fp32 form at 100 transitions
+    B = len(c5.sigma2)
+    Hc, yc, sc = dm.device_inputs(c5.H, c5.y, c5.sigma2)
+    det = dm.Detector(B, C5_NT, C5_NT, C5_M, C5_C, C5_T, SEED, "fp32", "precond", outputs=("symbols",))
+    out, tm = time_detector(det, (Hc, yc, sc), args.steps, args.warmup)
+    err = out["symbols"].cpu().numpy() != c5.x_idx
+    ci = B * C5_C * C5_T
+    value = ci / (tm["step_ms"] * 1e-3)
+    del det
+
+    # matched SER: the learned network, then the sweeps
+    progress("training")
+    w, training = train_network(
+        dm, torch, [(W.c2_snr_sweep(n_per_snr=128, seed=102), 32, [0, 5, 10, 20, 40, 80], 11),
+                    (W.c4_correlated(n_inst=48, seed=104), 32, [0, 10, 40], 12)],
+        "32x32 64-QAM (896 problems) and 128x128 256-QAM rho=0.5 (48 problems) chains, "
+        "targets = the same chain 20 transitions later")
+    c5_sweep = [("fp32", (25, 50, 100, 200)), ("bf16", (25, 50, 100, 200)), ("bf16+learned", (10, 25, 50, 100))]
+    matched = dict(workload="64x64 64-QAM headline batch", reference="fp32 plain, 100 transitions",
+                   rule="fastest setting with SER - SER_ref <= paired 95 % half-width", mmse_ser=mmse_ser(c5))
+    if not args.no_sweep:
+        progress("matched-SER sweep 64x64")
+        runs, m, _ = matched_ser_sweep(dm, torch, c5, w, c5_sweep, 100, 3)
+        matched.update(runs=runs, matched=m)
+        progress("matched-SER sweep 8x8")
+        b8 = W.make_batch(8, 8, 64, np.repeat([22.0, 24.0, 26.0], 4096), 3 * 4096, seed=8, cfg_id=8).as_precision(np.float32)
+        # a network trained on this size's own chains (other realisations), beside the one trained on
+        # the large systems
+        w8, training8 = train_network(
+            dm, torch, [(W.make_batch(8, 8, 64, np.repeat([22.0, 24.0, 26.0], 1024), 3 * 1024, seed=88, cfg_id=8),
+                         32, [0, 5, 10, 20, 40, 80], 13)],
+            "8x8 64-QAM at 22/24/26 dB (3072 other problems) chains, targets = the same chain 20 transitions later")
+        runs8, m8, ref8 = matched_ser_sweep(dm, torch, b8, w8, [("fp32", (25, 50, 100, 200)), ("bf16", (25, 50, 100)),
+                                                                ("bf16+learned", (10, 25, 50, 100))], 100, 3)
+        runs8x, m8x, _ = matched_ser_sweep(dm, torch, b8, w, [("fp32", (100,)), ("bf16+learned", (25, 50, 100))],
+                                           100, 3)
+        works = dict(workload="8x8 64-QAM i.i.d. Rayleigh CN(0,1/Nr), SNR 22/24/26 dB x 4096 (12288 problems), "
+                              "32 chains", reference="fp32 plain, 100 transitions", mmse_ser=mmse_ser(b8),
+                     training=training8, runs=runs8, matched=m8,
+                     large_system_network=dict(runs=[r for r in runs8x if r["form"] != "fp32"], matched=m8x))
+    else:
+        works = None
+
+    extras = None
+    if not args.no_extras:
+        progress("extra workloads")
+        extras = dict(
+            c2=dict(workload="32x32 64-QAM i.i.d. Rayleigh, SNR 16:2:28 dB x 1024 (7168 problems), 32 chains x 100",
+                    forms=extra_uniform(dm, torch, W.c2_snr_sweep().as_precision(np.float32), 32, 100,
+                                        ["fp32", "bf16"], args.steps, args.warmup, (16, 18, 20, 22, 24, 26, 28))),
+            c3_uneven=dict(workload="4096 uneven problems: Nt in {16,32,64,128}, Nr in {Nt,2Nt}, M in {4,16,64}, "
+                                    "SNR U(10,30) dB, 32 chains x 100, one plan (graph) launch",
+                           forms=extra_uneven(dm, torch, ["bf16", "fp32"], args.steps, args.warmup, args.autotune)),
+            c4=dict(workload="128x128 256-QAM Kronecker rho=0.5 both ends, 30 dB, 256 problems, 64 chains x 200",
+                    forms=extra_uniform(dm, torch, W.c4_correlated().as_precision(np.float32), 64, 200,
+                                        ["fp32", "bf16", "fp16"], max(3, args.steps // 2), args.warmup)))
+    progress("gradient stage")
+    gx = gx_stage(dm, torch, args.gx_loops)
+
+    ops = valu_ops_per_chain_iter(C5_NT, C5_M)
+    achieved = ops * ci / (tm["sampler_ms"] * 1e-3)
     traffic = None
-    tf = os.path.join(ROOT, "profiles", "sampler_32x32_64qam_fp32_traffic.json")
+    tf = os.path.join(ROOT, "profiles", "sampler_64x64_64qam_fp32_traffic.json")
     if os.path.exists(tf):
         t = json.load(open(tf))
-        if t.get("source_hash") == source_hash():
+        if t.get("source_hash") == source_hash(SAMPLER_SOURCES):
             traffic = t.get("bytes_per_launch")
+    gx5 = gx["64x64 64-QAM, 8192 problems x 32 chains"]
     line = {
         "metric": METRIC,
         "value": value,
@@ -316,29 +461,32 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r["step_ms"],
+        "ms_per_step": tm["step_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "32x32 64-QAM i.i.d. Rayleigh CN(0,1/Nr), SNR 16:2:28 dB x 1024 realisations "
-                               "(7168 problems), 32 chains x 100 transitions, preconditioned DMALA, tau=2, "
-                               "fp32-class (fp16-split MFMA)", "instances": B, "chains": CHAINS, "iters": ITERS},
-        "vectors_per_s": B / (r["step_ms"] * 1e-3),
-        "ser": r["ser"],
-        "stage_ms": {k: r[k] for k in ("setup_ms", "sampler_ms", "estimator_ms", "wall_ms")},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_VALU_OPS, "traffic": traffic,
+        "config": {"workload": "64x64 64-QAM i.i.d. Rayleigh CN(0,1/Nr), SNR 20:2:26 dB x 2048 realisations "
+                               "(8192 problems), 32 chains x 100 transitions, preconditioned DMALA, tau=2, "
+                               "fp32-class (fp16-split MFMA)", "instances": B, "chains": C5_C, "iters": C5_T},
+        "vectors_per_s": B / (tm["step_ms"] * 1e-3),
+        "ser": {str(s): float(err[k * 2048:(k + 1) * 2048].mean()) for k, s in enumerate(C5_SNRS)},
+        "stage_ms": tm,
+        "matched_ser": dict(matched, training=training),
+        "detector_works": works,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12,
+                     "unit": "T lane-ops/s", "frac": achieved / PEAK_VALU_OPS, "traffic": traffic,
                      "peak_definition": "non-packed VALU lane operations: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz",
                      "frac_of_packed_fp32_flop_peak": achieved / PEAK_FP32_VECTOR,
-                     "kernel": "sampler_kernel<float,4,8,PM_F16X2>",
-                     "gx_mfma_tflops": gx_flops_per_chain_iter(NT) * ci / (r["sampler_ms"] * 1e-3) / 1e12,
-                     "ops_per_chain_iter": algorithmic_ops_per_chain_iter(NT, NR, M)},
+                     "kernel": "sampler_kernel_w2<float, 4, 2, true, 8, PM_F16X2, false, 3, 0> (two waves per "
+                               "16 chains, matrices from L2, 3-level window)",
+                     "ops_per_chain_iter": ops,
+                     "gx_frac": gx5["frac"], "gx_tflops": gx5["tflops"],
+                     "gx_kernel": "gx_loop_kernel<8, 1, 1, true> (dmala_gx_loop, bf16)"},
+        "gx_stage": gx,
         "cpu_baseline": cpu,
-        "learned_c5": learned,
-        "forms": {f: {"chain_iters_per_s": ci / (res[f]["step_ms"] * 1e-3), "ms_per_step": res[f]["step_ms"],
-                      "sampler_ms": res[f]["sampler_ms"], "ser": res[f]["ser"]} for f in forms},
+        "extras": extras,
     }
     print(json.dumps(line))
 

@@ -11,7 +11,7 @@
  *   - outputs: the minimum-residual hard decision (text after Algorithm 1), the
  *     IS-based bit LLRs of eq. llr_is (log-sum-exp form, eq. llr_simple), and
  *     symbol marginals from the symbol-level analogue of the IS estimator
- *     (Appendix B), computed from the final sample of every chain (Section V-A).
+ *     (Appendix C), computed from the final sample of every chain (Section IV-A).
  *
  * Conventions (all buffers are caller-owned; nothing here allocates device
  * memory, synchronises the stream or keeps pointers after a call returns):
@@ -72,7 +72,7 @@ typedef enum { DMALA_FP64 = 0, DMALA_FP32 = 1, DMALA_BF16 = 2, DMALA_FP16 = 3 } 
  * per-antenna network (dmala_mlp_forward) from features of the current state.
  * Each kernel is a full MH step with its own forward and reverse proposal, so
  * pi_a stays invariant (the paper names such data-driven additions as future
- * work, Section VI; admissibility follows from eq. acc_prob).  The kernel
+ * work, Section V; admissibility follows from eq. acc_prob).  The kernel
  * choice uses the 24-bit uniform from the low bytes of words 4, 5, 6 of the
  * transition's random stream (plain iff u < mix_eps).  Not with DMALA_FP64. */
 typedef enum { DMALA_PRECOND = 0, DMALA_NAIVE = 1, DMALA_LEARNED = 2, DMALA_MHGD = 3 } dmala_proposal;
@@ -117,7 +117,7 @@ typedef struct {
   uint64_t seed;             /* Philox key */
   dmala_precision precision;
   dmala_proposal proposal;
-  double tau;                /* temperature of pi_a (eq. aux); <= 0 selects 2 (Section V-A) */
+  double tau;                /* temperature of pi_a (eq. aux); <= 0 selects 2 (Section IV-A) */
   double alpha_mult;         /* alpha = alpha_mult * sigma^2;          <= 0 selects 1 */
   double beta_mult;          /* beta  = beta_mult * dmin^2 / sigma^2;  <= 0 selects 1 */
   double gamma_mult;         /* gamma = gamma_mult * sigma^2 / (2 dmin^2); <= 0 selects 1 */
@@ -132,8 +132,10 @@ typedef struct {
                                 6: 128 dims, 4 waves / 16 chains, L2   (LEARNED only)
                                 (dims = 2 Nt rounded up to a power of two >= 32; a layout that does
                                 not match the shape returns DMALA_ERR_UNSUPPORTED) */
-  int32_t wg_chain_blocks;   /* layouts 0-2: 16-chain blocks sharing one workgroup (and one LDS copy
-                                of the matrices): 0 = automatic (up to 4), or 1, 2, 4 */
+  int32_t wg_chain_blocks;   /* 16-chain blocks of one instance per workgroup: 0 = automatic (up to 4),
+                                or 1, 2, 4; layouts 0-2 share one LDS copy of the matrices, the two-wave
+                                layouts 3 and 5 hold at most 2 blocks (their waves owning the same row
+                                tiles read the same matrix fragments together), the four-wave layouts 1 */
   const float* mlp_weights;  /* LEARNED: device float32 [DMALA_MLP_PARAMS]; otherwise ignored.
                                 LEARNED excludes layout 2; its defaults are layouts 0, 5, 6, 4 */
   double mix_eps;            /* LEARNED: probability of the PRECOND kernel per transition, in [0, 1] */

@@ -15,7 +15,7 @@ MIMO Detection Using Gradient-Based MCMC in Discrete Spaces":
   form of eq. llr_simple with F(a) = log(1+e^a) evaluated exactly); soft
   detection: Algorithm 2;
 * hard decision: the minimum-residual sample (text after Algorithm 1);
-* parameters: Section V-A (alpha = sigma^2, beta = dmin^2/sigma^2,
+* parameters: Section IV-A (alpha = sigma^2, beta = dmin^2/sigma^2,
   gamma = sigma^2/(2 dmin^2), tau = 2, final sample of each of the parallel
   samplers used for the soft output).
 
@@ -30,7 +30,7 @@ Readings where the paper is silent (each is listed in the design notes):
 * bits: per-axis binary-reflected Gray label of the level index, MSB first,
   antenna bits ordered [I bits, Q bits]; b = +1 <-> label bit 0;
 * symbol marginals (not defined in the paper) use the symbol-level analogue of
-  the IS estimator of Appendix B:
+  the IS estimator of Appendix C:
       p_m(a) propto sum_s pi_a(a | x^{[s]}_{-m}) exp(((tau-1)/tau) f(x^{[s]}_{m<-a})).
 """
 import numpy as np
@@ -99,7 +99,7 @@ class Problem:
         self.sigma2 = float(sigma2)
         self.tau = float(tau)
         self.variant = variant
-        # Section V-A defaults
+        # Section IV-A defaults
         self.alpha = float(alpha) if alpha is not None else self.sigma2
         self.beta = float(beta) if beta is not None else self.dmin ** 2 / self.sigma2
         self.gamma = float(gamma) if gamma is not None else self.sigma2 / (2.0 * self.dmin ** 2)

@@ -4,7 +4,7 @@ the training of its network, in float64 (test oracle).
 TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and bench.py's
 CPU-baseline leg may import this module; the product path never does.
 
-The paper does not define a learned proposal: its conclusion (Section VI)
+The paper does not define a learned proposal: its conclusion (Section V)
 names the combination of model-driven and data-driven methods as future work.
 What makes one admissible is the MH construction of Section III-A (eq.
 acc_prob, eq. acc_prob_general): a proposal q(. | x) that is a fixed function

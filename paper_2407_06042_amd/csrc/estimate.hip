@@ -1,7 +1,7 @@
 // Estimators on the final samples (Algorithm 2, steps after sampling).
 //
 // One workgroup per instance.  For every chain's final state x^[s] (the sample
-// list of Section V-A) the kernel recomputes the residual r = y - H x from the
+// list of Section IV-A) the kernel recomputes the residual r = y - H x from the
 // inputs, E = ||r||^2, f = -E/sigma^2 and c = H^H r.  Moving coordinate n of a
 // sample from level k_n to level k (e = k - k_n, real step d = 2 s e) changes f by
 //     delta(e) = (2 d c_n - d^2 ||h_m||^2) / sigma^2 = e (a_n - a2_m e),

@@ -328,7 +328,10 @@ dmala_status dmala_plan_autotune(dmala_plan P, const void* H, const void* y, con
         t.tile_config = tc;
         t.cbw = cb;
         if (class_plan(P, t) != DMALA_OK) continue;
-        if (tc >= 4 && cb != 4) continue;  // the split layouts ignore wg_chain_blocks
+        // the split layouts hold at most 4 / (waves per chain block) blocks per workgroup: skip settings
+        // that launch the same configuration
+        if ((tc == 5 || tc == 7) && cb != 4) continue;
+        if ((tc == 4 || tc == 6) && cb == 4) continue;
         double ms_best = INFINITY;
         for (int rep = 0; rep < 3; ++rep) {
           (void)hipEventRecord(e0, s);

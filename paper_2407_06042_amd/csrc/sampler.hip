@@ -28,10 +28,10 @@ size_t sampler_lds_bytes(const Shape& sh) {
     case 0: return sampler_cfg_lds(sh, 2, 1, false, 4);
     case 1: return sampler_cfg_lds(sh, 4, 1, false, 4);
     case 2: return sampler_cfg_lds(sh, 8, 1, false, 4);
-    case 3: return sampler_cfg_lds(sh, 4, 2, true, 2);
-    case 4: return sampler_cfg_lds(sh, 4, 4, true, 4);
-    case 5: return sampler_cfg_lds(sh, 2, 2, false, 2);
-    case 6: return sampler_cfg_lds(sh, 2, 4, true, 4);
+    case 3: return sampler_cfg_lds(sh, 4, 2, true, 2 * split_slots(sh, 2));
+    case 4: return sampler_cfg_lds(sh, 4, 4, true, 4 * split_slots(sh, 4));
+    case 5: return sampler_cfg_lds(sh, 2, 2, false, 2 * split_slots(sh, 2));
+    case 6: return sampler_cfg_lds(sh, 2, 4, true, 4 * split_slots(sh, 4));
   }
   return ~(size_t)0;
 }

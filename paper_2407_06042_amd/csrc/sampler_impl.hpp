@@ -346,8 +346,12 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   const size_t fs_base = a.desc ? (size_t)a.desc[inst].fs_off : (size_t)inst * a.C * N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int cl = lane & 15, h = lane >> 4;
-  const int wd = WD > 1 ? wave : 0;                       // dimension slice of this wave
-  const int cblock = WD > 1 ? blockIdx.y : blockIdx.y * nwaves + wave;
+  // dimension-split layouts: WD consecutive waves share one 16-chain block (a "slot"), and a
+  // workgroup holds nwaves / WD slots (chain blocks of the same instance, so that the waves
+  // owning the same row tiles read the same matrix fragments at the same time)
+  const int wd = WD > 1 ? wave % WD : 0;                  // dimension slice of this wave
+  const int slot = WD > 1 ? wave / WD : 0;
+  const int cblock = WD > 1 ? blockIdx.y * (nwaves / WD) + slot : blockIdx.y * nwaves + wave;
   const int chain = cblock * 16 + cl;
   const bool live = chain < a.C;
   const int rt0 = wd * RTW;                               // first row tile owned
@@ -390,9 +394,12 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   for (size_t o = threadIdx.x * 16; o < staged; o += blockDim.x * 16)
     *(uint4*)(smem + o) = *(const uint4*)(blk + kParamBytes + o);
   const InstParams ip = *(const InstParams*)blk;
-  unsigned char* xbuf = smem + ((staged + 15) & ~(size_t)15);      // 2 x KB x 1 KiB (WD > 1)
-  Red* rbuf = (Red*)(xbuf + (WD > 1 ? 2 * KB * 1024 : 0));          // 2 x WD x 16
-  unsigned char* mlp_lds = (unsigned char*)(rbuf + (WD > 1 ? 2 * WD * 16 : 0));   // network image (LRN)
+  const int nslots = WD > 1 ? nwaves / WD : 0;
+  unsigned char* xbuf = smem + ((staged + 15) & ~(size_t)15);      // per slot 2 x KB x 1 KiB (WD > 1)
+  Red* rbuf = (Red*)(xbuf + (size_t)nslots * 2 * KB * 1024);        // per slot 2 x WD x 16
+  unsigned char* mlp_lds = (unsigned char*)(rbuf + (size_t)nslots * 2 * WD * 16);   // network image (LRN)
+  xbuf += (size_t)slot * 2 * KB * 1024;
+  rbuf += (size_t)slot * 2 * WD * 16;
   // window coefficients: a per-mode LDS table, except where the matrices fill the LDS
   constexpr bool TAB = WIN > 0 && win_table(RTW, WD, MG);
   float* ctab_p = (float*)(mlp_lds + (LRN ? kMlpLdsBytes : 0));
@@ -1006,14 +1013,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
   sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND>(a);
 }
 
+// ... in 512-thread workgroups (two chain blocks of the four-wave layout).
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void sampler_kernel_w2_512(SamplerArgs a) {
+  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND>(a);
+}
+
 // LDS bytes of a configuration.
+// Whether the four-wave layout runs its two-waves-per-SIMD kernel (the windowed preconditioned
+// float chain), which then holds two 16-chain blocks in a 512-thread workgroup.
+inline bool split4_wide(const Shape& sh) {
+  return !sh.fp64 && !sh.lrn && !sh.mhgd && sh.pm != PM_NAIVE && sh.win > 0;
+}
+
+// 16-chain blocks per workgroup of a dimension-split layout (wd waves each): up to 4 waves, or
+// 8 for the wide four-wave case.
+inline int split_slots(const Shape& sh, int wd) {
+  const int cb = sh.cbw > 0 ? sh.cbw : 4, blocks = sh.Cpad / 16;
+  const int cap = (wd == 4 && split4_wide(sh)) ? 2 : 4 / wd;
+  int n = cb < cap ? cb : cap;
+  return n < blocks ? n : blocks;
+}
+
 inline size_t sampler_cfg_lds(const Shape& sh, int rtw, int wd, bool mg, int waves) {
   if (sh.fp64) return sh.frag_bytes + (size_t)waves * 16 * sh.Npad * sizeof(double);
   const int RT = rtw * wd, KB = RT / 2;
   const size_t mat = (size_t)(p_passes(sh.pm) + kEPasses) * RT * KB * 1024;
   size_t staged = mg ? 0 : (RT <= 4 ? sh.frag_bytes : mat);
   staged = (staged + 15) & ~(size_t)15;
-  if (wd > 1) staged += 2 * (size_t)KB * 1024 + 2 * (size_t)wd * 16 * sizeof(Red);
+  if (wd > 1) staged += (size_t)(waves / wd) * (2 * (size_t)KB * 1024 + 2 * (size_t)wd * 16 * sizeof(Red));
   if (sh.lrn) staged += kMlpLdsBytes;
   if (sh.win > 0 && win_table(rtw, wd, mg)) staged += kCtabBytes;
   return staged;
@@ -1024,7 +1052,11 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
   constexpr bool LRN = KND == 1;
   const int chain_blocks = sh.Cpad / 16;
   int waves, gy;
-  if (WD > 1) { waves = WD; gy = chain_blocks; }
+  if (WD > 1) {
+    const int slots = eval ? 1 : split_slots(sh, WD);   // evaluation kernels keep 256-thread workgroups
+    waves = WD * slots;
+    gy = (chain_blocks + slots - 1) / slots;
+  }
   else {
     const int cb = sh.cbw > 0 ? sh.cbw : 4;
     waves = chain_blocks < cb ? chain_blocks : cb;
@@ -1044,6 +1076,9 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
   if (eval) {
     if constexpr (kW2Eval) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, true, WIN, KND>;
     else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN, KND>;
+  } else if (waves > 4) {
+    if constexpr (kW2 && WD == 4 && !LRN) k = sampler_kernel_w2_512<Real, RTW, WD, MG, Q, PM, false, WIN, KND>;
+    else return hipErrorInvalidConfiguration;
   } else {
     if constexpr (kW2) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, KND>;
     else if constexpr (kW2Alone) k = sh.share ? sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, KND>

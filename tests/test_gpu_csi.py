@@ -1,4 +1,4 @@
-"""Imperfect channel knowledge (Section V-F setting, needs an MI355X): 16x16 16-QAM at 16.5 dB,
+"""Imperfect channel knowledge (Section IV-F setting, needs an MI355X): 16x16 16-QAM at 16.5 dB,
 detection with H_hat = H + E over a sweep of the estimation NMSE.
 
 The detector is unchanged (it sees H_hat); chains on H_hat still follow the oracle run on

@@ -112,7 +112,7 @@ def test_edge_shapes_fp32(nt, nr, M, C, T):
 
 @pytest.mark.parametrize("alpha_mult", [0.05, 0.2, 3.0])
 def test_step_size_multiplier_fp32(alpha_mult):
-    """Step size alpha = alpha_mult sigma^2 (Section V-A scales it with the noise): the index-unit
+    """Step size alpha = alpha_mult sigma^2 (Section IV-A scales it with the noise): the index-unit
     precision is kL = 2 log2(e) / alpha_mult, so 0.2 runs the 3-level window (kL = 14.4), 0.05 a
     kernel too peaked for the window's fp32 factorisation (kL = 57.7, all levels weighted directly)
     and 3.0 a flat kernel (kL = 0.96).  Chains follow the oracle run with the same alpha."""

@@ -244,7 +244,7 @@ def test_sampler_law_matches_exact_kernel_powers(variant):
 @pytest.mark.parametrize("tau", [1.0, 2.0, 3.0])
 @pytest.mark.parametrize("nt,M", [(2, 4), (2, 16), (1, 64)])
 def test_is_llr_is_exact_under_exact_expectation(tau, nt, M):
-    """Appendix B: replacing the sample mean by the exact expectation under pi_a gives eq. exact_llr."""
+    """Appendix C: replacing the sample mean by the exact expectation under pi_a gives eq. exact_llr."""
     p = _prob(nt, 2, M, 9.0, 30 + nt, tau=tau)
     K = exact.all_states(p.N, p.Q)
     lw = exact.log_target(p, K, tempered=True)

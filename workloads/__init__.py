@@ -10,10 +10,10 @@ n ~ CN(0, sigma^2) (sigma^2/2 per real element).  SNR = E||Hx||^2 / E||n||^2
 (footnote to the convergence experiment in Section III-B), which with
 E|h_ij|^2 = v_h and unit symbol energy gives sigma^2 = Nt * Nr * v_h / (Nr * SNR).
 
-Channels: i.i.d. Rayleigh CN(0, v_h) (Section V-A uses unit variance; the
+Channels: i.i.d. Rayleigh CN(0, v_h) (Section IV-A uses unit variance; the
 benchmark configurations use v_h = 1/Nr), or the Kronecker model
 H = R_r^{1/2} G R_t^{1/2} with exponential correlation R_ij = rho^|i-j|
-(Section V-C).
+(Section IV-D).
 """
 from dataclasses import dataclass, field
 import numpy as np
@@ -150,7 +150,7 @@ def c3_uneven(n_inst=4096, seed=3):
 
 
 def imperfect_csi(batch, nmse_db, seed=0):
-    """The same problems seen through an estimated channel H_hat = H + E (Section V-F).
+    """The same problems seen through an estimated channel H_hat = H + E (Section IV-F).
 
     E has i.i.d. CN(0, sigma_e^2) entries with sigma_e^2 = NMSE * E|h_ij|^2, so that
     E||E||_F^2 / E||H||_F^2 = NMSE.  y, sigma^2 and the transmitted symbols are
