@@ -256,12 +256,12 @@ def matched_ser_sweep(dm, torch, b, w, sweep, ref_T, reps):
 
 # ---------------------------------------------------------------- extra workloads
 
-def extra_uniform(dm, torch, b, C, T, forms, steps, warmup, snr_split=None):
+def extra_uniform(dm, torch, b, C, T, forms, steps, warmup, snr_split=None, tile=0):
     Hc, yc, sc = dm.device_inputs(b.H, b.y, b.sigma2)
     B = len(b.sigma2)
     res = {}
     for f in forms:
-        det = dm.Detector(B, b.nt, b.nr, b.M, C, T, SEED, f, "precond", outputs=("symbols",))
+        det = dm.Detector(B, b.nt, b.nr, b.M, C, T, SEED, f, "precond", outputs=("symbols",), tile_config=tile)
         out, tm = time_detector(det, (Hc, yc, sc), steps, warmup)
         err = out["symbols"].cpu().numpy() != b.x_idx
         r = dict(tm, chain_iters_per_s=B * C * T / (tm["step_ms"] * 1e-3), vectors_per_s=B / (tm["step_ms"] * 1e-3),
@@ -342,6 +342,7 @@ def main():
     ap.add_argument("--only", default=None, choices=("c5", "c2", "c4", "uneven", "gx"),
                     help="profiling: run one workload's timed steps only and print its timing")
     ap.add_argument("--autotune", default=None, help="uneven workload: autotune cache path (JSON)")
+    ap.add_argument("--tile", type=int, default=0, help="profiling (--only): sampler layout (tile_config) to use")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: problems shard across GPUs with no communication, and this "
@@ -371,13 +372,13 @@ def main():
 
     if args.only:
         if args.only == "c5":
-            r = extra_uniform(dm, torch, c5, C5_C, C5_T, ["fp32", "bf16"], args.steps, args.warmup)
+            r = extra_uniform(dm, torch, c5, C5_C, C5_T, ["fp32", "bf16"], args.steps, args.warmup, tile=args.tile)
         elif args.only == "c2":
             r = extra_uniform(dm, torch, W.c2_snr_sweep().as_precision(np.float32), 32, 100, ["fp32", "bf16"],
                               args.steps, args.warmup)
         elif args.only == "c4":
             r = extra_uniform(dm, torch, W.c4_correlated().as_precision(np.float32), 64, 200,
-                              ["fp32", "bf16", "fp16"], args.steps, args.warmup)
+                              ["fp32", "bf16", "fp16"], args.steps, args.warmup, tile=args.tile)
         elif args.only == "uneven":
             r = extra_uneven(dm, torch, ["bf16"], args.steps, args.warmup, args.autotune)
         else:

@@ -121,8 +121,8 @@ typedef struct {
   double alpha_mult;         /* alpha = alpha_mult * sigma^2;          <= 0 selects 1 */
   double beta_mult;          /* beta  = beta_mult * dmin^2 / sigma^2;  <= 0 selects 1 */
   double gamma_mult;         /* gamma = gamma_mult * sigma^2 / (2 dmin^2); <= 0 selects 1 */
-  int32_t tile_config;       /* sampler work layout: 0 = automatic (32 dims: layout 0, 64: 1, 128: 3,
-                                256: 4; LEARNED 64: 5, 128: 6); k >= 1 selects layout k - 1:
+  int32_t tile_config;       /* sampler work layout: 0 = automatic (32 dims: layout 0, 64: 1, 128: 7,
+                                256: 8 (NAIVE: 3, 4); LEARNED 64: 5, 128: 6); k >= 1 selects layout k - 1:
                                 0: 32 dims, 1 wave / 16 chains, matrices in LDS
                                 1: 64 dims, 1 wave / 16 chains, LDS
                                 2: 128 dims, 1 wave / 16 chains, LDS
@@ -130,6 +130,9 @@ typedef struct {
                                 4: 256 dims, 4 waves / 16 chains, L2
                                 5: 64 dims, 2 waves / 16 chains, LDS   (LEARNED only)
                                 6: 128 dims, 4 waves / 16 chains, L2   (LEARNED only)
+                                7: layout 3 with the matrices stored as complex planes (half the bytes;
+                                   not LEARNED, not FP64)
+                                8: layout 4 with complex-plane matrices (not LEARNED, not FP64)
                                 (dims = 2 Nt rounded up to a power of two >= 32; a layout that does
                                 not match the shape returns DMALA_ERR_UNSUPPORTED) */
   int32_t wg_chain_blocks;   /* 16-chain blocks of one instance per workgroup: 0 = automatic (up to 4),

@@ -281,7 +281,12 @@ class GxLoop:
         import torch
         self.torch = torch
         self.n_inst, self.nt, self.nr, self.M, self.C = n_inst, nt, nr, M, n_chains
-        self.params = make_params(n_chains, 1, 0, precision, "precond")
+        npad = 32
+        while npad < 2 * nt:
+            npad *= 2
+        # the loop reads real-equivalent fragments: the layout it pins (1 + layout 0, 1, 3 or 4)
+        tc = {32: 1, 64: 2, 128: 4, 256: 5}[npad]
+        self.params = make_params(n_chains, 1, 0, precision, "precond", tile_config=tc)
         self.ws_bytes = workspace_size(n_inst, nt, nr, M, self.params)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
         self.sink = torch.zeros(lib().dmala_gx_loop_sink_size(n_inst, nt, n_chains), dtype=torch.float32,

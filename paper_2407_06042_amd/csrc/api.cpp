@@ -81,13 +81,19 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
     const double kL = 2.0 * 1.4426950408889634 / (am * bm);
     sh.win = (!fp64 && !pl.naive && !lrn && !mhgd && Q >= 8 && kL * 12.0 >= 30.0 && kL <= 40.0) ? 3 : 0;
   }
-  if (fp64) {
-    sh.frag_bytes = round_up((2 * (size_t)sh.Npad * sh.Npad + 2 * (size_t)sh.Npad) * 8, 16);
-  } else {
-    // fragments, then the vectors pb, ez and the per-antenna network features
-    sh.frag_bytes = (size_t)(p_passes(sh.pm) + kEPasses) * sh.RT * sh.KB * 1024 + 3 * (size_t)sh.Npad * 4;
-  }
-  if (p->tile_config < 0 || p->tile_config > 7) return fail(DMALA_ERR_ARG, "tile_config must be in [0, 7]");
+  auto set_frag_bytes = [&]() {
+    if (fp64) {
+      sh.frag_bytes = round_up((2 * (size_t)sh.Npad * sh.Npad + 2 * (size_t)sh.Npad) * 8, 16);
+    } else {
+      // fragments (real-equivalent RT x KB, or complex planes 2 x RT/2 x RT/4 KiB per split term), then
+      // the vectors pb, ez and the per-antenna network features
+      const size_t pass = sh.cx ? (size_t)sh.RT * sh.RT / 4 * 1024 : (size_t)sh.RT * sh.KB * 1024;
+      sh.frag_bytes = (size_t)(p_passes(sh.pm) + kEPasses) * pass + 3 * (size_t)sh.Npad * 4;
+    }
+  };
+  sh.cx = 0;
+  set_frag_bytes();
+  if (p->tile_config < 0 || p->tile_config > 9) return fail(DMALA_ERR_ARG, "tile_config must be in [0, 9]");
   if (p->wg_chain_blocks != 0 && p->wg_chain_blocks != 1 && p->wg_chain_blocks != 2 && p->wg_chain_blocks != 4)
     return fail(DMALA_ERR_ARG, "wg_chain_blocks must be 0, 1, 2 or 4");
   sh.cbw = p->wg_chain_blocks ? p->wg_chain_blocks : 4;
@@ -98,6 +104,8 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
       return fail(DMALA_ERR_UNSUPPORTED, "tile_config %d does not fit this shape", p->tile_config);
     sh.cfg = p->tile_config - 1;
   }
+  sh.cx = (sh.cfg == 7 || sh.cfg == 8) ? 1 : 0;
+  set_frag_bytes();
   if (sampler_lds_bytes(sh) > 160 * 1024)
     return fail(DMALA_ERR_UNSUPPORTED, "shape needs %zu bytes of LDS (> 160 KiB)", sampler_lds_bytes(sh));
   sh.inst_bytes = round_up(kParamBytes + sh.frag_bytes, 256);
@@ -146,7 +154,7 @@ dmala_status enqueue(const void* H, const void* y, const void* sigma2, int32_t n
   sa.ws_inst = base + pl.inst_off; sa.inst_stride = sh.inst_bytes;
   sa.wscratch = base + pl.wscratch_off; sa.wscratch_stride = sh.wscratch_bytes;
   sa.n_inst = n_inst; sa.nt = sh.nt; sa.nr = sh.nr; sa.Q = sh.Q; sa.N = sh.N; sa.Npad = sh.Npad;
-  sa.RT = sh.RT; sa.KB = sh.KB; sa.fp64 = sh.fp64; sa.pm = sh.pm; sa.naive = pl.naive ? 1 : 0;
+  sa.RT = sh.RT; sa.KB = sh.KB; sa.fp64 = sh.fp64; sa.pm = sh.pm; sa.naive = pl.naive ? 1 : 0; sa.cx = sh.cx;
   sa.tau = pl.tau; sa.alpha_mult = pl.am; sa.beta_mult = pl.bm; sa.gamma_mult = pl.gm;
   auto mark = [&](int i) {
     if (!eval_out && out && out->stage_events[i]) (void)hipEventRecord((hipEvent_t)out->stage_events[i], stream);

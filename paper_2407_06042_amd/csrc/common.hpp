@@ -68,6 +68,7 @@ struct Shape {
   int lrn;         // 1: plain/learned kernel mixture (learned proposal network in the sampler)
   int share;       // 1: launched beside other classes' kernels (an uneven batch's graph branches)
   int mhgd;        // 1: the MHGD baseline kernel (nearest-point candidate, MH without the proposal ratio)
+  int cx;          // 1: matrices packed as complex planes (layouts 7, 8)
   size_t inst_bytes;   // per-instance setup block
   size_t frag_bytes;   // MFMA fragments (MFMA path)
   size_t state_bytes;  // per-instance sampler->estimator block
@@ -126,6 +127,7 @@ struct SetupArgs {
   unsigned char* ws_inst; size_t inst_stride;
   unsigned char* wscratch; size_t wscratch_stride;  // per-instance working matrix when nt > 32
   int n_inst, nt, nr, Q, N, Npad, RT, KB, fp64, pm, naive;
+  int cx;              // 1: pack the matrices as complex planes (the sampler's complex-plane layouts)
   double tau, alpha_mult, beta_mult, gamma_mult;
 };
 

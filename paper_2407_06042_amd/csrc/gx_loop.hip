@@ -168,6 +168,15 @@ size_t dmala_gx_loop_sink_size(int32_t n_inst, int32_t nt, int32_t n_chains) {
 dmala_status dmala_gx_loop(const void* H, const void* y, const void* sigma2, int32_t n_inst, int32_t nt, int32_t nr,
                            int32_t qam_order, const dmala_params* params, int32_t n_loops, int32_t run_setup,
                            float* sink, void* workspace, size_t workspace_bytes, dmala_stream_t stream) {
+  if (!params) return fail(DMALA_ERR_ARG, "params is NULL");
+  // the loop reads real-equivalent fragments: pin the matching layout (1 + layout 0, 1, 3 or 4)
+  dmala_params prm = *params;
+  {
+    int npad = 32;
+    while (npad < 2 * nt) npad *= 2;
+    prm.tile_config = npad == 32 ? 1 : (npad == 64 ? 2 : (npad == 128 ? 4 : 5));
+  }
+  params = &prm;
   Plan pl;
   dmala_status st = make_plan(n_inst, nt, nr, qam_order, params, pl);
   if (st != DMALA_OK) return st;

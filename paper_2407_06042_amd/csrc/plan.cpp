@@ -322,7 +322,7 @@ dmala_status dmala_plan_autotune(dmala_plan P, const void* H, const void* y, con
     }
     double best = INFINITY;
     ClassInfo best_c = c;
-    for (int tc = 1; tc <= 7; ++tc) {
+    for (int tc = 1; tc <= 9; ++tc) {
       for (int cb : {1, 2, 4}) {
         ClassInfo t = c;
         t.tile_config = tc;
@@ -330,8 +330,8 @@ dmala_status dmala_plan_autotune(dmala_plan P, const void* H, const void* y, con
         if (class_plan(P, t) != DMALA_OK) continue;
         // the split layouts hold at most 4 / (waves per chain block) blocks per workgroup: skip settings
         // that launch the same configuration
-        if ((tc == 5 || tc == 7) && cb != 4) continue;
-        if ((tc == 4 || tc == 6) && cb == 4) continue;
+        if ((tc == 5 || tc == 7 || tc == 9) && cb != 4) continue;
+        if ((tc == 4 || tc == 6 || tc == 8) && cb == 4) continue;
         double ms_best = INFINITY;
         for (int rep = 0; rep < 3; ++rep) {
           (void)hipEventRecord(e0, s);

@@ -316,7 +316,7 @@ struct Red {
 // chain block splitting the dimensions (RT = RTW * WD tiles in all), MG = the
 // packed matrices are read from the instance block in global memory (L2) instead
 // of being staged in LDS.
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND>
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false>
 __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   constexpr bool F64 = std::is_same<Real, double>::value;
   constexpr bool LRN = KND == 1;   // plain/learned kernel mixture
@@ -324,6 +324,8 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   static_assert(!F64 || (WD == 1 && !MG), "the float64 path uses one wave per chain block and LDS matrices");
   static_assert(!LRN || (!F64 && PM != PM_NAIVE && WIN == 0 && RTW <= 4), "learned variant: float, preconditioned, no window");
   static_assert(!MHG || (PM != PM_NAIVE && WIN == 0), "MHGD: the preconditioned gradient step, no proposal window");
+  static_assert(!CX || (!F64 && !LRN && MG && RTW * WD >= 8 && RTW % 4 == 0),
+                "complex-plane matrices: float, matrices from L2, whole 32-antenna K blocks per wave");
   static_assert(WD == 1 || RTW % 2 == 0, "dimension-split waves own whole K blocks");
   constexpr int RT = RTW * WD;
   constexpr int D = 4 * RTW;
@@ -387,7 +389,10 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   }
 
   // stage the instance's packed matrices and vectors in LDS
-  const size_t mat_bytes = F64 ? 0 : (size_t)(NPP + kEPasses) * RT * KB * 1024;
+  // bytes of one split term (pass) of a packed matrix: RT x KB real-equivalent fragments, or (complex
+  // planes) 2 planes x RT/2 antenna tiles x RT/4 K blocks of 32 antennas
+  constexpr size_t PASS = CX ? (size_t)RT * RT / 4 * 1024 : (size_t)RT * KB * 1024;
+  const size_t mat_bytes = F64 ? 0 : (size_t)(NPP + kEPasses) * PASS;
   size_t staged = 0;
   if constexpr (F64) staged = a.frag_bytes;
   else if constexpr (!MG) staged = (RT <= 4) ? (size_t)a.frag_bytes : mat_bytes;
@@ -438,7 +443,15 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   // per-antenna network features (dimension 2m: LS variance, 2m+1: conditional variance)
   const float* afv = (const float*)ezv + Npad;
 
-  auto dim_of = [&](int d) { return 16 * (rt0 + (d >> 2)) + 4 * h + (d & 3); };
+  // The lane's dimensions come in GR = RTW groups of 4 consecutive real dimensions: group g is
+  // dimensions 16 (rt0 + g) + 4 h + 0..3 (real-equivalent rows of row tile rt0 + g), or, with
+  // complex planes, 32 (rt0/2 + g/2) + 8 h + 4 (g%2) + 0..3 (Re and Im of the lane's 4 antennas
+  // 16 at + 4 h + 0..3 of antenna tile at = rt0/2 + g/2).  Group g draws from random block gdim(g)/4.
+  auto gdim = [&](int g) {
+    if constexpr (CX) return 32 * ((rt0 >> 1) + (g >> 1)) + 8 * h + 4 * (g & 1);
+    else return 16 * (rt0 + g) + 4 * h;
+  };
+  auto dim_of = [&](int d) { return gdim(d >> 2) + (d & 3); };
   int xphase = 0, rphase = 0;
 
   // Sum of per-lane partials over the chain's 4 lanes and (WD > 1) its WD waves;
@@ -488,6 +501,143 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
       }
 #pragma unroll
       for (int rt = 0; rt < RTW; ++rt) hook(rt);
+    } else if constexpr (CX) {
+      // Complex planes: the matrix X (Nt x Nt) is stored as its real and imaginary planes, and
+      //   V_re = Re(X) x_re - Im(X) x_im,   V_im = Im(X) x_re + Re(X) x_im
+      // (the real-equivalent product of eq. sys_model, row 2m = V_re of antenna m, 2m+1 = V_im):
+      // four products per (antenna tile, K block of 32 antennas), each plane fragment used twice.
+      // K block kb, element j of lane l: antenna 16 (2 kb + j/4) + 4 (l/16) + j%4, which is the
+      // lane's own antenna (Re in group dimension 2 i, Im in 2 i + 1) of antenna tile 2 kb + j/4.
+      constexpr int KBX = RT / 4, KBWX = RTW / 4, ATW = RTW / 2, AT = RT / 2;
+      half8 xr[KBX], xi[KBX], xn[KBX];
+      bf16x8 br[KBX], bi[KBX], bn[KBX];
+      // the wave's own K blocks (its antenna tiles), built from its registers
+      half8 ownr[KBWX], owni[KBWX];
+#pragma unroll
+      for (int kbl = 0; kbl < KBWX; ++kbl) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int d = ((2 * kbl + (j >> 2)) * 4 + (j & 3)) * 2;
+          ownr[kbl][j] = (_Float16)(int16_t)(2 * k[d] - QM1);        // exact: |lv| <= 15
+          owni[kbl][j] = (_Float16)(int16_t)(2 * k[d + 1] - QM1);
+        }
+      }
+      if constexpr (WD > 1) {
+        // every wave's K blocks of both planes through LDS (no register array indexed by the
+        // wave's slice number)
+        unsigned char* xb = xbuf + (xphase & 1) * 2 * KBX * 1024;
+        ++xphase;
+#pragma unroll
+        for (int kbl = 0; kbl < KBWX; ++kbl) {
+          const int kb = wd * KBWX + kbl;
+          *(half8*)(xb + (size_t)kb * 1024 + lane * 16) = ownr[kbl];
+          *(half8*)(xb + (size_t)(KBX + kb) * 1024 + lane * 16) = owni[kbl];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < KBX; ++kb) {
+          xr[kb] = *(const half8*)(xb + (size_t)kb * 1024 + lane * 16);
+          xi[kb] = *(const half8*)(xb + (size_t)(KBX + kb) * 1024 + lane * 16);
+        }
+      } else {
+#pragma unroll
+        for (int kb = 0; kb < KBX; ++kb) {
+          xr[kb] = ownr[kb];
+          xi[kb] = owni[kb];
+        }
+      }
+#pragma unroll
+      for (int kb = 0; kb < KBX; ++kb) {
+        uint32_t u[4];
+        __builtin_memcpy(u, &xi[kb], 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) u[q] ^= 0x80008000u;                          // -x_im
+        __builtin_memcpy(&xn[kb], u, 16);
+        if constexpr (PM == PM_BF16X1) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            br[kb][j] = (__bf16)(float)xr[kb][j];
+            bi[kb][j] = (__bf16)(float)xi[kb][j];
+            bn[kb][j] = (__bf16)(float)xn[kb][j];
+          }
+        }
+      }
+      const uint32_t fo = opaque_zero() + (uint32_t)lane * 16;
+      auto frag = [&](int p, int pl, int atg, int kb) -> const unsigned char* {
+        const uint32_t off = fo + (uint32_t)(((p * 2 + pl) * AT + atg) * KBX + kb) * 1024u;
+        return blk + kParamBytes + off;
+      };
+#pragma unroll
+      for (int at = 0; at < ATW; ++at) {
+        const int atg = (rt0 >> 1) + at;
+        // the energy matrix's fragments of the antenna tile, all loads issued before the products
+        uint4 fe[kEPasses][2][KBX];
+#pragma unroll
+        for (int p = 0; p < kEPasses; ++p)
+#pragma unroll
+          for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+            for (int kb = 0; kb < KBX; ++kb) fe[p][pl][kb] = *(const uint4*)frag(NPP + p, pl, atg, kb);
+        f32x4 er = {0.f, 0.f, 0.f, 0.f}, ei = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int p = 0; p < kEPasses; ++p)
+#pragma unroll
+          for (int kb = 0; kb < KBX; ++kb) {
+            half8 re, im;
+            __builtin_memcpy(&re, &fe[p][0][kb], 16);
+            __builtin_memcpy(&im, &fe[p][1][kb], 16);
+            er = __builtin_amdgcn_mfma_f32_16x16x32_f16(re, xr[kb], er, 0, 0, 0);
+            er = __builtin_amdgcn_mfma_f32_16x16x32_f16(im, xn[kb], er, 0, 0, 0);
+            ei = __builtin_amdgcn_mfma_f32_16x16x32_f16(im, xr[kb], ei, 0, 0, 0);
+            ei = __builtin_amdgcn_mfma_f32_16x16x32_f16(re, xi[kb], ei, 0, 0, 0);
+          }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          accE[(at * 4 + i) * 2] = er[i];
+          accE[(at * 4 + i) * 2 + 1] = ei[i];
+        }
+        if constexpr (PM != PM_NAIVE) {
+          // then the proposal matrix's (its loads issue behind the energy products)
+          uint4 fp[NPP > 0 ? NPP : 1][2][KBX];
+#pragma unroll
+          for (int p = 0; p < NPP; ++p)
+#pragma unroll
+            for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+              for (int kb = 0; kb < KBX; ++kb) fp[p][pl][kb] = *(const uint4*)frag(p, pl, atg, kb);
+          f32x4 pr = {0.f, 0.f, 0.f, 0.f}, pi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int p = 0; p < NPP; ++p)
+#pragma unroll
+            for (int kb = 0; kb < KBX; ++kb) {
+              if constexpr (PM == PM_BF16X1) {
+                bf16x8 re, im;
+                __builtin_memcpy(&re, &fp[p][0][kb], 16);
+                __builtin_memcpy(&im, &fp[p][1][kb], 16);
+                pr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(re, br[kb], pr, 0, 0, 0);
+                pr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(im, bn[kb], pr, 0, 0, 0);
+                pi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(im, br[kb], pi, 0, 0, 0);
+                pi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(re, bi[kb], pi, 0, 0, 0);
+              } else {
+                half8 re, im;
+                __builtin_memcpy(&re, &fp[p][0][kb], 16);
+                __builtin_memcpy(&im, &fp[p][1][kb], 16);
+                pr = __builtin_amdgcn_mfma_f32_16x16x32_f16(re, xr[kb], pr, 0, 0, 0);
+                pr = __builtin_amdgcn_mfma_f32_16x16x32_f16(im, xn[kb], pr, 0, 0, 0);
+                pi = __builtin_amdgcn_mfma_f32_16x16x32_f16(im, xr[kb], pi, 0, 0, 0);
+                pi = __builtin_amdgcn_mfma_f32_16x16x32_f16(re, xi[kb], pi, 0, 0, 0);
+              }
+            }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            accP[(at * 4 + i) * 2] = pr[i];
+            accP[(at * 4 + i) * 2 + 1] = pi[i];
+          }
+        }
+        hook(2 * at);
+        hook(2 * at + 1);
+        __builtin_amdgcn_sched_barrier(0);   // one antenna tile's fragments in registers at a time
+      }
     } else {
       // B operand: this wave's K blocks from its own registers.  The packed
       // matrices are zero in the padding columns, so a padding dimension's
@@ -775,7 +925,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
     // initial state from the t = 0 words
 #pragma unroll
     for (int rt = 0; rt < RTW; ++rt) {
-      uint32_t c[4] = {(uint32_t)(4 * (rt0 + rt) + h), 0u, (uint32_t)chain, rctr};
+      uint32_t c[4] = {(uint32_t)(gdim(rt) >> 2), 0u, (uint32_t)chain, rctr};
       philox4x32_10<PIPE>(c, key0, key1);
 #pragma unroll
       for (int i = 0; i < 4; ++i) kc[rt * 4 + i] = (int)(((uint64_t)(c[i] >> 8) * Q) >> 24);
@@ -818,7 +968,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
     // the registers they would hold meanwhile are not free).
     uint32_t w[RTW][4];
     auto word_block = [&](int rt, int tt) {
-      w[rt][0] = (uint32_t)(4 * (rt0 + rt) + h); w[rt][1] = (uint32_t)tt; w[rt][2] = (uint32_t)chain; w[rt][3] = rctr;
+      w[rt][0] = (uint32_t)(gdim(rt) >> 2); w[rt][1] = (uint32_t)tt; w[rt][2] = (uint32_t)chain; w[rt][3] = rctr;
       philox4x32_10<PIPE>(w[rt], key0, key1);
     };
     if constexpr (PIPE) {
@@ -982,7 +1132,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
       unsigned char* st = a.ws_state + (size_t)inst * a.state_stride;
 #pragma unroll
       for (int rt = 0; rt < RTW; ++rt) {
-        const int n0 = 16 * (rt0 + rt) + 4 * h;
+        const int n0 = gdim(rt);
         const uint32_t cur = (uint32_t)kc[rt * 4] | ((uint32_t)kc[rt * 4 + 1] << 8) | ((uint32_t)kc[rt * 4 + 2] << 16) | ((uint32_t)kc[rt * 4 + 3] << 24);
         *(uint32_t*)(st + so.k + (size_t)chain * Npad + n0) = cur;
         *(uint32_t*)(st + so.kbest + (size_t)chain * Npad + n0) = kbest[rt];
@@ -1001,22 +1151,22 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   }
 }
 
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND>
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false>
 __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
-  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND>(a);
+  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX>(a);
 }
 
 // The same kernel held to two waves per SIMD (at most 256 registers): the
 // learned variant with two row tiles per wave fits without spilling.
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND>
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sampler_kernel_w2(SamplerArgs a) {
-  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND>(a);
+  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX>(a);
 }
 
 // ... in 512-thread workgroups (two chain blocks of the four-wave layout).
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND>
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void sampler_kernel_w2_512(SamplerArgs a) {
-  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND>(a);
+  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX>(a);
 }
 
 // LDS bytes of a configuration.
@@ -1047,7 +1197,7 @@ inline size_t sampler_cfg_lds(const Shape& sh, int rtw, int wd, bool mg, int wav
   return staged;
 }
 
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, int WIN, int KND = 0>
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, int WIN, int KND = 0, bool CX = false>
 hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
   constexpr bool LRN = KND == 1;
   const int chain_blocks = sh.Cpad / 16;
@@ -1074,16 +1224,16 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
   constexpr bool kW2Alone = !LRN && RTW == 4 && !std::is_same<Real, double>::value && WD == 4 && WIN == 0 && PM != PM_NAIVE;
   void (*k)(SamplerArgs);
   if (eval) {
-    if constexpr (kW2Eval) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, true, WIN, KND>;
-    else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN, KND>;
+    if constexpr (kW2Eval) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, true, WIN, KND, CX>;
+    else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN, KND, CX>;
   } else if (waves > 4) {
-    if constexpr (kW2 && WD == 4 && !LRN) k = sampler_kernel_w2_512<Real, RTW, WD, MG, Q, PM, false, WIN, KND>;
+    if constexpr (kW2 && WD == 4 && !LRN) k = sampler_kernel_w2_512<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>;
     else return hipErrorInvalidConfiguration;
   } else {
-    if constexpr (kW2) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, KND>;
-    else if constexpr (kW2Alone) k = sh.share ? sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, KND>
-                                              : sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, KND>;
-    else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, KND>;
+    if constexpr (kW2) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>;
+    else if constexpr (kW2Alone) k = sh.share ? sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>
+                                              : sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>;
+    else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>;
   }
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1093,16 +1243,18 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
   return hipGetLastError();
 }
 
-template <typename Real, int RTW, int WD, bool MG, int PM>
+template <typename Real, int RTW, int WD, bool MG, int PM, bool CX = false>
 hipError_t launch_q(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
   // the 3-level window is used only for Q >= 8 (it would not be smaller otherwise)
   constexpr int WN = std::is_same<Real, double>::value ? 0 : 3;   // the float path only
   const bool win = WN > 0 && sh.win == 3;
   switch (sh.Q) {
-    case 2: return launch_t<Real, RTW, WD, MG, 2, PM, 0>(sh, a, eval, s);
-    case 4: return launch_t<Real, RTW, WD, MG, 4, PM, 0>(sh, a, eval, s);
-    case 8: return win ? launch_t<Real, RTW, WD, MG, 8, PM, WN>(sh, a, eval, s) : launch_t<Real, RTW, WD, MG, 8, PM, 0>(sh, a, eval, s);
-    case 16: return win ? launch_t<Real, RTW, WD, MG, 16, PM, WN>(sh, a, eval, s) : launch_t<Real, RTW, WD, MG, 16, PM, 0>(sh, a, eval, s);
+    case 2: return launch_t<Real, RTW, WD, MG, 2, PM, 0, 0, CX>(sh, a, eval, s);
+    case 4: return launch_t<Real, RTW, WD, MG, 4, PM, 0, 0, CX>(sh, a, eval, s);
+    case 8: return win ? launch_t<Real, RTW, WD, MG, 8, PM, WN, 0, CX>(sh, a, eval, s)
+                       : launch_t<Real, RTW, WD, MG, 8, PM, 0, 0, CX>(sh, a, eval, s);
+    case 16: return win ? launch_t<Real, RTW, WD, MG, 16, PM, WN, 0, CX>(sh, a, eval, s)
+                        : launch_t<Real, RTW, WD, MG, 16, PM, 0, 0, CX>(sh, a, eval, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1110,6 +1262,7 @@ hipError_t launch_q(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
 // Configurations (row tiles per wave, waves per chain block, matrices in L2):
 //   cfg 0: RT 2, 1 wave, LDS     cfg 1: RT 4, 1 wave, LDS     cfg 2: RT 8, 1 wave, LDS
 //   cfg 3: RT 8 as 2 waves x 4, L2     cfg 4: RT 16 as 4 waves x 4, L2
+//   cfg 7, 8: cfg 3, 4 with the matrices stored as complex planes
 template <typename Real, int PM>
 hipError_t launch_rt(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
   if constexpr (std::is_same<Real, double>::value) {
@@ -1125,19 +1278,21 @@ hipError_t launch_rt(const Shape& sh, const SamplerArgs& a, bool eval, hipStream
       case 2: return launch_q<Real, 8, 1, false, PM>(sh, a, eval, s);
       case 3: return launch_q<Real, 4, 2, true, PM>(sh, a, eval, s);
       case 4: return launch_q<Real, 4, 4, true, PM>(sh, a, eval, s);
+      case 7: return launch_q<Real, 4, 2, true, PM, true>(sh, a, eval, s);
+      case 8: return launch_q<Real, 4, 4, true, PM, true>(sh, a, eval, s);
     }
     return hipErrorInvalidValue;
   }
 }
 
 // The MHGD baseline on the plain layouts (every Q weighted directly: there is no window).
-template <typename Real, int RTW, int WD, bool MG, int PM>
+template <typename Real, int RTW, int WD, bool MG, int PM, bool CX = false>
 hipError_t launch_q_mhg(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
   switch (sh.Q) {
-    case 2: return launch_t<Real, RTW, WD, MG, 2, PM, 0, 2>(sh, a, eval, s);
-    case 4: return launch_t<Real, RTW, WD, MG, 4, PM, 0, 2>(sh, a, eval, s);
-    case 8: return launch_t<Real, RTW, WD, MG, 8, PM, 0, 2>(sh, a, eval, s);
-    case 16: return launch_t<Real, RTW, WD, MG, 16, PM, 0, 2>(sh, a, eval, s);
+    case 2: return launch_t<Real, RTW, WD, MG, 2, PM, 0, 2, CX>(sh, a, eval, s);
+    case 4: return launch_t<Real, RTW, WD, MG, 4, PM, 0, 2, CX>(sh, a, eval, s);
+    case 8: return launch_t<Real, RTW, WD, MG, 8, PM, 0, 2, CX>(sh, a, eval, s);
+    case 16: return launch_t<Real, RTW, WD, MG, 16, PM, 0, 2, CX>(sh, a, eval, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1156,6 +1311,8 @@ hipError_t launch_rt_mhg(const Shape& sh, const SamplerArgs& a, bool eval, hipSt
       case 2: return launch_q_mhg<Real, 8, 1, false, PM>(sh, a, eval, s);
       case 3: return launch_q_mhg<Real, 4, 2, true, PM>(sh, a, eval, s);
       case 4: return launch_q_mhg<Real, 4, 4, true, PM>(sh, a, eval, s);
+      case 7: return launch_q_mhg<Real, 4, 2, true, PM, true>(sh, a, eval, s);
+      case 8: return launch_q_mhg<Real, 4, 4, true, PM, true>(sh, a, eval, s);
     }
   }
   return hipErrorInvalidValue;

@@ -88,8 +88,12 @@ __device__ __forceinline__ float via_float(double v) {
 // (16 rt + l%16, 16 (2 kb + j/4) + 4 (l/16) + j%4): the K order matches the
 // dimensions each lane owns in the accumulator layout, so the sampler builds
 // the B operand from its own registers.
+// With cx != 0 the complex planes are packed instead (the sampler's complex-plane layouts): pass p,
+// plane pl (real, imaginary), antenna tile at (16 rows), K block kb of 32 antennas; lane l element j
+// holds plane(X)[16 at + l%16][16 (2 kb + j/4) + 4 (l/16) + j%4] -- the same K permutation over
+// antennas that the real-equivalent packing applies to real dimensions.
 __device__ float pack_fragments(const cd* X, int ld, double c, int nt, int N, int RT, int KB, int npass, int bf16,
-                                unsigned char* dst, double* red) {
+                                unsigned char* dst, double* red, int cx) {
   double mx = 0.0;
   for (int e = threadIdx.x; e < nt * nt; e += blockDim.x) {
     const cd v = X[(e / nt) * ld + e % nt];
@@ -100,19 +104,28 @@ __device__ float pack_fragments(const cd* X, int ld, double c, int nt, int N, in
   if (mx > 0.0) frexp(mx, &ex);
   const int e2 = 14 - ex;  // scaled max in [2^13, 2^14)
   const double sc = ldexp(c, e2);
-  const size_t pass_stride = (size_t)RT * KB * 1024;
-  const int items = RT * KB * 64;
+  const int AT = RT / 2, KBX = RT / 4;
+  const size_t pass_stride = cx ? (size_t)2 * AT * KBX * 1024 : (size_t)RT * KB * 1024;
+  const int items = (int)(pass_stride / 16);
   for (int it = threadIdx.x; it < items; it += blockDim.x) {
     const int l = it & 63;
     const int t = it >> 6;
-    const int kb = t % KB;
-    const int rt = t / KB;
+    // real-equivalent: (row tile, K block); complex planes: (plane, antenna tile, K block)
+    const int kb = cx ? t % KBX : t % KB;
+    const int rt = cx ? (t / KBX) % AT : t / KB;
+    const int pl = cx ? t / (KBX * AT) : 0;
     const int n = 16 * rt + (l & 15);
     union { _Float16 h[8]; __bf16 b[8]; uint4 u; } f0, f1, f2;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int n2 = 16 * (2 * kb + (j >> 2)) + 4 * (l >> 4) + (j & 3);
-      const double v = (n < N && n2 < N) ? sc * realeq(X, ld, n, n2) : 0.0;
+      double v;
+      if (cx) {
+        const cd e = X[(n < nt && n2 < nt ? n : 0) * ld + (n2 < nt ? n2 : 0)];
+        v = (n < nt && n2 < nt) ? sc * (pl ? e.im : e.re) : 0.0;
+      } else {
+        v = (n < N && n2 < N) ? sc * realeq(X, ld, n, n2) : 0.0;
+      }
       if (bf16) {
         f0.b[j] = (__bf16)via_float(v);
       } else {
@@ -125,7 +138,7 @@ __device__ float pack_fragments(const cd* X, int ld, double c, int nt, int N, in
         else f0.h[j] = hi;
       }
     }
-    unsigned char* o = dst + (size_t)(rt * KB + kb) * 1024 + l * 16;
+    unsigned char* o = dst + (size_t)t * 1024 + l * 16;
     *(uint4*)o = f0.u;
     if (npass > 1) *(uint4*)(o + pass_stride) = f1.u;
     if (npass > 2) *(uint4*)(o + 2 * pass_stride) = f2.u;
@@ -143,8 +156,10 @@ __device__ void pack_dense(const cd* X, int ld, double c, int N, int Npad, doubl
 
 // 256-thread workgroups (instances up to 32 antennas) run five per CU: at most 96 registers, and
 // about 31 KiB of LDS with H staged 16 receive antennas at a time.
-template <typename TIn, bool WGLOB, int BS>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 5 : 1))) void setup_kernel(SetupArgs a) {
+// RMAX: rows of the working matrix the Gauss-Jordan register layout covers (threads per row BS / RMAX).
+template <typename TIn, bool WGLOB, int BS, int RMAX>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? (WGLOB ? 4 : 5) : 1)))
+void setup_kernel(SetupArgs a) {
   const int b = blockIdx.x, tid = threadIdx.x, nt = a.nt, nr = a.nr, N = a.N, Npad = a.Npad;
   const int ld = nt + 1;  // padded leading dimension of the LDS matrices (no bank conflicts on columns)
   const InstDesc dsc = inst_desc(a.desc, b, nt, nr, a.Q * a.Q, 1);
@@ -187,7 +202,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 
     // blocks on or above the diagonal and the blocks of the z column are
     // computed, and the lower triangle is written as the conjugate.
     constexpr int kIC = BS == 256 ? 16 : 32;
-    constexpr int kBPT = WGLOB ? (BS >= 1024 ? 3 : 2) : 1;  // blocks per thread per group (one group for every nt)
+    constexpr int kBPT = WGLOB ? (BS >= 1024 || BS == 256 ? 3 : 2) : 1;  // blocks per thread per group (one group for every nt)
     cd* Ht = (cd*)(red + BS);               // kIC x ld, then one spare row read past the last column
     const int nb = (nt + 1) >> 1;           // 2-row blocks
     const int nbu = nb * (nb + 1) / 2;      // blocks on or above the diagonal
@@ -285,6 +300,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 
   const double cb = alpha / (2.0 * tau * sigma2 * s);
   const int npP = p_passes(a.pm);
   unsigned char* frag = blk + kParamBytes;
+  // bytes of one split term of a packed matrix (real-equivalent, or complex planes: half of it)
+  const size_t pass_bytes = a.cx ? (size_t)a.RT * a.RT / 4 * 1024 : (size_t)a.RT * a.KB * 1024;
   float scaleE = 1.0f, scaleP = 1.0f;
 
   // energy matrix and vector
@@ -294,8 +311,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 
     double* ezd = (double*)(blk + kParamBytes) + 2 * (size_t)Npad * Npad + Npad;
     for (int n = tid; n < Npad; n += blockDim.x) ezd[n] = n < N ? cz * realeq_vec(z, n) : 0.0;
   } else {
-    scaleE = pack_fragments(W, ld, cE, nt, N, a.RT, a.KB, kEPasses, 0, frag + (size_t)npP * a.RT * a.KB * 1024, red);
-    float* ezf = (float*)(frag + (size_t)(npP + kEPasses) * a.RT * a.KB * 1024) + Npad;
+    scaleE = pack_fragments(W, ld, cE, nt, N, a.RT, a.KB, kEPasses, 0, frag + (size_t)npP * pass_bytes, red, a.cx);
+    float* ezf = (float*)(frag + (size_t)(npP + kEPasses) * pass_bytes) + Npad;
     for (int n = tid; n < Npad; n += blockDim.x) ezf[n] = n < N ? (float)(cz * realeq_vec(z, n)) : 0.0f;
     float* afv = ezf + Npad;
     for (int n = tid; n < Npad; n += blockDim.x) {
@@ -321,7 +338,6 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 
     // p = o + TPR kb, o outer: column p then sits in register slot kb, a
     // compile-time index of the unrolled inner loop.  The two vectors alternate
     // between steps, so one barrier per step orders all reads and writes.
-    constexpr int RMAX = BS >= 1024 ? 128 : (BS >= 512 ? 64 : 32);  // rows covered (nt <= RMAX)
     constexpr int TPR = BS / RMAX;                               // threads per row
     constexpr int KMAX = RMAX / TPR;                             // columns per thread
     static_assert(64 % TPR == 0, "the threads of a row share a wavefront");
@@ -389,7 +405,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 
     }
     __syncthreads();
     if (!a.fp64) {
-      float* afv = (float*)(frag + (size_t)(npP + kEPasses) * a.RT * a.KB * 1024) + 2 * Npad;
+      float* afv = (float*)(frag + (size_t)(npP + kEPasses) * pass_bytes) + 2 * Npad;
       for (int m = tid; m < nt; m += blockDim.x)
         afv[2 * m] = (float)(log2(sigma2 * W[m * ld + m].re / (8.0 * s * s)) / 8.0);
     }
@@ -410,8 +426,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 
       double* pbd = (double*)(blk + kParamBytes) + 2 * (size_t)Npad * Npad;
       for (int n = tid; n < Npad; n += blockDim.x) pbd[n] = n < N ? cb * realeq_vec(bv, n) : 0.0;
     } else {
-      scaleP = pack_fragments(W, ld, cP, nt, N, a.RT, a.KB, npP, a.pm == PM_BF16X1, frag, red);
-      float* pbf = (float*)(frag + (size_t)(npP + kEPasses) * a.RT * a.KB * 1024);
+      scaleP = pack_fragments(W, ld, cP, nt, N, a.RT, a.KB, npP, a.pm == PM_BF16X1, frag, red, a.cx);
+      float* pbf = (float*)(frag + (size_t)(npP + kEPasses) * pass_bytes);
       for (int n = tid; n < Npad; n += blockDim.x) pbf[n] = n < N ? (float)(cb * realeq_vec(bv, n)) : 0.0f;
     }
   } else if (a.fp64) {
@@ -441,17 +457,12 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 
 
 bool setup_w_global(int nt) { return nt > 32; }
 
-template <int BS>
+template <int BS, bool WG, int RMAX>
 hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s) {
-  const bool wg = setup_w_global(a.nt);
-  const size_t lds = (size_t)((wg ? 0 : a.nt * (a.nt + 1)) + 6 * a.nt) * sizeof(cd) + BS * sizeof(double) +
+  if (WG != setup_w_global(a.nt) || a.nt > RMAX) return hipErrorInvalidValue;
+  const size_t lds = (size_t)((WG ? 0 : a.nt * (a.nt + 1)) + 6 * a.nt) * sizeof(cd) + BS * sizeof(double) +
                      ((BS == 256 ? 16 : 32) * (size_t)(a.nt + 1) + 32) * sizeof(cd);
-  void (*k)(SetupArgs);
-  if (wg != (BS > 256)) return hipErrorInvalidValue;   // the working matrix is in LDS exactly for 256 threads
-  if constexpr (BS > 256)
-    k = a.fp64 ? setup_kernel<double, true, BS> : setup_kernel<float, true, BS>;
-  else
-    k = a.fp64 ? setup_kernel<double, false, BS> : setup_kernel<float, false, BS>;
+  void (*k)(SetupArgs) = a.fp64 ? setup_kernel<double, WG, BS, RMAX> : setup_kernel<float, WG, BS, RMAX>;
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -465,8 +476,8 @@ hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s) {
 // sweep), so that LDS holds only the staging buffers: 512 threads and two workgroups per CU up to
 // 64 antennas (their latency-bound Gauss-Jordan steps overlap), 1024 threads beyond.
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
-  if (a.nt <= 32) return launch_setup_bs<256>(a, s);
-  return a.nt <= 64 ? launch_setup_bs<512>(a, s) : launch_setup_bs<1024>(a, s);
+  if (a.nt <= 32) return launch_setup_bs<256, false, 32>(a, s);
+  return a.nt <= 64 ? launch_setup_bs<512, true, 64>(a, s) : launch_setup_bs<1024, true, 128>(a, s);
 }
 
 }  // namespace dmala

@@ -37,7 +37,8 @@ def _gpu_mhgd(b, C, T, seed, precision, tau=2.0):
 
 
 @pytest.mark.parametrize("precision,nt,M,snr,C,T", [("fp64", 4, 16, 10.0, 16, 50), ("fp32", 4, 16, 10.0, 16, 50),
-                                                     ("fp32", 32, 64, 22.0, 32, 60), ("fp64", 32, 64, 22.0, 16, 30)])
+                                                     ("fp32", 32, 64, 22.0, 32, 60), ("fp64", 32, 64, 22.0, 16, 30),
+                                                     ("fp32", 64, 64, 24.0, 32, 40)])
 def test_mhgd_chains_match_the_oracle(precision, nt, M, snr, C, T):
     batch = W.make_batch(nt, nt, M, snr, 3, seed=nt + M)
     b = batch.as_precision(np.float64 if precision == "fp64" else np.float32)

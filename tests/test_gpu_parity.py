@@ -230,7 +230,11 @@ def test_windowed_proposal_matches_oracle(M, snr, shift):
     (48, 64, 0.0, 20.0, 32, 30, 0),      # 96 dims padded to 128, automatic layout
     (64, 64, 0.0, 22.0, 32, 30, 3),      # one wave per 16 chains, matrices in LDS
     (64, 64, 0.0, 22.0, 32, 30, 4),      # two waves per 16 chains, matrices from L2
+    (64, 64, 0.0, 22.0, 48, 30, 8),      # the same with complex-plane matrices, three chain blocks
+    (50, 16, 0.0, 18.0, 32, 30, 8),      # complex planes, 50 antennas (padding rows and K columns)
     (128, 256, 0.5, 30.0, 32, 20, 0),    # Kronecker-correlated 128x128 256-QAM, four waves per 16 chains
+    (128, 256, 0.5, 30.0, 48, 20, 9),    # complex planes, four waves per 16 chains, 512-thread workgroups
+    (100, 64, 0.0, 24.0, 32, 20, 9),     # complex planes, 100 antennas
     (41, 16, 0.0, 18.0, 32, 30, 0),      # 1024-thread setup, 41 rows over 16 threads per row (ragged slots)
     (70, 64, 0.0, 22.0, 32, 20, 0),      # working matrix in the workspace, 70 rows over 8 threads per row
     (128, 4, 0.0, 8.0, 32, 20, 0),       # QPSK: 256 marginal rows, H read from global memory (1024 threads)
@@ -255,10 +259,11 @@ def test_large_shapes_fp32(nt, M, rho, snr, C, T, tile):
 
 
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
-@pytest.mark.parametrize("nt,M", [(32, 64), (64, 64), (128, 256)])
-def test_reduced_precision_kernel_is_reversible(precision, nt, M):
+@pytest.mark.parametrize("nt,M,tile", [(32, 64, 0), (64, 64, 0), (128, 256, 0), (64, 64, 8), (128, 256, 9)])
+def test_reduced_precision_kernel_is_reversible(precision, nt, M, tile):
     """Reduced-precision proposals keep the exact target: device log-ratios are antisymmetric
-    and the energy term matches the float64 metric on random state pairs."""
+    and the energy term matches the float64 metric on random state pairs (tile 8, 9: complex-plane
+    matrices)."""
     import torch
     import paper_2407_06042_amd as dm
     b = W.make_batch(nt, nt, M, 25.0, 1, seed=nt).as_precision(np.float32)
@@ -268,8 +273,10 @@ def test_reduced_precision_kernel_is_reversible(precision, nt, M):
     xf = rng.integers(0, prob.Q, size=(1, P, prob.N))
     xt = np.where(rng.random((1, P, prob.N)) < 0.1, rng.integers(0, prob.Q, size=(1, P, prob.N)), xf)
     Hcm, y, s2 = dm.device_inputs(b.H, b.y, b.sigma2, precision)
-    fwd = dm.debug_eval(Hcm, y, s2, M, torch.from_numpy(xf).cuda(), torch.from_numpy(xt).cuda(), precision=precision).cpu().numpy()[0]
-    rev = dm.debug_eval(Hcm, y, s2, M, torch.from_numpy(xt).cuda(), torch.from_numpy(xf).cuda(), precision=precision).cpu().numpy()[0]
+    fwd = dm.debug_eval(Hcm, y, s2, M, torch.from_numpy(xf).cuda(), torch.from_numpy(xt).cuda(), precision=precision,
+                        tile_config=tile).cpu().numpy()[0]
+    rev = dm.debug_eval(Hcm, y, s2, M, torch.from_numpy(xt).cuda(), torch.from_numpy(xf).cuda(), precision=precision,
+                        tile_config=tile).cpu().numpy()[0]
     # log q(x'|x) forward == log q(x'|x) seen as the reverse term of the swapped pair
     np.testing.assert_allclose(fwd[:, 0], rev[:, 1], rtol=1e-6, atol=1e-5)
     np.testing.assert_allclose(fwd[:, 3], -rev[:, 3], rtol=1e-5, atol=1e-4)
