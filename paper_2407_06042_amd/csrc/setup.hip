@@ -47,6 +47,7 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 // the same block: the Gauss-Jordan update keeps four row entries in flight
 // (the compiler would otherwise load all of them at once and spill the matrix).
 typedef double d2v __attribute__((ext_vector_type(2)));
+typedef double d4 __attribute__((ext_vector_type(4)));
 template <int TPR>
 __device__ __forceinline__ void lds_read4(uint32_t a, d2v (&r)[4]) {
   asm volatile(
@@ -60,15 +61,19 @@ __device__ __forceinline__ void lds_read4(uint32_t a, d2v (&r)[4]) {
       : "memory");
 }
 
+// Sum (or maximum) of v over the workgroup, returned to every thread: a butterfly within each
+// wavefront, then one pass over the per-wave partials in a fixed order (two barriers).
 __device__ double block_reduce(double v, double* red, bool is_max) {
-  const int tid = threadIdx.x;
-  red[tid] = v;
-  __syncthreads();
-  for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
-    if (tid < w) red[tid] = is_max ? fmax(red[tid], red[tid + w]) : red[tid] + red[tid + w];
-    __syncthreads();
+  const int tid = threadIdx.x, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double u = __shfl_xor(v, o, 64);
+    v = is_max ? fmax(v, u) : v + u;
   }
-  const double r = red[0];
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int w = 1; w < nw; ++w) r = is_max ? fmax(r, red[w]) : r + red[w];
   __syncthreads();
   return r;
 }
@@ -154,14 +159,15 @@ __device__ void pack_dense(const cd* X, int ld, double c, int N, int Npad, doubl
   }
 }
 
-// 256-thread workgroups (instances up to 32 antennas) run five per CU: at most 96 registers, and
-// about 31 KiB of LDS with H staged 16 receive antennas at a time.
+// Working-matrix placement and thread counts (launch_setup): up to 64 antennas 256 threads with the
+// matrix in LDS (up to about 75 KiB: two workgroups per CU), beyond that 1024 threads with the
+// matrix in this instance's slice of the workspace.
 // RMAX: rows of the working matrix the Gauss-Jordan register layout covers (threads per row BS / RMAX).
 template <typename TIn, bool WGLOB, int BS, int RMAX>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? (WGLOB ? 4 : 5) : 1)))
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RMAX <= 32 ? 5 : (BS == 256 ? 2 : 1))))
 void setup_kernel(SetupArgs a) {
   const int b = blockIdx.x, tid = threadIdx.x, nt = a.nt, nr = a.nr, N = a.N, Npad = a.Npad;
-  const int ld = nt + 1;  // padded leading dimension of the LDS matrices (no bank conflicts on columns)
+  const int ld = nt + 1;  // padded leading dimension of the matrices (no LDS bank conflicts on columns)
   const InstDesc dsc = inst_desc(a.desc, b, nt, nr, a.Q * a.Q, 1);
   const TIn* Hg = (const TIn*)a.H + 2 * dsc.h_off;
   const TIn* y = (const TIn*)a.y + 2 * dsc.y_off;
@@ -178,9 +184,9 @@ void setup_kernel(SetupArgs a) {
     z = W + nt * ld;
   }
   cd* bv = z + nt;
-  cd* rowp = bv + nt;       // 2 x nt (alternating Gauss-Jordan steps)
-  cd* colp = rowp + 2 * nt; // 2 x nt
-  double* red = (double*)(colp + 2 * nt);
+  cd* rowp = bv + nt;       // 2 x 2 x nt (alternating Gauss-Jordan steps, two pivot rows each)
+  cd* colp = rowp + 4 * nt; // 2 x 2 x nt
+  double* red = (double*)(colp + 4 * nt);
   unsigned char* blk = a.ws_inst + (size_t)b * a.inst_stride;
 
   const int Q = a.Q, M = Q * Q;
@@ -190,96 +196,98 @@ void setup_kernel(SetupArgs a) {
   const double beta = a.naive ? 1.0 : a.beta_mult * s * s / sigma2;
   const double gamma = a.gamma_mult * sigma2 / (2.0 * s * s);
 
-  // G = H^H H and z = H^H y.  H is staged in LDS in chunks of receive
-  // antennas, transposed with a padded row (Ht[i][m]); each thread accumulates
-  // its (m, m2) entries (and entries of z) in registers across the chunks.
+  // G = H^H H and z = H^H y.  H is staged in LDS in chunks of receive antennas,
+  // transposed with a padded row whose last entry holds y (Ht[i][m], Ht[i][nt] = y_i).
+  // G on the matrix cores: with X = Re + i Im of the staged H^T (nt x nr),
+  //   Re G = Re Re^T + Im Im^T,   Im G = Re Im^T - Im Re^T,
+  // four float64 16x16x4 MFMAs per 16 x 16 tile and 4 receive antennas; each wave
+  // accumulates the upper-triangle tiles (tr <= tc) assigned to it in registers across
+  // the chunks and writes the tile and its conjugate transpose.  z on the vector ALUs:
+  // P = BS / RMAX consecutive threads share an antenna m and split the receive
+  // antennas, then sum over those lanes.
   double nonfinite = 0.0;
   {
-    // H is staged in LDS in chunks of receive antennas, transposed with a padded
-    // row whose last entry holds y (Ht[i][m], Ht[i][nt] = y_i), so that z is one
-    // more column of the product: z_m = (H^H [H y])_{m, nt}.  Each thread
-    // accumulates a 2 x 2 block of entries in registers across the chunks; only
-    // blocks on or above the diagonal and the blocks of the z column are
-    // computed, and the lower triangle is written as the conjugate.
-    constexpr int kIC = BS == 256 ? 16 : 32;
-    constexpr int kBPT = WGLOB ? (BS >= 1024 || BS == 256 ? 3 : 2) : 1;  // blocks per thread per group (one group for every nt)
-    cd* Ht = (cd*)(red + BS);               // kIC x ld, then one spare row read past the last column
-    const int nb = (nt + 1) >> 1;           // 2-row blocks
-    const int nbu = nb * (nb + 1) / 2;      // blocks on or above the diagonal
-    const int nblk = nbu + nb;              // ... and the z column
-    for (int b0 = 0; b0 < nblk; b0 += kBPT * BS) {
-      int m[kBPT], m2[kBPT];
-      cd acc[kBPT][2][2];
+    constexpr int kIC = RMAX <= 32 ? 16 : 32;
+    constexpr int NW = BS / 64;
+    constexpr int kNT = (RMAX + 15) / 16;                         // tile rows at nt = RMAX
+    constexpr int kTPW = (kNT * (kNT + 1) / 2 + NW - 1) / NW;     // tiles per wave
+    constexpr int P = BS / RMAX;
+    static_assert(P >= 1 && 64 % P == 0, "the threads of an antenna share a wavefront");
+    // kIC x ld, then one spare row; with the working matrix in LDS (33 to 64
+    // antennas) the staging buffer is its first rows, written only after the last read
+    cd* Ht = (!WGLOB && RMAX > 32) ? W : (cd*)(red + BS);
+    const int lane = tid & 63, wv = tid >> 6;
+    const int ntr = (nt + 15) >> 4, ntiles = ntr * (ntr + 1) / 2;
+    int m0[kTPW], m1[kTPW];
+    d4 gre[kTPW], gim[kTPW];
 #pragma unroll
-      for (int q = 0; q < kBPT; ++q) {
-        int bi = b0 + tid + q * BS;
-        if (bi < nbu) {           // upper block (br, bc), bc >= br, row-major over the triangle
-          int br = 0;
-          while (bi >= nb - br) { bi -= nb - br; ++br; }
-          m[q] = 2 * br;
-          m2[q] = 2 * (br + bi);
-        } else {                  // z block (past nblk: idle)
-          m[q] = 2 * (bi - nbu);
-          m2[q] = nt;
-        }
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-          for (int c = 0; c < 2; ++c) acc[q][r][c] = {0.0, 0.0};
+    for (int q = 0; q < kTPW; ++q) {
+      int t = wv + q * NW, tr = 0;
+      if (t >= ntiles) t = 0;
+      while (t >= ntr - tr) { t -= ntr - tr; ++tr; }
+      m0[q] = 16 * tr;
+      m1[q] = 16 * (tr + t);
+      gre[q] = d4{0.0, 0.0, 0.0, 0.0};
+      gim[q] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+    const int zm = tid / P, zp = tid % P;
+    cd zacc = {0.0, 0.0};
+    for (int i0 = 0; i0 < nr; i0 += kIC) {
+      const int ic = nr - i0 < kIC ? nr - i0 : kIC;
+      for (int e = tid; e < ic * (nt + 1); e += BS) {
+        const int mm = e / ic, ii = e % ic;
+        const TIn* src = mm < nt ? Hg + 2 * ((size_t)mm * nr + i0 + ii) : y + 2 * (i0 + ii);
+        Ht[ii * ld + mm] = {(double)src[0], (double)src[1]};
       }
-      for (int i0 = 0; i0 < nr; i0 += kIC) {
-        const int ic = nr - i0 < kIC ? nr - i0 : kIC;
-        for (int e = tid; e < ic * (nt + 1); e += BS) {
-          const int mm = e / ic, ii = e % ic;
-          const TIn* src = mm < nt ? Hg + 2 * ((size_t)mm * nr + i0 + ii) : y + 2 * (i0 + ii);
-          Ht[ii * ld + mm] = {(double)src[0], (double)src[1]};
-        }
-        __syncthreads();
+      __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kBPT; ++q) {
-          if (b0 + tid + q * BS < nblk) {
-            // reads reach one entry past a row (column nt + 1, or row nt of an odd nt):
-            // those products are never stored
-            const cd* ha = Ht + m[q];
-            const cd* hb = Ht + m2[q];
-            for (int ii = 0; ii < ic; ++ii) {
-              const cd a0 = ha[ii * ld], a1 = ha[ii * ld + 1];
-              const cd c0 = hb[ii * ld], c1 = hb[ii * ld + 1];
-              const cd av[2] = {a0, a1}, cv[2] = {c0, c1};
-#pragma unroll
-              for (int r = 0; r < 2; ++r)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                  cd& g = acc[q][r][c];
-                  g.re = fma(av[r].re, cv[c].re, fma(av[r].im, cv[c].im, g.re));
-                  g.im = fma(av[r].re, cv[c].im, fma(-av[r].im, cv[c].re, g.im));
-                }
-            }
+      for (int q = 0; q < kTPW; ++q) {
+        if (wv + q * NW < ntiles) {
+          const int ra = m0[q] + (lane & 15), rb = m1[q] + (lane & 15);
+          for (int kk = 0; kk < ic; kk += 4) {
+            const int ii = kk + (lane >> 4);
+            const bool ok = ii < ic;
+            const cd va = (ok && ra < nt) ? Ht[ii * ld + ra] : cd{0.0, 0.0};
+            const cd vb = (ok && rb < nt) ? Ht[ii * ld + rb] : cd{0.0, 0.0};
+            gre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.re, vb.re, gre[q], 0, 0, 0);
+            gre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.im, vb.im, gre[q], 0, 0, 0);
+            gim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.re, vb.im, gim[q], 0, 0, 0);
+            gim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-va.im, vb.re, gim[q], 0, 0, 0);
           }
         }
-        __syncthreads();
       }
+      if (zm < nt) {
+        for (int ii = zp; ii < ic; ii += P) {
+          const cd h = Ht[ii * ld + zm], yv = Ht[ii * ld + nt];
+          zacc.re = fma(h.re, yv.re, fma(h.im, yv.im, zacc.re));
+          zacc.im = fma(h.re, yv.im, fma(-h.im, yv.re, zacc.im));
+        }
+      }
+      __syncthreads();
+    }
 #pragma unroll
-      for (int q = 0; q < kBPT; ++q) {
-        if (b0 + tid + q * BS < nblk) {
+    for (int o = P >> 1; o > 0; o >>= 1) {
+      zacc.re += __shfl_xor(zacc.re, o, 64);
+      zacc.im += __shfl_xor(zacc.im, o, 64);
+    }
+    if (zm < nt && zp == 0) {
+      z[zm] = zacc;
+      if (!isfinite(zacc.re) || !isfinite(zacc.im)) nonfinite = 1.0;
+    }
+    // lane l, register j of a tile's accumulator: row l / 16 + 4 j, column l % 16
 #pragma unroll
-          for (int r = 0; r < 2; ++r)
+    for (int q = 0; q < kTPW; ++q) {
+      if (wv + q * NW < ntiles) {
+        const int col = m1[q] + (lane & 15);
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              const int i = m[q] + r, j = m2[q] + c;
-              const cd g = acc[q][r][c];
-              if (i >= nt) continue;
-              if (m2[q] == nt) {
-                if (c == 0) z[i] = g;
-                else continue;
-              } else if (j < nt) {
-                W[i * ld + j] = g;
-                if (m2[q] != m[q]) W[j * ld + i] = {g.re, -g.im};
-              } else {
-                continue;
-              }
-              if (!isfinite(g.re) || !isfinite(g.im)) nonfinite = 1.0;
-            }
+        for (int j = 0; j < 4; ++j) {
+          const int row = m0[q] + (lane >> 4) + 4 * j;
+          if (row < nt && col < nt) {
+            const double re = gre[q][j], im = gim[q][j];
+            W[row * ld + col] = {re, im};
+            if (m0[q] != m1[q]) W[col * ld + row] = {re, -im};
+            if (!isfinite(re) || !isfinite(im)) nonfinite = 1.0;
+          }
         }
       }
     }
@@ -323,102 +331,174 @@ void setup_kernel(SetupArgs a) {
   __syncthreads();
 
   if (!a.naive) {
-    // W <- (G + gamma I)^-1 by in-place Gauss-Jordan
-    for (int m = tid; m < nt; m += blockDim.x) W[m * ld + m].re += gamma;
-    __syncthreads();
-    // Gauss-Jordan with the working matrix in registers: thread t keeps row
-    // t / TPR, columns t % TPR + TPR k (k < KMAX), for the whole sweep.  A step on
-    // pivot p: the owners of column p publish it (colp); the threads of row p,
+    // W <- (G + gamma I)^-1 by in-place Gauss-Jordan with the working matrix in
+    // registers, in S x S blocks on a T x T thread grid: thread (ti, tj) keeps
+    // rows ti + T a and columns tj + T c (a, c < S) for the whole sweep.  A step
+    // on pivot p: the owners of column p publish it (colp); the threads of row p,
     // which share a wavefront with the pivot, read the pivot from its lane, scale
     // their row by its inverse (the inverse itself in column p) and publish it
     // (rowp); after one barrier every other row i clears its column p and
-    // subtracts colp[i] * rowp, which leaves -w_ip / w_pp there.  The steps on
+    // subtracts colp[i] * rowp, which leaves -w_ip / w_pp there.  Per step a
+    // thread reads S entries of each vector for S^2 updates.  The steps on
     // different pivots commute (G + gamma I is Hermitian positive definite, so
     // every pivot stays nonzero in any order), so they run in the order
-    // p = o + TPR kb, o outer: column p then sits in register slot kb, a
+    // p = o + T kb, o outer: row and column p then sit in register slot kb, a
     // compile-time index of the unrolled inner loop.  The two vectors alternate
     // between steps, so one barrier per step orders all reads and writes.
-    constexpr int TPR = BS / RMAX;                               // threads per row
-    constexpr int KMAX = RMAX / TPR;                             // columns per thread
-    static_assert(64 % TPR == 0, "the threads of a row share a wavefront");
-    static_assert(KMAX % 4 == 0 && 6 * TPR + 1 < 256, "row entries are read four at a time");
-    const int gi = tid / TPR, gj = tid % TPR;
-    cd w[KMAX];
+    constexpr int T = BS >= 1024 ? 32 : 16;
+    constexpr int S = RMAX / T;
+    static_assert(T * T == BS && S * T == RMAX && 64 % T == 0, "square thread grid, a row's threads in one wavefront");
+    const int ti = tid / T, tj = tid % T;
+    cd w[S][S];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-      const int j = gj + TPR * k;
-      w[k] = (gi < nt && j < nt) ? W[gi * ld + j] : cd{0.0, 0.0};
-    }
+    for (int ra = 0; ra < S; ++ra)
+#pragma unroll
+      for (int c = 0; c < S; ++c) {
+        const int i = ti + T * ra, j = tj + T * c;
+        w[ra][c] = (i < nt && j < nt) ? W[i * ld + j] : cd{0.0, 0.0};
+        if (i == j && i < nt) w[ra][c].re += gamma;
+      }
+    // Pivots are taken two at a time where they can be (rows p and p + 1 of the same
+    // register slot, owned by thread rows o and o + 1 of one wavefront): the 2 x 2
+    // pivot block B is inverted in registers, rows p and p + 1 become B^-1 times
+    // themselves (the partner row's entries come from lane + T), and every other row
+    // subtracts colp0[i] * rowp0 + colp1[i] * rowp1 -- one barrier per two pivots.
+    // (1024 threads: single pivots, as the pair step would not fit in 128 registers.)
+    constexpr bool kPair = BS < 1024;
     int par = 0;
 #pragma unroll 1
-    for (int o = 0; o < TPR && o < nt; ++o) {
+    for (int o = 0; o < T && o < nt; o += kPair ? 2 : 1) {
 #pragma unroll
-      for (int kb = 0; kb < KMAX; ++kb) {
-        const int p = o + TPR * kb;
-        if (p < nt) {
-          cd* rp = rowp + par * nt;
-          cd* cp = colp + par * nt;
-          par ^= 1;
-          if (gi < nt && gj == o) cp[gi] = w[kb];
-          if (gi == p) {
-            const int lane = (p * TPR + o) & 63;
-            const cd piv = {readlane_f64(w[kb].re, lane), readlane_f64(w[kb].im, lane)};
-            const double rd = 1.0 / (piv.re * piv.re + piv.im * piv.im);
-            const cd inv = {piv.re * rd, -piv.im * rd};
+      for (int kb = 0; kb < S; ++kb) {
+        const int p = o + T * kb;
+        if (p >= nt) continue;
+        cd* rp = rowp + par * 2 * nt;
+        cd* cp = colp + par * 2 * nt;
+        par ^= 1;
+        if (kPair && p + 1 < nt) {
+          if (tj == o || tj == o + 1) {
+            cd* cpx = cp + (tj == o ? 0 : nt);
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k) w[k] = cmul(w[k], inv);
-            if (gj == o) w[kb] = inv;
+            for (int ra = 0; ra < S; ++ra)
+              if (ti + T * ra < nt) cpx[ti + T * ra] = w[ra][kb];
+          }
+          if (tid >> 6 == (o * T) >> 6) {   // the wavefront of rows p and p + 1
+            const int l0 = (o * T + o) & 63;
+            const cd pa = {readlane_f64(w[kb][kb].re, l0), readlane_f64(w[kb][kb].im, l0)};
+            const cd pb = {readlane_f64(w[kb][kb].re, l0 + 1), readlane_f64(w[kb][kb].im, l0 + 1)};
+            const cd pc = {readlane_f64(w[kb][kb].re, l0 + T), readlane_f64(w[kb][kb].im, l0 + T)};
+            const cd pd = {readlane_f64(w[kb][kb].re, l0 + T + 1), readlane_f64(w[kb][kb].im, l0 + T + 1)};
+            const cd det = {pa.re * pd.re - pa.im * pd.im - (pb.re * pc.re - pb.im * pc.im),
+                            pa.re * pd.im + pa.im * pd.re - (pb.re * pc.im + pb.im * pc.re)};
+            const double rd = 1.0 / (det.re * det.re + det.im * det.im);
+            const cd idet = {det.re * rd, -det.im * rd};
+            const cd q00 = cmul(pd, idet), q11 = cmul(pa, idet);
+            const cd q01 = cmul({-pb.re, -pb.im}, idet), q10 = cmul({-pc.re, -pc.im}, idet);
+            const bool top = ti == o;
+            const cd qs = top ? q00 : q11, qo = top ? q01 : q10;   // own row, partner row
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-              const int j = gj + TPR * k;
-              if (j < nt) rp[j] = w[k];
+            for (int c = 0; c < S; ++c) {
+              const cd oth = {__shfl_xor(w[kb][c].re, T, 64), __shfl_xor(w[kb][c].im, T, 64)};
+              if (ti == o || ti == o + 1) w[kb][c] = cadd(cmul(qs, w[kb][c]), cmul(qo, oth));
+            }
+            if (ti == o || ti == o + 1) {
+              if (tj == o) w[kb][kb] = top ? q00 : q10;
+              if (tj == o + 1) w[kb][kb] = top ? q01 : q11;
+              cd* rpx = rp + (top ? 0 : nt);
+#pragma unroll
+              for (int c = 0; c < S; ++c)
+                if (tj + T * c < nt) rpx[tj + T * c] = w[kb][c];
             }
           }
           __syncthreads();
-          if (gi < nt && gi != p) {
-            const cd ci = cp[gi];
-            if (gj == o) w[kb] = {0.0, 0.0};
-            // entries past column nt - 1 read whatever follows rowp in LDS (inside the
-            // allocation); they are never stored
-            const uint32_t ra = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) cd*)(rp + gj);
+          // row entries past column nt - 1 read whatever follows the row vectors in LDS
+          // (inside the allocation); they update register entries that are never stored
+          cd r0[S], r1[S];
 #pragma unroll
-            for (int k0 = 0; k0 < KMAX; k0 += 4) {
-              if (TPR * k0 < nt) {
-                d2v r[4];
-                lds_read4<TPR>(ra + 16 * TPR * k0, r);
+          for (int c = 0; c < S; ++c) {
+            r0[c] = rp[tj + T * c];
+            r1[c] = rp[nt + tj + T * c];
+          }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                  cd& v = w[k0 + q];
-                  v.re = fma(-ci.re, r[q].x, fma(ci.im, r[q].y, v.re));
-                  v.im = fma(-ci.re, r[q].y, fma(-ci.im, r[q].x, v.im));
-                }
+          for (int ra = 0; ra < S; ++ra) {
+            const int i = ti + T * ra;
+            if (i < nt && i != p && i != p + 1) {
+              const cd c0 = cp[i], c1 = cp[nt + i];
+              if (tj == o || tj == o + 1) w[ra][kb] = {0.0, 0.0};
+#pragma unroll
+              for (int c = 0; c < S; ++c) {
+                cd& v = w[ra][c];
+                v.re = fma(-c0.re, r0[c].re, fma(c0.im, r0[c].im, v.re));
+                v.im = fma(-c0.re, r0[c].im, fma(-c0.im, r0[c].re, v.im));
+                v.re = fma(-c1.re, r1[c].re, fma(c1.im, r1[c].im, v.re));
+                v.im = fma(-c1.re, r1[c].im, fma(-c1.im, r1[c].re, v.im));
+              }
+            }
+          }
+        } else {
+          // a single pivot (1024 threads, or the last row of a slot that nt leaves unpaired)
+          if (tj == o) {
+#pragma unroll
+            for (int ra = 0; ra < S; ++ra)
+              if (ti + T * ra < nt) cp[ti + T * ra] = w[ra][kb];
+          }
+          if (ti == o) {
+            const int l0 = (o * T + o) & 63;
+            const cd piv = {readlane_f64(w[kb][kb].re, l0), readlane_f64(w[kb][kb].im, l0)};
+            const double rd = 1.0 / (piv.re * piv.re + piv.im * piv.im);
+            const cd inv = {piv.re * rd, -piv.im * rd};
+#pragma unroll
+            for (int c = 0; c < S; ++c) w[kb][c] = cmul(w[kb][c], inv);
+            if (tj == o) w[kb][kb] = inv;
+#pragma unroll
+            for (int c = 0; c < S; ++c)
+              if (tj + T * c < nt) rp[tj + T * c] = w[kb][c];
+          }
+          __syncthreads();
+          cd r[S];
+#pragma unroll
+          for (int c = 0; c < S; ++c) r[c] = rp[tj + T * c];
+#pragma unroll
+          for (int ra = 0; ra < S; ++ra) {
+            const int i = ti + T * ra;
+            if (i < nt && i != p) {
+              const cd ci = cp[i];
+              if (tj == o) w[ra][kb] = {0.0, 0.0};
+#pragma unroll
+              for (int c = 0; c < S; ++c) {
+                cd& v = w[ra][c];
+                v.re = fma(-ci.re, r[c].re, fma(ci.im, r[c].im, v.re));
+                v.im = fma(-ci.re, r[c].im, fma(-ci.im, r[c].re, v.im));
               }
             }
           }
         }
       }
     }
+    // From the registers of M's blocks: b = M z (each thread's columns, then summed over the T
+    // threads of a row, which every one of them ends with bit for bit), the preconditioned
+    // variance feature from M's diagonal, and A = I - gamma M written back over the matrix.
+    float* afv = (float*)(frag + (size_t)(npP + kEPasses) * pass_bytes) + 2 * Npad;
+    cd zc[S];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-      const int j = gj + TPR * k;
-      if (gi < nt && j < nt) W[gi * ld + j] = w[k];
-    }
-    __syncthreads();
-    if (!a.fp64) {
-      float* afv = (float*)(frag + (size_t)(npP + kEPasses) * pass_bytes) + 2 * Npad;
-      for (int m = tid; m < nt; m += blockDim.x)
-        afv[2 * m] = (float)(log2(sigma2 * W[m * ld + m].re / (8.0 * s * s)) / 8.0);
-    }
-    // b = M z, then W <- A = I - gamma M
-    for (int m = tid; m < nt; m += blockDim.x) {
-      cd acc = {0.0, 0.0};
-      for (int j = 0; j < nt; ++j) acc = cadd(acc, cmul(W[m * ld + j], z[j]));
-      bv[m] = acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < nt * nt; e += blockDim.x) {
-      const int i = e / nt, j = e % nt;
-      W[i * ld + j] = {(i == j ? 1.0 : 0.0) - gamma * W[i * ld + j].re, -gamma * W[i * ld + j].im};
+    for (int c = 0; c < S; ++c) zc[c] = tj + T * c < nt ? z[tj + T * c] : cd{0.0, 0.0};
+#pragma unroll
+    for (int ra = 0; ra < S; ++ra) {
+      const int i = ti + T * ra;
+      cd bp = {0.0, 0.0};
+#pragma unroll
+      for (int c = 0; c < S; ++c) {
+        const int j = tj + T * c;
+        bp = cadd(bp, cmul(w[ra][c], zc[c]));
+        if (i < nt && j < nt) W[i * ld + j] = {(j == i ? 1.0 : 0.0) - gamma * w[ra][c].re, -gamma * w[ra][c].im};
+      }
+#pragma unroll
+      for (int o = T >> 1; o > 0; o >>= 1) {
+        bp.re += __shfl_xor(bp.re, o, 64);
+        bp.im += __shfl_xor(bp.im, o, 64);
+      }
+      if (i < nt && tj == 0) bv[i] = bp;
+      if (i < nt && tj == ti && !a.fp64) afv[2 * i] = (float)(log2(sigma2 * w[ra][ra].re / (8.0 * s * s)) / 8.0);
     }
     __syncthreads();
     if (a.fp64) {
@@ -455,13 +535,15 @@ void setup_kernel(SetupArgs a) {
   }
 }
 
-bool setup_w_global(int nt) { return nt > 32; }
+bool setup_w_global(int nt) { return nt > 64; }
 
 template <int BS, bool WG, int RMAX>
 hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s) {
   if (WG != setup_w_global(a.nt) || a.nt > RMAX) return hipErrorInvalidValue;
-  const size_t lds = (size_t)((WG ? 0 : a.nt * (a.nt + 1)) + 6 * a.nt) * sizeof(cd) + BS * sizeof(double) +
-                     ((BS == 256 ? 16 : 32) * (size_t)(a.nt + 1) + 32) * sizeof(cd);
+  constexpr int kIC = RMAX <= 32 ? 16 : 32;
+  const bool alias = !WG && RMAX > 32;   // the staging buffer is the working matrix's first rows
+  const size_t lds = (size_t)((WG ? 0 : a.nt * (a.nt + 1)) + 10 * a.nt) * sizeof(cd) + BS * sizeof(double) +
+                     (alias ? 0 : (kIC * (size_t)(a.nt + 1) + 32) * sizeof(cd));
   void (*k)(SetupArgs) = a.fp64 ? setup_kernel<double, WG, BS, RMAX> : setup_kernel<float, WG, BS, RMAX>;
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -471,13 +553,14 @@ hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Up to 32 antennas: 256 threads, the working matrix in LDS, five workgroups per CU.  Larger
-// instances keep the working matrix in the workspace between phases (in registers during the
-// sweep), so that LDS holds only the staging buffers: 512 threads and two workgroups per CU up to
-// 64 antennas (their latency-bound Gauss-Jordan steps overlap), 1024 threads beyond.
+// Up to 32 antennas: 256 threads, the working matrix in LDS, five workgroups per CU.  Up to 64
+// antennas: 256 threads, the working matrix in LDS (about 75 KiB with the other vectors), two
+// workgroups per CU whose latency-bound Gauss-Jordan steps overlap.  Larger instances keep the
+// working matrix in the workspace between phases (in registers during the sweep), so that LDS
+// holds only the staging buffers: 1024 threads.
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
   if (a.nt <= 32) return launch_setup_bs<256, false, 32>(a, s);
-  return a.nt <= 64 ? launch_setup_bs<512, true, 64>(a, s) : launch_setup_bs<1024, true, 128>(a, s);
+  return a.nt <= 64 ? launch_setup_bs<256, false, 64>(a, s) : launch_setup_bs<1024, true, 128>(a, s);
 }
 
 }  // namespace dmala
