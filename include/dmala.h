@@ -259,10 +259,20 @@ dmala_status dmala_debug_eval(const void* H, const void* y, const void* sigma2,
                               size_t workspace_bytes, dmala_stream_t stream);
 
 /* ---- Uneven batches: instances of different Nt, Nr, M in one graph launch ----
- * A plan groups the instances of a batch by shape class (Nt, Nr, M), orders the
- * classes by decreasing work (longest processing time first) and runs them all
- * as one HIP graph: per class a setup, a sampler and an estimator kernel, the
- * classes on parallel branches.  Buffers are packed in instance order:
+ * (Section II-A: a base station detects many users' streams of different sizes at
+ * once.)  A plan groups the instances of a batch by shape class (Nt, Nr, M) and runs
+ * them all as one HIP graph.  Persistent form (the float chains of the plain
+ * preconditioned and naive proposals): the work of all classes is split into items
+ * (setup: an instance; sampler: an instance and a group of 16-chain blocks;
+ * estimator: an instance), the items are grouped by the kernel instantiation that
+ * runs them, and each group is one persistent launch whose resident workgroups take
+ * items from a device list -- the classes with the largest items first (longest
+ * processing time) -- through a global atomic counter; the groups run in stage order
+ * on one stream.  A class's results are bit for bit those of dmala_detect over its
+ * instances.  Other precisions and proposals (float64, learned, MHGD): per class a
+ * setup, a sampler and an estimator kernel, the classes on parallel branches in
+ * decreasing order of work.  Executions of one plan must not overlap (they share its
+ * tables and counters).  Buffers are packed in instance order:
  *   H of instance b at complex offset sum_{j<b} Nt_j Nr_j (column-major per instance),
  *   y at sum_{j<b} Nr_j, sigma2[b]; symbols at sum Nt_j; marginals and marginals_mc at
  *   sum Nt_j M_j; llrs at sum Nt_j log2 M_j; best_energy[b]; final_state at
@@ -271,9 +281,10 @@ dmala_status dmala_debug_eval(const void* H, const void* y, const void* sigma2,
  *   n_chains and n_iters).
  * The per-instance random counters use the instance index b, so a plan and a
  * dmala_detect call over the same instances give identical chains.
- * The plan owns a small device table (hipMalloc at creation, freed by
+ * The plan owns small device tables (instance table at creation; work items,
+ * per-class arguments and counters when its graph is built; freed by
  * dmala_plan_destroy) and its graph; the graph is rebuilt when execute is called
- * with different buffers.  Params: as for dmala_detect (tile_config 0 lets each
+ * with different buffers (that call synchronises the device first).  Params: as for dmala_detect (tile_config 0 lets each
  * class use its tuned or default layout). */
 typedef struct dmala_plan_s* dmala_plan;
 typedef struct { int32_t nt, nr, qam_order; } dmala_shape;
@@ -301,6 +312,10 @@ dmala_status dmala_plan_autotune(dmala_plan plan, const void* H, const void* y, 
 int32_t dmala_plan_num_classes(dmala_plan plan);
 dmala_status dmala_plan_class_info(dmala_plan plan, int32_t k, dmala_shape* shape, int32_t* n_inst,
                                    int32_t* tile_config, int32_t* wg_chain_blocks, double* tuned_ms);
+
+/* The plan's current graph: kernel nodes (*n_kernels) and whether it is the persistent
+ * form (*persistent, 1 or 0); both -1 before the first execute. */
+dmala_status dmala_plan_graph_info(dmala_plan plan, int32_t* n_kernels, int32_t* persistent);
 
 void dmala_plan_destroy(dmala_plan plan);
 

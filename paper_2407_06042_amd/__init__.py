@@ -95,6 +95,8 @@ def lib():
         L.dmala_plan_class_info.restype = ctypes.c_int
         L.dmala_plan_class_info.argtypes = [vp, i32, ctypes.POINTER(Shape), ctypes.POINTER(i32), ctypes.POINTER(i32),
                                             ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+        L.dmala_plan_graph_info.restype = ctypes.c_int
+        L.dmala_plan_graph_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.dmala_plan_destroy.restype = None
         L.dmala_plan_destroy.argtypes = [vp]
         L.dmala_mlp_forward.restype = ctypes.c_int
@@ -111,7 +113,8 @@ def lib():
 
 EXPORTED = ["dmala_workspace_size", "dmala_detect", "dmala_detect_static", "dmala_debug_eval", "dmala_sync_status",
             "dmala_detect_one_workspace_size", "dmala_detect_one", "dmala_gx_loop_sink_size", "dmala_gx_loop", "dmala_plan_create", "dmala_plan_execute",
-            "dmala_plan_autotune", "dmala_plan_num_classes", "dmala_plan_class_info", "dmala_plan_destroy",
+            "dmala_plan_autotune", "dmala_plan_num_classes", "dmala_plan_class_info", "dmala_plan_graph_info",
+            "dmala_plan_destroy",
             "dmala_mlp_forward", "dmala_mlp_train_workspace_size", "dmala_mlp_train_step",
             "dmala_last_error", "dmala_version"]
 
@@ -415,6 +418,14 @@ class Plan:
             out.append(dict(nt=sh.nt, nr=sh.nr, M=sh.qam_order, count=n.value, tile_config=tc.value,
                             wg_chain_blocks=cb.value, tuned_ms=ms.value))
         return out
+
+    def graph_info(self):
+        """(kernel nodes, persistent) of the plan's current graph; (-1, -1) before the first call."""
+        nk, pe = ctypes.c_int32(), ctypes.c_int32()
+        st = lib().dmala_plan_graph_info(self.handle, ctypes.byref(nk), ctypes.byref(pe))
+        if st != 0:
+            raise DmalaError(st, last_error())
+        return nk.value, pe.value
 
     def __del__(self):
         h = getattr(self, "handle", None)

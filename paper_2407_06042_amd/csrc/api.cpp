@@ -141,12 +141,12 @@ dmala_status hip_fail(hipError_t e, const char* what) {
   return fail(DMALA_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-dmala_status enqueue(const void* H, const void* y, const void* sigma2, int32_t n_inst, const Plan& pl,
-                     const dmala_params* p, const dmala_outputs* out, const InstDesc* desc, unsigned char* base,
-                     const int8_t* x_from, const int8_t* x_to, double* eval_out, hipStream_t stream,
-                     double* eval_dim, double sigma2_val) {
+void make_args(const void* H, const void* y, const void* sigma2, int32_t n_inst, const Plan& pl, const dmala_params* p,
+               const dmala_outputs* out, const InstDesc* desc, unsigned char* base, const int8_t* x_from,
+               const int8_t* x_to, double* eval_out, double* eval_dim, double sigma2_val, SetupArgs& sa,
+               SamplerArgs& ka, EstArgs& ea) {
   const Shape& sh = pl.sh;
-  SetupArgs sa{};
+  sa = SetupArgs{};
   sa.desc = desc;
   sa.H = H; sa.y = y; sa.sigma2 = sigma2;
   sa.sigma2_val = sigma2_val;
@@ -156,14 +156,8 @@ dmala_status enqueue(const void* H, const void* y, const void* sigma2, int32_t n
   sa.n_inst = n_inst; sa.nt = sh.nt; sa.nr = sh.nr; sa.Q = sh.Q; sa.N = sh.N; sa.Npad = sh.Npad;
   sa.RT = sh.RT; sa.KB = sh.KB; sa.fp64 = sh.fp64; sa.pm = sh.pm; sa.naive = pl.naive ? 1 : 0; sa.cx = sh.cx;
   sa.tau = pl.tau; sa.alpha_mult = pl.am; sa.beta_mult = pl.bm; sa.gamma_mult = pl.gm;
-  auto mark = [&](int i) {
-    if (!eval_out && out && out->stage_events[i]) (void)hipEventRecord((hipEvent_t)out->stage_events[i], stream);
-  };
-  mark(0);
-  hipError_t e = launch_setup(sa, stream);
-  if (e != hipSuccess) return hip_fail(e, "setup launch");
 
-  SamplerArgs ka{};
+  ka = SamplerArgs{};
   ka.desc = desc;
   ka.ws_inst = base + pl.inst_off; ka.inst_stride = sh.inst_bytes;
   ka.ws_state = base + pl.state_off; ka.state_stride = sh.state_bytes;
@@ -171,8 +165,7 @@ dmala_status enqueue(const void* H, const void* y, const void* sigma2, int32_t n
   ka.key0 = (uint32_t)(p->seed & 0xFFFFFFFFu); ka.key1 = (uint32_t)(p->seed >> 32);
   ka.ctr_base = p->counter_base;
   ka.frag_bytes = (int)sh.frag_bytes;
-  const bool eval = eval_out != nullptr;
-  if (eval) {
+  if (eval_out) {
     ka.x_from = x_from; ka.x_to = x_to; ka.eval_out = eval_out; ka.eval_dim = eval_dim;
   } else if (out) {
     ka.final_state = out->final_state; ka.accept_count = out->accept_count;
@@ -182,25 +175,49 @@ dmala_status enqueue(const void* H, const void* y, const void* sigma2, int32_t n
   }
   ka.mlp = sh.lrn ? p->mlp_weights : nullptr;
   ka.mix_thr = pl.mix_thr;
+
+  ea = EstArgs{};
+  ea.desc = desc;
+  ea.H = H; ea.y = y; ea.sigma2 = sigma2;
+  ea.ws_inst = base + pl.inst_off; ea.inst_stride = sh.inst_bytes;
+  ea.ws_state = base + pl.state_off; ea.state_stride = sh.state_bytes;
+  ea.n_inst = n_inst; ea.nt = sh.nt; ea.nr = sh.nr; ea.Q = sh.Q; ea.N = sh.N; ea.Npad = sh.Npad;
+  ea.C = sh.C; ea.Cpad = sh.Cpad; ea.fp64 = sh.fp64;
+  ea.chunk = estimate_chunk(sh.nt, sh.nr, sh.M, sh.N, sh.C, sh.fp64 != 0);
+  ea.llr_mode = (int)p->llr_mode;
+  ea.llr_clip = 20.0f;
+  if (out) {
+    ea.symbols = out->symbols; ea.marginals = out->marginals; ea.llrs = out->llrs;
+    ea.best_energy = out->best_energy; ea.marginals_mc = out->marginals_mc;
+  }
+}
+
+bool wants_estimates(const dmala_outputs* out) {
+  return out && (out->symbols || out->marginals || out->llrs || out->best_energy || out->marginals_mc);
+}
+
+dmala_status enqueue(const void* H, const void* y, const void* sigma2, int32_t n_inst, const Plan& pl,
+                     const dmala_params* p, const dmala_outputs* out, const InstDesc* desc, unsigned char* base,
+                     const int8_t* x_from, const int8_t* x_to, double* eval_out, hipStream_t stream,
+                     double* eval_dim, double sigma2_val) {
+  const Shape& sh = pl.sh;
+  SetupArgs sa;
+  SamplerArgs ka;
+  EstArgs ea;
+  make_args(H, y, sigma2, n_inst, pl, p, out, desc, base, x_from, x_to, eval_out, eval_dim, sigma2_val, sa, ka, ea);
+  auto mark = [&](int i) {
+    if (!eval_out && out && out->stage_events[i]) (void)hipEventRecord((hipEvent_t)out->stage_events[i], stream);
+  };
+  mark(0);
+  hipError_t e = launch_setup(sa, stream);
+  if (e != hipSuccess) return hip_fail(e, "setup launch");
+  const bool eval = eval_out != nullptr;
   mark(1);
   e = launch_sampler(sh, ka, eval, stream);
   if (e != hipSuccess) return hip_fail(e, "sampler launch");
   mark(2);
   if (eval || !out) return DMALA_OK;
-
-  if (out->symbols || out->marginals || out->llrs || out->best_energy || out->marginals_mc) {
-    EstArgs ea{};
-    ea.desc = desc;
-    ea.H = H; ea.y = y; ea.sigma2 = sigma2;
-    ea.ws_inst = base + pl.inst_off; ea.inst_stride = sh.inst_bytes;
-    ea.ws_state = base + pl.state_off; ea.state_stride = sh.state_bytes;
-    ea.n_inst = n_inst; ea.nt = sh.nt; ea.nr = sh.nr; ea.Q = sh.Q; ea.N = sh.N; ea.Npad = sh.Npad;
-    ea.C = sh.C; ea.Cpad = sh.Cpad; ea.fp64 = sh.fp64;
-    ea.chunk = estimate_chunk(sh.nt, sh.nr, sh.M, sh.N, sh.C, sh.fp64 != 0);
-    ea.llr_mode = (int)p->llr_mode;
-    ea.llr_clip = 20.0f;
-    ea.symbols = out->symbols; ea.marginals = out->marginals; ea.llrs = out->llrs;
-    ea.best_energy = out->best_energy; ea.marginals_mc = out->marginals_mc;
+  if (wants_estimates(out)) {
     e = launch_estimate(ea, stream);
     if (e != hipSuccess) return hip_fail(e, "estimator launch");
   }

@@ -162,11 +162,64 @@ struct EstArgs {
   float llr_clip;  // |LLR| limit of the list and Monte Carlo forms
 };
 
+// Persistent launches (uneven-batch plans).  A work item is one instance (workspace slot) of one
+// class of the plan and, for the sampler, one group of 16-chain blocks; a persistent launch keeps
+// its workgroups resident and each takes the next item of a list (longest classes first) from a
+// global atomic counter until the list is exhausted.  The workgroup that finishes last returns
+// both counters to 0, so a captured graph can replay the launch.
+struct WorkItem {
+  int32_t cls, inst, cg, pad_;
+};
+
+struct Persist {
+  const WorkItem* items;   // NULL: a direct launch (instance blockIdx.x, chain group blockIdx.y)
+  int32_t n_items;
+  int32_t lds_off;         // byte offset of the item broadcast word in the dynamic LDS
+  int32_t* counter;        // [0] next item, [1] workgroups finished
+  const void* cls;         // per-class argument structs (SetupArgs, SamplerArgs or EstArgs)
+};
+
+#ifdef __HIPCC__
+// Next item index for the whole workgroup (after a barrier that ends the previous item's LDS use).
+__device__ inline int persist_take(const Persist& p, unsigned char* lds) {
+  int* slot = (int*)(lds + p.lds_off);
+  __syncthreads();
+  if (threadIdx.x == 0) slot[0] = __hip_atomic_fetch_add(p.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(slot[0]);
+}
+
+// The workgroup has taken its last item; the last one to get here resets the counters.
+__device__ inline void persist_done(const Persist& p) {
+  if (threadIdx.x == 0) {
+    const int f = __hip_atomic_fetch_add(p.counter + 1, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (f == (int)gridDim.x - 1) {
+      __hip_atomic_store(p.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(p.counter + 1, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+#endif
+
+// Launch geometry of one class's kernel: the kernel (identity of a persistent family), threads per
+// workgroup, dynamic LDS bytes and the direct grid.
+struct KernelCfg {
+  const void* k = nullptr;
+  int threads = 0;
+  size_t lds = 0;
+  int gx = 0, gy = 0;
+};
+
 // Host launchers (defined in the .hip translation units).
-hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
+// With cfg != NULL the launchers only fill in the class's launch geometry; with p != NULL (and
+// p->items set) they make a persistent launch of p->n_items items on `grid` workgroups.
+hipError_t launch_setup(const SetupArgs& a, hipStream_t s, const Persist* p = nullptr, int grid = 0,
+                        KernelCfg* cfg = nullptr);
 bool setup_w_global(int nt);
-hipError_t launch_sampler(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s);
-hipError_t launch_estimate(const EstArgs& a, hipStream_t s);
+hipError_t launch_sampler(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s, const Persist* p = nullptr,
+                          int grid = 0, KernelCfg* cfg = nullptr);
+hipError_t launch_estimate(const EstArgs& a, hipStream_t s, const Persist* p = nullptr, int grid = 0,
+                           KernelCfg* cfg = nullptr);
 size_t sampler_lds_bytes(const Shape& sh);
 bool sampler_cfg_valid(const Shape& sh, int cfg);
 int sampler_default_cfg(const Shape& sh);

@@ -61,11 +61,10 @@ struct CM {
 };
 
 template <typename R, int Q, bool SH, int BS>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 && sizeof(R) == 4 && Q <= 8 ? 5 : 1)))
-void estimate_kernel(EstArgs a) {
+__device__ __forceinline__ void estimate_body(const EstArgs& a, const int b) {
   constexpr int M = Q * Q;
   constexpr int NB = Q == 2 ? 1 : (Q == 4 ? 2 : (Q == 8 ? 3 : 4));
-  const int b = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
+  const int tid = threadIdx.x, nth = blockDim.x;
   const int nt = a.nt, nr = a.nr, C = a.C, Npad = a.Npad, N = a.N, CH = a.chunk;
   const InstDesc dsc = inst_desc(a.desc, b, nt, nr, M, C);
   const R* Hg = (const R*)a.H + 2 * dsc.h_off;
@@ -411,6 +410,26 @@ void estimate_kernel(EstArgs a) {
   }
 }
 
+// Direct launch (PERS false): instance blockIdx.x.  Persistent launch: items from the list, each
+// with its class's arguments.
+template <typename R, int Q, bool SH, int BS, bool PERS = false>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 && sizeof(R) == 4 && Q <= 8 ? 5 : 1)))
+void estimate_kernel(EstArgs a, Persist p) {
+  if constexpr (!PERS) {
+    estimate_body<R, Q, SH, BS>(a, blockIdx.x);
+  } else {
+    extern __shared__ __attribute__((aligned(16))) unsigned char esm[];
+    for (;;) {
+      const int it = persist_take(p, esm);
+      if (it >= p.n_items) break;
+      const WorkItem w = p.items[it];
+      const EstArgs ca = ((const EstArgs*)p.cls)[__builtin_amdgcn_readfirstlane(w.cls)];
+      estimate_body<R, Q, SH, BS>(ca, __builtin_amdgcn_readfirstlane(w.inst));
+    }
+    persist_done(p);
+  }
+}
+
 size_t estimate_lds_bytes(int nt, int nr, int M, int N, int chunk, bool fp64) {
   const size_t R = fp64 ? 8 : 4;
   const size_t cm = fp64 ? 32 : 20;
@@ -454,42 +473,56 @@ int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64) {
 }
 
 template <typename R, int Q, int BS>
-static hipError_t launch_eb(const EstArgs& a, hipStream_t s) {
+static hipError_t launch_eb(const EstArgs& a, hipStream_t s, const Persist* p, int gn, KernelCfg* cfg) {
   const size_t hbytes = 2 * (size_t)(a.nt + 1) * a.nr * sizeof(R);
   const bool sh = estimate_h_in_lds(a.nt, a.nr, sizeof(R) == 8);
   const size_t lds = estimate_lds_bytes(a.nt, a.nr, Q * Q, a.N, a.chunk, a.fp64) + (sh ? hbytes + 16 : 0);
-  auto k = sh ? estimate_kernel<R, Q, true, BS> : estimate_kernel<R, Q, false, BS>;
-  if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  void (*k)(EstArgs, Persist);
+  if (p || cfg) k = sh ? estimate_kernel<R, Q, true, BS, true> : estimate_kernel<R, Q, false, BS, true>;
+  else k = sh ? estimate_kernel<R, Q, true, BS> : estimate_kernel<R, Q, false, BS>;
+  if (cfg) {
+    cfg->k = (const void*)k;
+    cfg->threads = BS;
+    cfg->lds = lds;
+    cfg->gx = a.n_inst;
+    cfg->gy = 1;
+    return hipSuccess;
+  }
+  // a persistent launch keeps one more aligned word after the body's LDS (the item broadcast)
+  const size_t lds_run = p ? ((p->lds_off + 4 + 15) & ~(size_t)15) : lds;
+  if (lds_run > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_run);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k, dim3(a.n_inst), dim3(BS), lds, s, a);
+  if (p) hipLaunchKernelGGL(k, dim3(gn), dim3(BS), lds_run, s, a, *p);
+  else hipLaunchKernelGGL(k, dim3(a.n_inst), dim3(BS), lds, s, a, Persist{});
   return hipGetLastError();
 }
 
 template <typename R, int Q>
-static hipError_t launch_e(const EstArgs& a, hipStream_t s) {
+static hipError_t launch_e(const EstArgs& a, hipStream_t s, const Persist* p, int gn, KernelCfg* cfg) {
   if constexpr (sizeof(R) == 8) {
-    return launch_eb<R, Q, 256>(a, s);
+    return launch_eb<R, Q, 256>(a, s, p, gn, cfg);
   } else {
     const int bs = estimate_threads(a.nt, a.nr, Q, false);
-    return bs == 256 ? launch_eb<R, Q, 256>(a, s) : (bs == 512 ? launch_eb<R, Q, 512>(a, s) : launch_eb<R, Q, 1024>(a, s));
+    return bs == 256 ? launch_eb<R, Q, 256>(a, s, p, gn, cfg)
+                     : (bs == 512 ? launch_eb<R, Q, 512>(a, s, p, gn, cfg) : launch_eb<R, Q, 1024>(a, s, p, gn, cfg));
   }
 }
 
 template <typename R>
-static hipError_t launch_r(const EstArgs& a, hipStream_t s) {
+static hipError_t launch_r(const EstArgs& a, hipStream_t s, const Persist* p, int gn, KernelCfg* cfg) {
   switch (a.Q) {
-    case 2: return launch_e<R, 2>(a, s);
-    case 4: return launch_e<R, 4>(a, s);
-    case 8: return launch_e<R, 8>(a, s);
-    case 16: return launch_e<R, 16>(a, s);
+    case 2: return launch_e<R, 2>(a, s, p, gn, cfg);
+    case 4: return launch_e<R, 4>(a, s, p, gn, cfg);
+    case 8: return launch_e<R, 8>(a, s, p, gn, cfg);
+    case 16: return launch_e<R, 16>(a, s, p, gn, cfg);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_estimate(const EstArgs& a, hipStream_t s) {
-  return a.fp64 ? launch_r<double>(a, s) : launch_r<float>(a, s);
+hipError_t launch_estimate(const EstArgs& a, hipStream_t s, const Persist* p, int gn, KernelCfg* cfg) {
+  return a.fp64 ? launch_r<double>(a, s, p, gn, cfg) : launch_r<float>(a, s, p, gn, cfg);
 }
 
 }  // namespace dmala

@@ -38,5 +38,13 @@ dmala_status enqueue(const void* H, const void* y, const void* sigma2, int32_t n
                      const int8_t* x_from, const int8_t* x_to, double* eval_out, hipStream_t stream,
                      double* eval_dim = nullptr, double sigma2_val = 0.0);
 
+// The three kernels' arguments for one class (as enqueue passes them).
+void make_args(const void* H, const void* y, const void* sigma2, int32_t n_inst, const Plan& pl, const dmala_params* p,
+               const dmala_outputs* out, const InstDesc* desc, unsigned char* base, const int8_t* x_from,
+               const int8_t* x_to, double* eval_out, double* eval_dim, double sigma2_val, SetupArgs& sa,
+               SamplerArgs& ka, EstArgs& ea);
+// Whether any estimator output is requested.
+bool wants_estimates(const dmala_outputs* out);
+
 }  // namespace host
 }  // namespace dmala

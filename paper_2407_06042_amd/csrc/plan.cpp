@@ -47,10 +47,32 @@ std::string class_key(const dmala_shape& s, const dmala_params& p) {
 
 }  // namespace
 
+// One persistent launch: a kernel (setup, sampler or estimator instantiation) and the classes
+// whose items it runs.
+struct Family {
+  int stage = 0;            // 0 setup, 1 sampler, 2 estimator
+  const void* k = nullptr;
+  int threads = 0;
+  size_t lds = 0;           // largest body LDS of the member classes
+  std::vector<int> cls;     // member classes, largest items first
+  double cost = 0.0;
+  int item_off = 0, n_items = 0, grid = 0;
+};
+
 struct dmala_plan_s {
   dmala_params params{};
   int n_inst = 0;
   std::vector<ClassInfo> classes;
+  bool persistent = false;  // the graph is the persistent form
+  std::vector<Family> fams;
+  WorkItem* items_dev = nullptr;
+  size_t items_cap = 0;
+  unsigned char* args_dev = nullptr;  // per-class SetupArgs, SamplerArgs, EstArgs arrays
+  size_t args_cap = 0;
+  int32_t* counters = nullptr;        // two per family
+  int counters_cap = 0;
+  int n_cu = 0;
+  std::vector<hipEvent_t> stage_ev;   // per stage: fork and branch joins of the persistent graph
   InstDesc* desc_dev = nullptr;
   size_t ws_total = 0;
   int n_branches = 1;
@@ -72,9 +94,13 @@ struct dmala_plan_s {
   ~dmala_plan_s() {
     drop_graph();
     if (desc_dev) (void)hipFree(desc_dev);
+    if (items_dev) (void)hipFree(items_dev);
+    if (args_dev) (void)hipFree(args_dev);
+    if (counters) (void)hipFree(counters);
     for (auto s : branches) (void)hipStreamDestroy(s);
     if (cap) (void)hipStreamDestroy(cap);
     for (auto e : joins) (void)hipEventDestroy(e);
+    for (auto e : stage_ev) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
   }
 };
@@ -102,6 +128,201 @@ void assign_branches(dmala_plan_s* P) {
   }
 }
 
+// Grow a device buffer (contents not kept).
+template <typename T>
+hipError_t ensure(T*& ptr, size_t& cap, size_t n) {
+  if (n <= cap && ptr) return hipSuccess;
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+  const hipError_t e = hipMalloc((void**)&ptr, n * sizeof(T) + 256);
+  if (e == hipSuccess) cap = n;
+  return e;
+}
+
+// The persistent form: the classes' setup, sampler and estimator work split into items
+// (instance, or instance x chain group), grouped by the kernel instantiation that runs them; one
+// persistent launch per group, groups in stage order on one stream, items of the classes with
+// the largest items first.  DMALA_ERR_UNSUPPORTED when a class has no persistent kernel
+// (float64, learned and MHGD chains), which then take the branch graph.
+dmala_status build_graph_persistent(dmala_plan_s* P, const void* H, const void* y, const void* sigma2,
+                                    const dmala_outputs* out, unsigned char* ws) {
+  const int nc = (int)P->classes.size();
+  hipError_t e;
+  // an earlier launch of this plan may still read the tables rewritten below
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "synchronise");
+  dmala_outputs o = *out;
+  for (int i = 0; i < 4; ++i) o.stage_events[i] = nullptr;
+  const bool est = wants_estimates(&o);
+  std::vector<SetupArgs> sa(nc);
+  std::vector<SamplerArgs> ka(nc);
+  std::vector<EstArgs> ea(nc);
+  std::vector<KernelCfg> cfg(3 * nc);
+  for (int ci = 0; ci < nc; ++ci) {
+    const ClassInfo& c = P->classes[ci];
+    make_args(H, y, sigma2, c.count, c.pl, &P->params, &o, P->desc_dev + c.first, ws + c.ws_off, nullptr, nullptr,
+              nullptr, nullptr, 0.0, sa[ci], ka[ci], ea[ci]);
+    if (launch_setup(sa[ci], nullptr, nullptr, 0, &cfg[3 * ci]) != hipSuccess ||
+        launch_sampler(c.pl.sh, ka[ci], false, nullptr, nullptr, 0, &cfg[3 * ci + 1]) != hipSuccess ||
+        (est && launch_estimate(ea[ci], nullptr, nullptr, 0, &cfg[3 * ci + 2]) != hipSuccess))
+      return DMALA_ERR_UNSUPPORTED;
+  }
+  if (!P->n_cu) {
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "get device");
+    if ((e = hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+      return hip_fail(e, "device attribute");
+  }
+  // families: (stage, kernel, threads)
+  P->fams.clear();
+  std::map<std::tuple<int, const void*, int>, int> fidx;
+  auto item_cost = [&](int stage, int ci) {
+    const ClassInfo& c = P->classes[ci];
+    const double nt = c.shape.nt, nr = c.shape.nr, M = c.shape.qam_order;
+    if (stage == 0) return nt * nt * (nt + nr);
+    if (stage == 1) return c.cost / ((double)c.count * std::max(1, cfg[3 * ci + 1].gy));
+    return (double)P->params.n_chains * nt * (nr + M);
+  };
+  for (int stage = 0; stage < (est ? 3 : 2); ++stage)
+    for (int ci = 0; ci < nc; ++ci) {
+      const KernelCfg& k = cfg[3 * ci + stage];
+      const auto key = std::make_tuple(stage, k.k, k.threads);
+      auto it = fidx.find(key);
+      if (it == fidx.end()) {
+        it = fidx.emplace(key, (int)P->fams.size()).first;
+        Family f;
+        f.stage = stage;
+        f.k = k.k;
+        f.threads = k.threads;
+        P->fams.push_back(f);
+      }
+      Family& f = P->fams[it->second];
+      f.lds = std::max(f.lds, k.lds);
+      f.cls.push_back(ci);
+      f.cost += item_cost(stage, ci) * P->classes[ci].count * (stage == 1 ? k.gy : 1);
+    }
+  std::vector<WorkItem> items;
+  for (auto& f : P->fams) {
+    std::stable_sort(f.cls.begin(), f.cls.end(),
+                     [&](int a, int b) { return item_cost(f.stage, a) > item_cost(f.stage, b); });
+    f.item_off = (int)items.size();
+    for (int ci : f.cls) {
+      const int gy = f.stage == 1 ? cfg[3 * ci + 1].gy : 1;
+      for (int i = 0; i < P->classes[ci].count; ++i)
+        for (int g = 0; g < gy; ++g) items.push_back(WorkItem{ci, i, g, 0});
+    }
+    f.n_items = (int)items.size() - f.item_off;
+    const size_t lds_run = ((f.lds + 15) & ~(size_t)15) + 16;
+    if (lds_run > 65536 &&
+        (e = hipFuncSetAttribute(f.k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_run)) != hipSuccess)
+      return hip_fail(e, "kernel attribute");
+    int nb = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f.k, f.threads, lds_run)) != hipSuccess)
+      return hip_fail(e, "occupancy");
+    if (nb < 1) return fail(DMALA_ERR_HIP, "a persistent kernel does not fit a CU");
+    f.grid = std::min(f.n_items, nb * P->n_cu);
+  }
+  // heavier families of a stage first
+  std::stable_sort(P->fams.begin(), P->fams.end(), [](const Family& a, const Family& b) {
+    return a.stage != b.stage ? a.stage < b.stage : a.cost > b.cost;
+  });
+  const size_t args_bytes = (size_t)nc * (sizeof(SetupArgs) + sizeof(SamplerArgs) + sizeof(EstArgs));
+  if ((e = ensure(P->items_dev, P->items_cap, items.size())) != hipSuccess ||
+      (e = ensure(P->args_dev, P->args_cap, args_bytes)) != hipSuccess)
+    return hip_fail(e, "plan tables");
+  if ((int)P->fams.size() * 2 > P->counters_cap) {
+    size_t cap = 0;
+    if ((e = ensure(P->counters, cap, P->fams.size() * 2)) != hipSuccess) return hip_fail(e, "plan counters");
+    P->counters_cap = (int)cap;
+    if ((e = hipMemset(P->counters, 0, cap * sizeof(int32_t))) != hipSuccess) return hip_fail(e, "plan counters");
+  }
+  unsigned char* a_setup = P->args_dev;
+  unsigned char* a_samp = a_setup + (size_t)nc * sizeof(SetupArgs);
+  unsigned char* a_est = a_samp + (size_t)nc * sizeof(SamplerArgs);
+  if ((e = hipMemcpy(P->items_dev, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(a_setup, sa.data(), nc * sizeof(SetupArgs), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(a_samp, ka.data(), nc * sizeof(SamplerArgs), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(a_est, ea.data(), nc * sizeof(EstArgs), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "plan table upload");
+  // Branches: the launches of a stage go to the least loaded of kPersBranches streams (longest
+  // first), so that a group's tail and the bandwidth-bound large-instance groups overlap other
+  // groups of the stage; the stages are joined (every event recorded in the capture is waited on
+  // inside it).
+  constexpr int kPersBranches = 4;
+  while ((int)P->branches.size() < kPersBranches) {
+    hipStream_t bs;
+    hipEvent_t ev;
+    if ((e = hipStreamCreateWithFlags(&bs, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream create");
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event create");
+    P->branches.push_back(bs);
+    P->joins.push_back(ev);
+  }
+  const int nstage = est ? 3 : 2;
+  while ((int)P->stage_ev.size() < nstage * (1 + kPersBranches)) {
+    hipEvent_t ev;
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event create");
+    P->stage_ev.push_back(ev);
+  }
+  const int nf = (int)P->fams.size();
+  if ((e = hipStreamBeginCapture(P->cap, hipStreamCaptureModeRelaxed)) != hipSuccess) return hip_fail(e, "begin capture");
+  dmala_status st = DMALA_OK;
+  int fi = 0;
+  for (int stage = 0; stage < nstage && st == DMALA_OK; ++stage) {
+    int n_st = 0;
+    while (fi + n_st < nf && P->fams[fi + n_st].stage == stage) ++n_st;
+    const int nbr = std::max(1, std::min(kPersBranches, n_st));
+    hipEvent_t* ev = P->stage_ev.data() + stage * (1 + kPersBranches);
+    (void)hipEventRecord(ev[0], P->cap);
+    for (int b = 0; b < nbr; ++b) (void)hipStreamWaitEvent(P->branches[b], ev[0], 0);
+    std::vector<double> load(nbr, 0.0);
+    for (int end = fi + n_st; fi < end && st == DMALA_OK; ++fi) {
+      const Family& f = P->fams[fi];
+      const int br = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[br] += f.cost;
+      hipStream_t bs = P->branches[br];
+      const int rep = f.cls[0];
+      Persist pp{};
+      pp.items = P->items_dev + f.item_off;
+      pp.n_items = f.n_items;
+      pp.lds_off = (int32_t)((f.lds + 15) & ~(size_t)15);
+      pp.counter = P->counters + 2 * fi;
+      pp.cls = f.stage == 0 ? (const void*)a_setup : (f.stage == 1 ? (const void*)a_samp : (const void*)a_est);
+      KernelCfg chk;
+      hipError_t le;
+      if (f.stage == 0) {
+        le = launch_setup(sa[rep], nullptr, nullptr, 0, &chk);
+        if (le == hipSuccess && chk.k == f.k) le = launch_setup(sa[rep], bs, &pp, f.grid);
+      } else if (f.stage == 1) {
+        le = launch_sampler(P->classes[rep].pl.sh, ka[rep], false, nullptr, nullptr, 0, &chk);
+        if (le == hipSuccess && chk.k == f.k) le = launch_sampler(P->classes[rep].pl.sh, ka[rep], false, bs, &pp, f.grid);
+      } else {
+        le = launch_estimate(ea[rep], nullptr, nullptr, 0, &chk);
+        if (le == hipSuccess && chk.k == f.k) le = launch_estimate(ea[rep], bs, &pp, f.grid);
+      }
+      if (le == hipSuccess && chk.k != f.k) le = hipErrorInvalidValue;
+      if (le != hipSuccess) st = hip_fail(le, "persistent launch");
+    }
+    for (int b = 0; b < nbr; ++b) {
+      (void)hipEventRecord(ev[1 + b], P->branches[b]);
+      (void)hipStreamWaitEvent(P->cap, ev[1 + b], 0);
+    }
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(P->cap, &g);
+  if (st != DMALA_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "end capture");
+  P->graph = g;
+  if ((e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0)) != hipSuccess) {
+    P->drop_graph();
+    return hip_fail(e, "graph instantiate");
+  }
+  P->persistent = true;
+  return DMALA_OK;
+}
+
 dmala_status build_graph(dmala_plan_s* P, const void* H, const void* y, const void* sigma2, const dmala_outputs* out,
                          unsigned char* ws) {
   hipError_t e;
@@ -118,6 +339,9 @@ dmala_status build_graph(dmala_plan_s* P, const void* H, const void* y, const vo
     P->joins.push_back(ev);
   }
   P->drop_graph();
+  P->persistent = false;
+  const dmala_status sp = build_graph_persistent(P, H, y, sigma2, out, ws);
+  if (sp != DMALA_ERR_UNSUPPORTED) return sp;
   dmala_outputs o = *out;
   for (int i = 0; i < 4; ++i) o.stage_events[i] = nullptr;
   if ((e = hipStreamBeginCapture(P->cap, hipStreamCaptureModeRelaxed)) != hipSuccess) return hip_fail(e, "begin capture");
@@ -377,6 +601,26 @@ dmala_status dmala_plan_class_info(dmala_plan P, int32_t k, dmala_shape* shape, 
   if (tile_config) *tile_config = c.pl.sh.cfg + 1;
   if (wg_chain_blocks) *wg_chain_blocks = c.pl.sh.cbw;
   if (tuned_ms) *tuned_ms = c.tuned_ms;
+  return DMALA_OK;
+}
+
+dmala_status dmala_plan_graph_info(dmala_plan P, int32_t* n_kernels, int32_t* persistent) {
+  if (!P || !n_kernels || !persistent) return fail(DMALA_ERR_ARG, "NULL argument");
+  *n_kernels = -1;
+  *persistent = -1;
+  if (!P->graph) return DMALA_OK;
+  size_t n = 0;
+  hipError_t e = hipGraphGetNodes(P->graph, nullptr, &n);
+  if (e != hipSuccess) return hip_fail(e, "graph nodes");
+  std::vector<hipGraphNode_t> nodes(n);
+  if (n && (e = hipGraphGetNodes(P->graph, nodes.data(), &n)) != hipSuccess) return hip_fail(e, "graph nodes");
+  int32_t k = 0;
+  for (auto nd : nodes) {
+    hipGraphNodeType t;
+    if (hipGraphNodeGetType(nd, &t) == hipSuccess && t == hipGraphNodeTypeKernel) ++k;
+  }
+  *n_kernels = k;
+  *persistent = P->persistent ? 1 : 0;
   return DMALA_OK;
 }
 

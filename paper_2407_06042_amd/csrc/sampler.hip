@@ -5,18 +5,18 @@
 
 namespace dmala {
 
-hipError_t launch_sampler_f64_naive(const Shape&, const SamplerArgs&, bool, hipStream_t);
-hipError_t launch_sampler_f64_pre(const Shape&, const SamplerArgs&, bool, hipStream_t);
-hipError_t launch_sampler_naive(const Shape&, const SamplerArgs&, bool, hipStream_t);
-hipError_t launch_sampler_f16x2(const Shape&, const SamplerArgs&, bool, hipStream_t);
-hipError_t launch_sampler_f16x1(const Shape&, const SamplerArgs&, bool, hipStream_t);
-hipError_t launch_sampler_bf16x1(const Shape&, const SamplerArgs&, bool, hipStream_t);
-hipError_t launch_sampler_lrn_f16x2(const Shape&, const SamplerArgs&, bool, hipStream_t);
-hipError_t launch_sampler_lrn_f16x1(const Shape&, const SamplerArgs&, bool, hipStream_t);
-hipError_t launch_sampler_lrn_bf16x1(const Shape&, const SamplerArgs&, bool, hipStream_t);
-hipError_t launch_sampler_mhgd_f64(const Shape&, const SamplerArgs&, bool, hipStream_t);
-hipError_t launch_sampler_mhgd_f16x2(const Shape&, const SamplerArgs&, bool, hipStream_t);
-hipError_t launch_sampler_mhgd_bf16x1(const Shape&, const SamplerArgs&, bool, hipStream_t);
+hipError_t launch_sampler_f64_naive(const Shape&, const SamplerArgs&, bool, hipStream_t, const Persist*, int, KernelCfg*);
+hipError_t launch_sampler_f64_pre(const Shape&, const SamplerArgs&, bool, hipStream_t, const Persist*, int, KernelCfg*);
+hipError_t launch_sampler_naive(const Shape&, const SamplerArgs&, bool, hipStream_t, const Persist*, int, KernelCfg*);
+hipError_t launch_sampler_f16x2(const Shape&, const SamplerArgs&, bool, hipStream_t, const Persist*, int, KernelCfg*);
+hipError_t launch_sampler_f16x1(const Shape&, const SamplerArgs&, bool, hipStream_t, const Persist*, int, KernelCfg*);
+hipError_t launch_sampler_bf16x1(const Shape&, const SamplerArgs&, bool, hipStream_t, const Persist*, int, KernelCfg*);
+hipError_t launch_sampler_lrn_f16x2(const Shape&, const SamplerArgs&, bool, hipStream_t, const Persist*, int, KernelCfg*);
+hipError_t launch_sampler_lrn_f16x1(const Shape&, const SamplerArgs&, bool, hipStream_t, const Persist*, int, KernelCfg*);
+hipError_t launch_sampler_lrn_bf16x1(const Shape&, const SamplerArgs&, bool, hipStream_t, const Persist*, int, KernelCfg*);
+hipError_t launch_sampler_mhgd_f64(const Shape&, const SamplerArgs&, bool, hipStream_t, const Persist*, int, KernelCfg*);
+hipError_t launch_sampler_mhgd_f16x2(const Shape&, const SamplerArgs&, bool, hipStream_t, const Persist*, int, KernelCfg*);
+hipError_t launch_sampler_mhgd_bf16x1(const Shape&, const SamplerArgs&, bool, hipStream_t, const Persist*, int, KernelCfg*);
 
 size_t sampler_lds_bytes(const Shape& sh) {
   if (sh.fp64) {
@@ -63,27 +63,28 @@ int sampler_default_cfg(const Shape& sh) {
   return -1;
 }
 
-hipError_t launch_sampler(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+hipError_t launch_sampler(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s, const Persist* p, int gn,
+                    KernelCfg* cfg) {
   if (sh.mhgd) {
-    if (sh.fp64) return launch_sampler_mhgd_f64(sh, a, eval, s);
-    if (sh.pm == PM_F16X2) return launch_sampler_mhgd_f16x2(sh, a, eval, s);
-    if (sh.pm == PM_BF16X1) return launch_sampler_mhgd_bf16x1(sh, a, eval, s);
+    if (sh.fp64) return launch_sampler_mhgd_f64(sh, a, eval, s, p, gn, cfg);
+    if (sh.pm == PM_F16X2) return launch_sampler_mhgd_f16x2(sh, a, eval, s, p, gn, cfg);
+    if (sh.pm == PM_BF16X1) return launch_sampler_mhgd_bf16x1(sh, a, eval, s, p, gn, cfg);
     return hipErrorInvalidValue;
   }
-  if (sh.fp64) return sh.pm == PM_NAIVE ? launch_sampler_f64_naive(sh, a, eval, s) : launch_sampler_f64_pre(sh, a, eval, s);
+  if (sh.fp64) return sh.pm == PM_NAIVE ? launch_sampler_f64_naive(sh, a, eval, s, p, gn, cfg) : launch_sampler_f64_pre(sh, a, eval, s, p, gn, cfg);
   if (sh.lrn) {
     switch (sh.pm) {
-      case PM_F16X2: return launch_sampler_lrn_f16x2(sh, a, eval, s);
-      case PM_F16X1: return launch_sampler_lrn_f16x1(sh, a, eval, s);
-      case PM_BF16X1: return launch_sampler_lrn_bf16x1(sh, a, eval, s);
+      case PM_F16X2: return launch_sampler_lrn_f16x2(sh, a, eval, s, p, gn, cfg);
+      case PM_F16X1: return launch_sampler_lrn_f16x1(sh, a, eval, s, p, gn, cfg);
+      case PM_BF16X1: return launch_sampler_lrn_bf16x1(sh, a, eval, s, p, gn, cfg);
     }
     return hipErrorInvalidValue;
   }
   switch (sh.pm) {
-    case PM_NAIVE: return launch_sampler_naive(sh, a, eval, s);
-    case PM_F16X2: return launch_sampler_f16x2(sh, a, eval, s);
-    case PM_F16X1: return launch_sampler_f16x1(sh, a, eval, s);
-    case PM_BF16X1: return launch_sampler_bf16x1(sh, a, eval, s);
+    case PM_NAIVE: return launch_sampler_naive(sh, a, eval, s, p, gn, cfg);
+    case PM_F16X2: return launch_sampler_f16x2(sh, a, eval, s, p, gn, cfg);
+    case PM_F16X1: return launch_sampler_f16x1(sh, a, eval, s, p, gn, cfg);
+    case PM_BF16X1: return launch_sampler_bf16x1(sh, a, eval, s, p, gn, cfg);
   }
   return hipErrorInvalidValue;
 }

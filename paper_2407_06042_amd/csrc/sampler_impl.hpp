@@ -317,7 +317,7 @@ struct Red {
 // packed matrices are read from the instance block in global memory (L2) instead
 // of being staged in LDS.
 template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false>
-__device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
+__device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int inst, const int cgy) {
   constexpr bool F64 = std::is_same<Real, double>::value;
   constexpr bool LRN = KND == 1;   // plain/learned kernel mixture
   constexpr bool MHG = KND == 2;   // the MHGD baseline (nearest-point candidate, MH without the proposal ratio)
@@ -339,7 +339,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   constexpr bool PIPE = !LRN && !F64 && WD == 1 && RTW <= 4;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
-  const int inst = blockIdx.x;                            // index within this launch (workspace slot)
+  // inst: index within the class (workspace slot); cgy: group of 16-chain blocks
   const int N = a.N, Npad = a.Npad;
   const unsigned char* blk = a.ws_inst + (size_t)inst * a.inst_stride;
   // the caller's instance index (RNG counter, per-instance outputs) and final-state offset
@@ -353,7 +353,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   // owning the same row tiles read the same matrix fragments at the same time)
   const int wd = WD > 1 ? wave % WD : 0;                  // dimension slice of this wave
   const int slot = WD > 1 ? wave / WD : 0;
-  const int cblock = WD > 1 ? blockIdx.y * (nwaves / WD) + slot : blockIdx.y * nwaves + wave;
+  const int cblock = WD > 1 ? cgy * (nwaves / WD) + slot : cgy * nwaves + wave;
   const int chain = cblock * 16 + cl;
   const bool live = chain < a.C;
   const int rt0 = wd * RTW;                               // first row tile owned
@@ -1151,22 +1151,46 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a) {
   }
 }
 
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false>
-__global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a) {
-  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX>(a);
+// Direct launch (PERS false): instance blockIdx.x, chain group blockIdx.y.  Persistent launch:
+// items from the list until it is exhausted, each with its class's arguments (a separate
+// instantiation, so that the direct kernels keep their registers).
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX, bool PERS>
+__device__ __forceinline__ void sampler_entry(const SamplerArgs& a, const Persist& p) {
+  if constexpr (!PERS) {
+    sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX>(a, blockIdx.x, blockIdx.y);
+  } else {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    for (;;) {
+      const int it = persist_take(p, smem);
+      if (it >= p.n_items) break;
+      const WorkItem w = p.items[it];
+      const SamplerArgs ca = ((const SamplerArgs*)p.cls)[__builtin_amdgcn_readfirstlane(w.cls)];
+      sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX>(ca, __builtin_amdgcn_readfirstlane(w.inst),
+                                                                 __builtin_amdgcn_readfirstlane(w.cg));
+    }
+    persist_done(p);
+  }
+}
+
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false,
+          bool PERS = false>
+__global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a, Persist p) {
+  sampler_entry<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX, PERS>(a, p);
 }
 
 // The same kernel held to two waves per SIMD (at most 256 registers): the
 // learned variant with two row tiles per wave fits without spilling.
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sampler_kernel_w2(SamplerArgs a) {
-  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX>(a);
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false,
+          bool PERS = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sampler_kernel_w2(SamplerArgs a, Persist p) {
+  sampler_entry<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX, PERS>(a, p);
 }
 
 // ... in 512-thread workgroups (two chain blocks of the four-wave layout).
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void sampler_kernel_w2_512(SamplerArgs a) {
-  sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX>(a);
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false,
+          bool PERS = false>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void sampler_kernel_w2_512(SamplerArgs a, Persist p) {
+  sampler_entry<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX, PERS>(a, p);
 }
 
 // LDS bytes of a configuration.
@@ -1198,7 +1222,8 @@ inline size_t sampler_cfg_lds(const Shape& sh, int rtw, int wd, bool mg, int wav
 }
 
 template <typename Real, int RTW, int WD, bool MG, int Q, int PM, int WIN, int KND = 0, bool CX = false>
-hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s, const Persist* p, int gn,
+                    KernelCfg* cfg) {
   constexpr bool LRN = KND == 1;
   const int chain_blocks = sh.Cpad / 16;
   int waves, gy;
@@ -1222,8 +1247,24 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
   constexpr bool kW2Eval = LRN && RTW == 2;
   constexpr bool kW2 = kW2Eval || (!LRN && RTW == 4 && !std::is_same<Real, double>::value && (WD < 4 || (WIN > 0 && PM != PM_NAIVE)));
   constexpr bool kW2Alone = !LRN && RTW == 4 && !std::is_same<Real, double>::value && WD == 4 && WIN == 0 && PM != PM_NAIVE;
-  void (*k)(SamplerArgs);
-  if (eval) {
+  void (*k)(SamplerArgs, Persist);
+  // persistent instantiations (plans): the plain float chains
+  constexpr bool kPersOK = KND == 0 && !std::is_same<Real, double>::value;
+  const bool pers = (p != nullptr || cfg != nullptr) && !eval;
+  if (pers) {
+    if constexpr (kPersOK) {
+      if (waves > 4) {
+        if constexpr (kW2 && WD == 4) k = sampler_kernel_w2_512<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX, true>;
+        else return hipErrorInvalidConfiguration;
+      } else if constexpr (kW2) {
+        k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX, true>;
+      } else {
+        k = sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX, true>;
+      }
+    } else {
+      return hipErrorNotSupported;
+    }
+  } else if (eval) {
     if constexpr (kW2Eval) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, true, WIN, KND, CX>;
     else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN, KND, CX>;
   } else if (waves > 4) {
@@ -1235,26 +1276,38 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
                                               : sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>;
     else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>;
   }
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (cfg) {
+    cfg->k = (const void*)k;
+    cfg->threads = 64 * waves;
+    cfg->lds = lds;
+    cfg->gx = (int)grid.x;
+    cfg->gy = (int)grid.y;
+    return hipSuccess;
+  }
+  // a persistent launch keeps one more aligned word after the body's LDS (the item broadcast)
+  const size_t lds_run = p ? ((p->lds_off + 4 + 15) & ~(size_t)15) : lds;
+  if (lds_run > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_run);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k, grid, dim3(64 * waves), lds, s, a);
+  if (p) hipLaunchKernelGGL(k, dim3(gn), dim3(64 * waves), lds_run, s, a, *p);
+  else hipLaunchKernelGGL(k, grid, dim3(64 * waves), lds, s, a, Persist{});
   return hipGetLastError();
 }
 
 template <typename Real, int RTW, int WD, bool MG, int PM, bool CX = false>
-hipError_t launch_q(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+hipError_t launch_q(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s, const Persist* p, int gn,
+                    KernelCfg* cfg) {
   // the 3-level window is used only for Q >= 8 (it would not be smaller otherwise)
   constexpr int WN = std::is_same<Real, double>::value ? 0 : 3;   // the float path only
   const bool win = WN > 0 && sh.win == 3;
   switch (sh.Q) {
-    case 2: return launch_t<Real, RTW, WD, MG, 2, PM, 0, 0, CX>(sh, a, eval, s);
-    case 4: return launch_t<Real, RTW, WD, MG, 4, PM, 0, 0, CX>(sh, a, eval, s);
-    case 8: return win ? launch_t<Real, RTW, WD, MG, 8, PM, WN, 0, CX>(sh, a, eval, s)
-                       : launch_t<Real, RTW, WD, MG, 8, PM, 0, 0, CX>(sh, a, eval, s);
-    case 16: return win ? launch_t<Real, RTW, WD, MG, 16, PM, WN, 0, CX>(sh, a, eval, s)
-                        : launch_t<Real, RTW, WD, MG, 16, PM, 0, 0, CX>(sh, a, eval, s);
+    case 2: return launch_t<Real, RTW, WD, MG, 2, PM, 0, 0, CX>(sh, a, eval, s, p, gn, cfg);
+    case 4: return launch_t<Real, RTW, WD, MG, 4, PM, 0, 0, CX>(sh, a, eval, s, p, gn, cfg);
+    case 8: return win ? launch_t<Real, RTW, WD, MG, 8, PM, WN, 0, CX>(sh, a, eval, s, p, gn, cfg)
+                       : launch_t<Real, RTW, WD, MG, 8, PM, 0, 0, CX>(sh, a, eval, s, p, gn, cfg);
+    case 16: return win ? launch_t<Real, RTW, WD, MG, 16, PM, WN, 0, CX>(sh, a, eval, s, p, gn, cfg)
+                        : launch_t<Real, RTW, WD, MG, 16, PM, 0, 0, CX>(sh, a, eval, s, p, gn, cfg);
   }
   return hipErrorInvalidValue;
 }
@@ -1264,22 +1317,23 @@ hipError_t launch_q(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
 //   cfg 3: RT 8 as 2 waves x 4, L2     cfg 4: RT 16 as 4 waves x 4, L2
 //   cfg 7, 8: cfg 3, 4 with the matrices stored as complex planes
 template <typename Real, int PM>
-hipError_t launch_rt(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+hipError_t launch_rt(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s, const Persist* p, int gn,
+                    KernelCfg* cfg) {
   if constexpr (std::is_same<Real, double>::value) {
     switch (sh.RT) {
-      case 2: return launch_q<Real, 2, 1, false, PM>(sh, a, eval, s);
-      case 4: return launch_q<Real, 4, 1, false, PM>(sh, a, eval, s);
+      case 2: return launch_q<Real, 2, 1, false, PM>(sh, a, eval, s, p, gn, cfg);
+      case 4: return launch_q<Real, 4, 1, false, PM>(sh, a, eval, s, p, gn, cfg);
     }
     return hipErrorInvalidValue;
   } else {
     switch (sh.cfg) {
-      case 0: return launch_q<Real, 2, 1, false, PM>(sh, a, eval, s);
-      case 1: return launch_q<Real, 4, 1, false, PM>(sh, a, eval, s);
-      case 2: return launch_q<Real, 8, 1, false, PM>(sh, a, eval, s);
-      case 3: return launch_q<Real, 4, 2, true, PM>(sh, a, eval, s);
-      case 4: return launch_q<Real, 4, 4, true, PM>(sh, a, eval, s);
-      case 7: return launch_q<Real, 4, 2, true, PM, true>(sh, a, eval, s);
-      case 8: return launch_q<Real, 4, 4, true, PM, true>(sh, a, eval, s);
+      case 0: return launch_q<Real, 2, 1, false, PM>(sh, a, eval, s, p, gn, cfg);
+      case 1: return launch_q<Real, 4, 1, false, PM>(sh, a, eval, s, p, gn, cfg);
+      case 2: return launch_q<Real, 8, 1, false, PM>(sh, a, eval, s, p, gn, cfg);
+      case 3: return launch_q<Real, 4, 2, true, PM>(sh, a, eval, s, p, gn, cfg);
+      case 4: return launch_q<Real, 4, 4, true, PM>(sh, a, eval, s, p, gn, cfg);
+      case 7: return launch_q<Real, 4, 2, true, PM, true>(sh, a, eval, s, p, gn, cfg);
+      case 8: return launch_q<Real, 4, 4, true, PM, true>(sh, a, eval, s, p, gn, cfg);
     }
     return hipErrorInvalidValue;
   }
@@ -1287,32 +1341,34 @@ hipError_t launch_rt(const Shape& sh, const SamplerArgs& a, bool eval, hipStream
 
 // The MHGD baseline on the plain layouts (every Q weighted directly: there is no window).
 template <typename Real, int RTW, int WD, bool MG, int PM, bool CX = false>
-hipError_t launch_q_mhg(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+hipError_t launch_q_mhg(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s, const Persist* p, int gn,
+                    KernelCfg* cfg) {
   switch (sh.Q) {
-    case 2: return launch_t<Real, RTW, WD, MG, 2, PM, 0, 2, CX>(sh, a, eval, s);
-    case 4: return launch_t<Real, RTW, WD, MG, 4, PM, 0, 2, CX>(sh, a, eval, s);
-    case 8: return launch_t<Real, RTW, WD, MG, 8, PM, 0, 2, CX>(sh, a, eval, s);
-    case 16: return launch_t<Real, RTW, WD, MG, 16, PM, 0, 2, CX>(sh, a, eval, s);
+    case 2: return launch_t<Real, RTW, WD, MG, 2, PM, 0, 2, CX>(sh, a, eval, s, p, gn, cfg);
+    case 4: return launch_t<Real, RTW, WD, MG, 4, PM, 0, 2, CX>(sh, a, eval, s, p, gn, cfg);
+    case 8: return launch_t<Real, RTW, WD, MG, 8, PM, 0, 2, CX>(sh, a, eval, s, p, gn, cfg);
+    case 16: return launch_t<Real, RTW, WD, MG, 16, PM, 0, 2, CX>(sh, a, eval, s, p, gn, cfg);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename Real, int PM>
-hipError_t launch_rt_mhg(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+hipError_t launch_rt_mhg(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s, const Persist* p, int gn,
+                    KernelCfg* cfg) {
   if constexpr (std::is_same<Real, double>::value) {
     switch (sh.RT) {
-      case 2: return launch_q_mhg<Real, 2, 1, false, PM>(sh, a, eval, s);
-      case 4: return launch_q_mhg<Real, 4, 1, false, PM>(sh, a, eval, s);
+      case 2: return launch_q_mhg<Real, 2, 1, false, PM>(sh, a, eval, s, p, gn, cfg);
+      case 4: return launch_q_mhg<Real, 4, 1, false, PM>(sh, a, eval, s, p, gn, cfg);
     }
   } else {
     switch (sh.cfg) {
-      case 0: return launch_q_mhg<Real, 2, 1, false, PM>(sh, a, eval, s);
-      case 1: return launch_q_mhg<Real, 4, 1, false, PM>(sh, a, eval, s);
-      case 2: return launch_q_mhg<Real, 8, 1, false, PM>(sh, a, eval, s);
-      case 3: return launch_q_mhg<Real, 4, 2, true, PM>(sh, a, eval, s);
-      case 4: return launch_q_mhg<Real, 4, 4, true, PM>(sh, a, eval, s);
-      case 7: return launch_q_mhg<Real, 4, 2, true, PM, true>(sh, a, eval, s);
-      case 8: return launch_q_mhg<Real, 4, 4, true, PM, true>(sh, a, eval, s);
+      case 0: return launch_q_mhg<Real, 2, 1, false, PM>(sh, a, eval, s, p, gn, cfg);
+      case 1: return launch_q_mhg<Real, 4, 1, false, PM>(sh, a, eval, s, p, gn, cfg);
+      case 2: return launch_q_mhg<Real, 8, 1, false, PM>(sh, a, eval, s, p, gn, cfg);
+      case 3: return launch_q_mhg<Real, 4, 2, true, PM>(sh, a, eval, s, p, gn, cfg);
+      case 4: return launch_q_mhg<Real, 4, 4, true, PM>(sh, a, eval, s, p, gn, cfg);
+      case 7: return launch_q_mhg<Real, 4, 2, true, PM, true>(sh, a, eval, s, p, gn, cfg);
+      case 8: return launch_q_mhg<Real, 4, 4, true, PM, true>(sh, a, eval, s, p, gn, cfg);
     }
   }
   return hipErrorInvalidValue;
@@ -1322,25 +1378,27 @@ hipError_t launch_rt_mhg(const Shape& sh, const SamplerArgs& a, bool eval, hipSt
 // two-tile dimension splits 5 (64 dims, 2 waves, LDS matrices) and 6 (128 dims, 4 waves, L2), which
 // keep the network, the two cached proposals and the state within 256 registers.
 template <int RTW, int WD, bool MG, int PM>
-hipError_t launch_q_lrn(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+hipError_t launch_q_lrn(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s, const Persist* p, int gn,
+                    KernelCfg* cfg) {
   switch (sh.Q) {
-    case 2: return launch_t<float, RTW, WD, MG, 2, PM, 0, 1>(sh, a, eval, s);
-    case 4: return launch_t<float, RTW, WD, MG, 4, PM, 0, 1>(sh, a, eval, s);
-    case 8: return launch_t<float, RTW, WD, MG, 8, PM, 0, 1>(sh, a, eval, s);
-    case 16: return launch_t<float, RTW, WD, MG, 16, PM, 0, 1>(sh, a, eval, s);
+    case 2: return launch_t<float, RTW, WD, MG, 2, PM, 0, 1>(sh, a, eval, s, p, gn, cfg);
+    case 4: return launch_t<float, RTW, WD, MG, 4, PM, 0, 1>(sh, a, eval, s, p, gn, cfg);
+    case 8: return launch_t<float, RTW, WD, MG, 8, PM, 0, 1>(sh, a, eval, s, p, gn, cfg);
+    case 16: return launch_t<float, RTW, WD, MG, 16, PM, 0, 1>(sh, a, eval, s, p, gn, cfg);
   }
   return hipErrorInvalidValue;
 }
 
 template <int PM>
-hipError_t launch_rt_lrn(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
+hipError_t launch_rt_lrn(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s, const Persist* p, int gn,
+                    KernelCfg* cfg) {
   switch (sh.cfg) {
-    case 0: return launch_q_lrn<2, 1, false, PM>(sh, a, eval, s);
-    case 1: return launch_q_lrn<4, 1, false, PM>(sh, a, eval, s);
-    case 3: return launch_q_lrn<4, 2, true, PM>(sh, a, eval, s);
-    case 4: return launch_q_lrn<4, 4, true, PM>(sh, a, eval, s);
-    case 5: return launch_q_lrn<2, 2, false, PM>(sh, a, eval, s);
-    case 6: return launch_q_lrn<2, 4, true, PM>(sh, a, eval, s);
+    case 0: return launch_q_lrn<2, 1, false, PM>(sh, a, eval, s, p, gn, cfg);
+    case 1: return launch_q_lrn<4, 1, false, PM>(sh, a, eval, s, p, gn, cfg);
+    case 3: return launch_q_lrn<4, 2, true, PM>(sh, a, eval, s, p, gn, cfg);
+    case 4: return launch_q_lrn<4, 4, true, PM>(sh, a, eval, s, p, gn, cfg);
+    case 5: return launch_q_lrn<2, 2, false, PM>(sh, a, eval, s, p, gn, cfg);
+    case 6: return launch_q_lrn<2, 4, true, PM>(sh, a, eval, s, p, gn, cfg);
   }
   return hipErrorInvalidValue;
 }

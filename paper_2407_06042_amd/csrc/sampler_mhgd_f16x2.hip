@@ -2,7 +2,8 @@
 #include "sampler_impl.hpp"
 
 namespace dmala {
-hipError_t launch_sampler_mhgd_f16x2(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s) {
-  return launch_rt_mhg<float, PM_F16X2>(sh, a, eval, s);
+hipError_t launch_sampler_mhgd_f16x2(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s, const Persist* p, int gn,
+                    KernelCfg* cfg) {
+  return launch_rt_mhg<float, PM_F16X2>(sh, a, eval, s, p, gn, cfg);
 }
 }  // namespace dmala

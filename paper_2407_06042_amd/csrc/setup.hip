@@ -164,9 +164,8 @@ __device__ void pack_dense(const cd* X, int ld, double c, int N, int Npad, doubl
 // matrix in this instance's slice of the workspace.
 // RMAX: rows of the working matrix the Gauss-Jordan register layout covers (threads per row BS / RMAX).
 template <typename TIn, bool WGLOB, int BS, int RMAX>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RMAX <= 32 ? 5 : (BS == 256 ? 2 : 1))))
-void setup_kernel(SetupArgs a) {
-  const int b = blockIdx.x, tid = threadIdx.x, nt = a.nt, nr = a.nr, N = a.N, Npad = a.Npad;
+__device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
+  const int tid = threadIdx.x, nt = a.nt, nr = a.nr, N = a.N, Npad = a.Npad;
   const int ld = nt + 1;  // padded leading dimension of the matrices (no LDS bank conflicts on columns)
   const InstDesc dsc = inst_desc(a.desc, b, nt, nr, a.Q * a.Q, 1);
   const TIn* Hg = (const TIn*)a.H + 2 * dsc.h_off;
@@ -489,7 +488,9 @@ void setup_kernel(SetupArgs a) {
 #pragma unroll
       for (int c = 0; c < S; ++c) {
         const int j = tj + T * c;
-        bp = cadd(bp, cmul(w[ra][c], zc[c]));
+        // register entries of columns j >= nt hold whatever the sweep read past the row
+        // vectors (possibly not finite): they are left out, not multiplied by zero
+        if (j < nt) bp = cadd(bp, cmul(w[ra][c], zc[c]));
         if (i < nt && j < nt) W[i * ld + j] = {(j == i ? 1.0 : 0.0) - gamma * w[ra][c].re, -gamma * w[ra][c].im};
       }
 #pragma unroll
@@ -535,21 +536,54 @@ void setup_kernel(SetupArgs a) {
   }
 }
 
+// Direct launch (PERS false): instance blockIdx.x.  Persistent launch: items from the list, each
+// with its class's arguments.
+template <typename TIn, bool WGLOB, int BS, int RMAX, bool PERS = false>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RMAX <= 32 ? 5 : (BS == 256 ? 2 : 1))))
+void setup_kernel(SetupArgs a, Persist p) {
+  if constexpr (!PERS) {
+    setup_body<TIn, WGLOB, BS, RMAX>(a, blockIdx.x);
+  } else {
+    extern __shared__ double smem_setup[];
+    for (;;) {
+      const int it = persist_take(p, (unsigned char*)smem_setup);
+      if (it >= p.n_items) break;
+      const WorkItem w = p.items[it];
+      const SetupArgs ca = ((const SetupArgs*)p.cls)[__builtin_amdgcn_readfirstlane(w.cls)];
+      setup_body<TIn, WGLOB, BS, RMAX>(ca, __builtin_amdgcn_readfirstlane(w.inst));
+    }
+    persist_done(p);
+  }
+}
+
 bool setup_w_global(int nt) { return nt > 64; }
 
 template <int BS, bool WG, int RMAX>
-hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s) {
+hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s, const Persist* p, int gn, KernelCfg* cfg) {
   if (WG != setup_w_global(a.nt) || a.nt > RMAX) return hipErrorInvalidValue;
   constexpr int kIC = RMAX <= 32 ? 16 : 32;
   const bool alias = !WG && RMAX > 32;   // the staging buffer is the working matrix's first rows
   const size_t lds = (size_t)((WG ? 0 : a.nt * (a.nt + 1)) + 10 * a.nt) * sizeof(cd) + BS * sizeof(double) +
                      (alias ? 0 : (kIC * (size_t)(a.nt + 1) + 32) * sizeof(cd));
-  void (*k)(SetupArgs) = a.fp64 ? setup_kernel<double, WG, BS, RMAX> : setup_kernel<float, WG, BS, RMAX>;
-  if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  void (*k)(SetupArgs, Persist);
+  if (p || cfg) k = a.fp64 ? setup_kernel<double, WG, BS, RMAX, true> : setup_kernel<float, WG, BS, RMAX, true>;
+  else k = a.fp64 ? setup_kernel<double, WG, BS, RMAX> : setup_kernel<float, WG, BS, RMAX>;
+  if (cfg) {
+    cfg->k = (const void*)k;
+    cfg->threads = BS;
+    cfg->lds = lds;
+    cfg->gx = a.n_inst;
+    cfg->gy = 1;
+    return hipSuccess;
+  }
+  // a persistent launch keeps one more aligned word after the body's LDS (the item broadcast)
+  const size_t lds_run = p ? ((p->lds_off + 4 + 15) & ~(size_t)15) : lds;
+  if (lds_run > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_run);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k, dim3(a.n_inst), dim3(BS), lds, s, a);
+  if (p) hipLaunchKernelGGL(k, dim3(gn), dim3(BS), lds_run, s, a, *p);
+  else hipLaunchKernelGGL(k, dim3(a.n_inst), dim3(BS), lds, s, a, Persist{});
   return hipGetLastError();
 }
 
@@ -558,9 +592,9 @@ hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s) {
 // workgroups per CU whose latency-bound Gauss-Jordan steps overlap.  Larger instances keep the
 // working matrix in the workspace between phases (in registers during the sweep), so that LDS
 // holds only the staging buffers: 1024 threads.
-hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
-  if (a.nt <= 32) return launch_setup_bs<256, false, 32>(a, s);
-  return a.nt <= 64 ? launch_setup_bs<256, false, 64>(a, s) : launch_setup_bs<1024, true, 128>(a, s);
+hipError_t launch_setup(const SetupArgs& a, hipStream_t s, const Persist* p, int gn, KernelCfg* cfg) {
+  if (a.nt <= 32) return launch_setup_bs<256, false, 32>(a, s, p, gn, cfg);
+  return a.nt <= 64 ? launch_setup_bs<256, false, 64>(a, s, p, gn, cfg) : launch_setup_bs<1024, true, 128>(a, s, p, gn, cfg);
 }
 
 }  // namespace dmala

@@ -109,6 +109,10 @@ def test_plan_graph_replays_are_identical():
     for rep in range(4):
         res = plan(H, y, sig)
         torch.cuda.synchronize()
+        if rep == 0:
+            nk, pers = plan.graph_info()
+            print("plan graph: %d kernel nodes, persistent %d, %d classes" % (nk, pers, len(plan.classes())), flush=True)
+            assert pers == 1 and 3 <= nk < 3 * len(plan.classes())
         cur = {k: v.cpu().numpy().copy() for k, v in res.items()}
         # eager work on the same stream between replays
         z = torch.randn(1 << 20, device="cuda").sum()
@@ -121,6 +125,31 @@ def test_plan_graph_replays_are_identical():
         else:
             for k in ref:
                 np.testing.assert_array_equal(cur[k], ref[k])
+
+
+def test_plan_float64_takes_the_branch_graph():
+    """float64 chains have no persistent kernels: the plan runs per-class kernels on branches, and each
+    instance still equals a uniform dmala_detect of it (random counter at its index)."""
+    import torch
+    import paper_2407_06042_amd as dm
+    shapes = [(4, 4, 16), (8, 8, 64), (4, 4, 16), (2, 4, 4)]
+    C, T = 16, 15
+    Hs, ys, s2, xs = _uneven(shapes, np.full(len(shapes), 15.0), 3)
+    Hd = [h.astype(np.complex128) for h in Hs]
+    yd = [v.astype(np.complex128) for v in ys]
+    H, y, sig = dm.pack_uneven(Hd, yd, s2.astype(np.float64), precision="fp64")
+    plan = dm.Plan(shapes, C, T, 17, precision="fp64", outputs=("symbols", "final_state"))
+    out = {k: v.cpu().numpy() for k, v in plan(H, y, sig).items()}
+    torch.cuda.synchronize()
+    nk, pers = plan.graph_info()
+    assert pers == 0 and nk == 3 * len(plan.classes())
+    off = _offsets(shapes, C)
+    for b, (nt, nr, M) in enumerate(shapes):
+        Hc, yc, sc = dm.device_inputs(Hd[b][None], yd[b][None], s2[b:b + 1].astype(np.float64), "fp64")
+        u = dm.Detector(1, nt, nr, M, C, T, 17, "fp64", outputs=("symbols", "final_state"), counter_base=b)(Hc, yc, sc)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(u["final_state"].cpu().numpy().reshape(-1), out["final_state"][off["fs"][b]:off["fs"][b + 1]])
+        np.testing.assert_array_equal(u["symbols"].cpu().numpy().reshape(-1), out["symbols"][off["sym"][b]:off["sym"][b + 1]])
 
 
 def test_plan_autotune_and_cache(tmp_path):
@@ -176,8 +205,26 @@ def test_uneven_full_size_sampled_parity():
         ser[prec] = float(np.mean(out["symbols"] != truth))
         if prec != "fp32":
             continue
+        nk, pers = plan.graph_info()
+        print("uneven plan graph: %d kernel nodes (persistent %d) for %d classes" % (nk, pers, len(plan.classes())),
+              flush=True)
+        assert pers == 1 and nk <= 36
         th = out["trace_hash"].view(np.uint32).reshape(len(shapes), C, T)
         off = _offsets(shapes, C)
+        # every class: its first instance alone through dmala_detect (random counter at its index), bit for bit
+        for cls in sorted(set(shapes)):
+            b = shapes.index(cls)
+            nt_, nr_, M_ = cls
+            Hc, yc, sc = dm.device_inputs(Hs[b][None], ys[b][None], s2[b:b + 1])
+            u = dm.Detector(1, nt_, nr_, M_, C, T, seed, outputs=("symbols", "final_state", "accept_count"),
+                            counter_base=b)(Hc, yc, sc)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(u["final_state"].cpu().numpy().reshape(-1),
+                                          out["final_state"][off["fs"][b]:off["fs"][b + 1]], err_msg=str(cls))
+            np.testing.assert_array_equal(u["accept_count"].cpu().numpy().reshape(-1),
+                                          out["accept_count"][b * C:(b + 1) * C], err_msg=str(cls))
+            np.testing.assert_array_equal(u["symbols"].cpu().numpy().reshape(-1),
+                                          out["symbols"][off["sym"][b]:off["sym"][b + 1]], err_msg=str(cls))
         for nt in (16, 32, 64, 128):
             picks = [i for i, s in enumerate(shapes) if s[0] == nt][:2]
             n_id_nt = 0
