@@ -192,7 +192,7 @@ def mmse_ser(b):
 
 # ---------------------------------------------------------------- the learned proposal
 
-def train_network(dm, torch, sources, data):
+def train_network(dm, torch, sources, data, keep_rows=False):
     """Train the per-antenna network on the method's own chains: sources = [(batch, C, feature_iters, seed)],
     targets = the same chain 20 transitions later (learned.collect)."""
     from paper_2407_06042_amd import learned as L
@@ -210,7 +210,67 @@ def train_network(dm, torch, sources, data):
     hist = L.train(w, rows, tg, 400, batch=65536, lr=3e-3, lr_final=2e-4, log_every=399)
     ev.record(1)
     torch.cuda.synchronize()
-    return w, dict(ms=ev.elapsed_ms(0, 1), rows=int(rows.shape[0]), steps=400, final_loss=hist[-1][1], data=data)
+    info = dict(ms=ev.elapsed_ms(0, 1), rows=int(rows.shape[0]), steps=400, final_loss=hist[-1][1], data=data)
+    if keep_rows:
+        return w, info, rows, tg
+    return w, info
+
+
+def head_comparison(torch, rows, tg, steps=400, batch=65536, seed=5):
+    """Held-out cross-entropy (nats per antenna) of three proposals on the same rows (one constellation):
+    the plain preconditioned one; the learned family (4 outputs: per-axis centre offset and log2 precision
+    factor, clamped to [-4, 4]); and a head with one logit per QAM point added to the plain proposal's
+    (M outputs).  Same 7 -> 64 -> 64 ReLU trunk, zero-initialised output layer, Adam with the library's
+    schedule (3e-3 -> 2e-4), fp32 -- a torch model of both heads, used only for this comparison."""
+    g = torch.Generator(device=rows.device)
+    g.manual_seed(seed)
+    Q = int(rows[0, 10].item())
+    perm = torch.randperm(rows.shape[0], device=rows.device, generator=g)
+    n_ho = rows.shape[0] // 5
+    ho, trn = perm[:n_ho], perm[n_ho:]
+    j = torch.arange(Q, device=rows.device, dtype=torch.float32)
+
+    def axis_lq(mu, kap):
+        return torch.log_softmax(-kap[:, None] * (j[None, :] - mu[:, None]) ** 2, dim=-1)
+
+    def ce(kind, net, idx):
+        X, mu, kap, t = rows[idx, :7], rows[idx, 7:9], rows[idx, 9], tg[idx].long()
+        if kind == "plain":
+            return -(axis_lq(mu[:, 0], kap).gather(1, t[:, :1]) + axis_lq(mu[:, 1], kap).gather(1, t[:, 1:2])).mean()
+        out = net(X)
+        if kind == "family":
+            b = out[:, 2:4].clamp(-4.0, 4.0)
+            l0 = axis_lq(mu[:, 0] + out[:, 0], kap * torch.exp2(b[:, 0])).gather(1, t[:, :1])
+            l1 = axis_lq(mu[:, 1] + out[:, 1], kap * torch.exp2(b[:, 1])).gather(1, t[:, 1:2])
+            return -(l0 + l1).mean()
+        base = (-kap[:, None] * (j[None, :] - mu[:, :1]) ** 2)[:, :, None] + \
+               (-kap[:, None] * (j[None, :] - mu[:, 1:2]) ** 2)[:, None, :]
+        lq = torch.log_softmax(base.reshape(-1, Q * Q) + out, dim=-1)
+        return -lq.gather(1, (t[:, 0] * Q + t[:, 1])[:, None]).mean()
+
+    res = dict(rows_train=int(trn.numel()), rows_held_out=int(n_ho), Q=Q, steps=steps, batch=batch)
+    with torch.no_grad():
+        res["plain_xent"] = float(ce("plain", None, ho))
+    for kind, n_out in (("family", 4), ("m_logits", Q * Q)):
+        torch.manual_seed(seed)
+        net = torch.nn.Sequential(torch.nn.Linear(7, 64), torch.nn.ReLU(), torch.nn.Linear(64, 64), torch.nn.ReLU(),
+                                  torch.nn.Linear(64, n_out)).to(rows.device)
+        torch.nn.init.zeros_(net[4].weight)
+        torch.nn.init.zeros_(net[4].bias)
+        opt = torch.optim.Adam(net.parameters(), lr=3e-3)
+        for s_ in range(steps):
+            for pg in opt.param_groups:
+                pg["lr"] = 3e-3 * (2e-4 / 3e-3) ** (s_ / max(1, steps - 1))
+            idx = trn[torch.randint(0, trn.numel(), (batch,), device=rows.device, generator=g)]
+            loss = ce(kind, net, idx)
+            opt.zero_grad()
+            loss.backward()
+            opt.step()
+        with torch.no_grad():
+            res[kind + "_xent"] = float(ce(kind, net, ho))
+    res["network_macs_per_antenna"] = dict(family=7 * 64 + 64 * 64 + 64 * 4, m_logits=7 * 64 + 64 * 64 + 64 * Q * Q)
+    res["draw_exponentials_per_antenna"] = dict(family=4, m_logits=Q * Q)
+    return res
 
 
 def matched_ser_sweep(dm, torch, b, w, sweep, ref_T, reps):
@@ -415,17 +475,21 @@ def main():
         b8 = W.make_batch(8, 8, 64, np.repeat([22.0, 24.0, 26.0], 4096), 3 * 4096, seed=8, cfg_id=8).as_precision(np.float32)
         # a network trained on this size's own chains (other realisations), beside the one trained on
         # the large systems
-        w8, training8 = train_network(
+        w8, training8, rows8, tg8 = train_network(
             dm, torch, [(W.make_batch(8, 8, 64, np.repeat([22.0, 24.0, 26.0], 1024), 3 * 1024, seed=88, cfg_id=8),
                          32, [0, 5, 10, 20, 40, 80], 13)],
-            "8x8 64-QAM at 22/24/26 dB (3072 other problems) chains, targets = the same chain 20 transitions later")
+            "8x8 64-QAM at 22/24/26 dB (3072 other problems) chains, targets = the same chain 20 transitions later",
+            keep_rows=True)
+        progress("head comparison")
+        heads = head_comparison(torch, rows8, tg8)
+        del rows8, tg8
         runs8, m8, ref8 = matched_ser_sweep(dm, torch, b8, w8, [("fp32", (25, 50, 100, 200)), ("bf16", (25, 50, 100)),
                                                                 ("bf16+learned", (10, 25, 50, 100))], 100, 3)
         runs8x, m8x, _ = matched_ser_sweep(dm, torch, b8, w, [("fp32", (100,)), ("bf16+learned", (25, 50, 100))],
                                            100, 3)
         works = dict(workload="8x8 64-QAM i.i.d. Rayleigh CN(0,1/Nr), SNR 22/24/26 dB x 4096 (12288 problems), "
                               "32 chains", reference="fp32 plain, 100 transitions", mmse_ser=mmse_ser(b8),
-                     training=training8, runs=runs8, matched=m8,
+                     training=training8, runs=runs8, matched=m8, head_comparison=heads,
                      large_system_network=dict(runs=[r for r in runs8x if r["form"] != "fp32"], matched=m8x))
     else:
         works = None
