@@ -11,8 +11,10 @@
 // The training network is float32 without rounding.  Three kernels:
 //   rows:    one thread per row: forward, loss, output gradient, backward to
 //            the hidden layers; stores the activations and deltas it needs;
-//   partial: per chunk of rows, one thread per parameter sums its gradient
-//            terms (and the loss) in row order;
+//   partial: per chunk of 256 rows, one wavefront forms the weight gradients
+//            dW = sum_r delta_r a_r^T on the matrix cores (float32 16x16x4
+//            MFMAs, the rows as the K dimension; a column of ones in the B
+//            operand gives the biases) and sums the loss;
 //   adam:    one thread per parameter sums the chunks in order and updates
 //            the parameter and the two moment estimates (Adam, Kingma & Ba).
 // No atomics: the result does not depend on scheduling.
@@ -53,7 +55,7 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float* __restric
 // dout[4], loss[1], 1 pad.
 constexpr int kRecA0 = 0, kRecA1 = 8, kRecA2 = 72, kRecD1 = 136, kRecD2 = 200, kRecDo = 264, kRecL = 268;
 constexpr int kRec = 272;
-constexpr int kChunk = 512;  // rows per partial sum
+constexpr int kChunk = 256;  // rows per partial sum (one wavefront)
 
 __global__ __launch_bounds__(256) void mlp_rows_kernel(const float* __restrict__ w, const float* __restrict__ rows,
                                                        const int32_t* __restrict__ tgt, int n, float inv_n,
@@ -142,29 +144,78 @@ __global__ __launch_bounds__(256) void mlp_rows_kernel(const float* __restrict__
   }
 }
 
-// Gradient term of parameter p for one record: (delta offset, activation offset) or bias (act < 0).
-__device__ __forceinline__ void param_terms(int p, int& dlt, int& act) {
-  if (p < kOffB1) { const int j = p / kMlpIn, i = p % kMlpIn; dlt = kRecD1 + j; act = kRecA0 + i; }
-  else if (p < kOffW2) { dlt = kRecD1 + (p - kOffB1); act = -1; }
-  else if (p < kOffB2) { const int q = p - kOffW2; dlt = kRecD2 + q / kMlpHid; act = kRecA1 + q % kMlpHid; }
-  else if (p < kOffW3) { dlt = kRecD2 + (p - kOffB2); act = -1; }
-  else if (p < kOffB3) { const int q = p - kOffW3; dlt = kRecDo + q / kMlpHid; act = kRecA2 + q % kMlpHid; }
-  else if (p < kMlpParams) { dlt = kRecDo + (p - kOffB3); act = -1; }
-  else { dlt = kRecL; act = -1; }  // p == kMlpParams: the loss
-}
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void mlp_partial_kernel(const float* __restrict__ rec, int n, float* __restrict__ part) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p > kMlpParams) return;
-  int dlt, act;
-  param_terms(p, dlt, act);
-  const int r0 = blockIdx.y * kChunk, r1 = min(n, r0 + kChunk);
-  float s = 0.f;
-  for (int r = r0; r < r1; ++r) {
-    const float* o = rec + (size_t)r * kRec;
-    s = fmaf(o[dlt], act >= 0 ? o[act] : 1.f, s);
+// One wavefront per chunk of kChunk rows.  v_mfma_f32_16x16x4f32 lane layout (checked on the device):
+// A (16 x 4) lane l holds A[l % 16][l / 16], B (4 x 16) lane l holds B[l / 16][l % 16], and register j of
+// the accumulator holds D[4 (l / 16) + j][l % 16].  With 4 rows per step (row r0 + l / 16):
+//   dW2 (64 x 64, bias column): A = d2 tile, B = a1 tile or the ones column;
+//   dW1 (64 x 8 = W1 | b1):     A = d1 tile, B = a0 (its 8th entry is the constant 1);
+//   dW3 (4 x 64, bias column):  A = dout (rows 0..3 of the tile), B = a2 tile or the ones column.
+__global__ __launch_bounds__(64) void mlp_partial_kernel(const float* __restrict__ rec, int n, float* __restrict__ part) {
+  const int l = threadIdx.x, c = l & 15, q = l >> 4;
+  const int r0 = blockIdx.x * kChunk;
+  f32x4 g2[4][5], g1[4], g3[5];
+  const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    g1[t] = z;
+#pragma unroll
+    for (int u = 0; u < 5; ++u) g2[t][u] = z;
   }
-  part[(size_t)blockIdx.y * (kMlpParams + 1) + p] = s;
+#pragma unroll
+  for (int u = 0; u < 5; ++u) g3[u] = z;
+  float ls = 0.f;
+  for (int kk = 0; kk < kChunk; kk += 4) {
+    const int r = r0 + kk + q;
+    const bool ok = r < n;
+    const float* o = rec + (size_t)(ok ? r : 0) * kRec;
+    float a1v[4], a2v[4], d1v[4], d2v[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      a1v[t] = ok ? o[kRecA1 + 16 * t + c] : 0.f;
+      a2v[t] = ok ? o[kRecA2 + 16 * t + c] : 0.f;
+      d1v[t] = ok ? o[kRecD1 + 16 * t + c] : 0.f;
+      d2v[t] = ok ? o[kRecD2 + 16 * t + c] : 0.f;
+    }
+    const float a0v = (ok && c < 8) ? o[kRecA0 + c] : 0.f;
+    const float dov = (ok && c < kMlpOut) ? o[kRecDo + c] : 0.f;
+    const float one = (ok && c == 0) ? 1.f : 0.f;
+    if (ok && c == 0) ls += o[kRecL];
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) {
+#pragma unroll
+      for (int it = 0; it < 4; ++it) g2[jt][it] = __builtin_amdgcn_mfma_f32_16x16x4f32(d2v[jt], a1v[it], g2[jt][it], 0, 0, 0);
+      g2[jt][4] = __builtin_amdgcn_mfma_f32_16x16x4f32(d2v[jt], one, g2[jt][4], 0, 0, 0);
+      g1[jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(d1v[jt], a0v, g1[jt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int it = 0; it < 4; ++it) g3[it] = __builtin_amdgcn_mfma_f32_16x16x4f32(dov, a2v[it], g3[it], 0, 0, 0);
+    g3[4] = __builtin_amdgcn_mfma_f32_16x16x4f32(dov, one, g3[4], 0, 0, 0);
+  }
+  float* out = part + (size_t)blockIdx.x * (kMlpParams + 1);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int row = 4 * q + j;   // row of the accumulator tile
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) {
+      const int u = 16 * jt + row;   // hidden unit
+#pragma unroll
+      for (int it = 0; it < 4; ++it) out[kOffW2 + u * kMlpHid + 16 * it + c] = g2[jt][it][j];
+      if (c == 0) out[kOffB2 + u] = g2[jt][4][j];
+      if (c < kMlpIn) out[kOffW1 + u * kMlpIn + c] = g1[jt][j];
+      if (c == kMlpIn) out[kOffB1 + u] = g1[jt][j];
+    }
+    if (row < kMlpOut) {
+#pragma unroll
+      for (int it = 0; it < 4; ++it) out[kOffW3 + row * kMlpHid + 16 * it + c] = g3[it][j];
+      if (c == 0) out[kOffB3 + row] = g3[4][j];
+    }
+  }
+  // the loss: the four lanes (c == 0) of the four row slots, in a fixed order
+  ls += __shfl_xor(ls, 16);
+  ls += __shfl_xor(ls, 32);
+  if (l == 0) out[kMlpParams] = ls;
 }
 
 __global__ __launch_bounds__(256) void mlp_adam_kernel(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
@@ -237,7 +288,7 @@ dmala_status dmala_mlp_train_step(float* weights, float* adam_m, float* adam_v, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "mlp rows launch");
   const int pb = (kMlpParams + 1 + 255) / 256;
-  hipLaunchKernelGGL(mlp_partial_kernel, dim3(pb, chunks), dim3(256), 0, s, rec, n_rows, part);
+  hipLaunchKernelGGL(mlp_partial_kernel, dim3(chunks), dim3(64), 0, s, rec, n_rows, part);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "mlp partial launch");
   hipLaunchKernelGGL(mlp_adam_kernel, dim3(pb), dim3(256), 0, s, weights, adam_m, adam_v, part, chunks, step, lr, loss,

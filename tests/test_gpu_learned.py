@@ -86,7 +86,7 @@ def test_training_step_matches_the_oracle():
     import torch
     import paper_2407_06042_amd as dm
     P = _params(5, scale=3.0)
-    rows, tgt = _train_set(1500, 9)     # 3 partial-sum chunks, the last one ragged
+    rows, tgt = _train_set(1500, 9)     # 6 partial-sum chunks of 256 rows, the last one ragged
     w = _dev(P)
     tr = dm.MlpTrainer(w, lr=2e-3)
     rows_d = torch.from_numpy(rows.astype(np.float32)).cuda()
