@@ -32,8 +32,8 @@ size_t sampler_lds_bytes(const Shape& sh) {
     case 4: return sampler_cfg_lds(sh, 4, 4, true, 4 * split_slots(sh, 4));
     case 5: return sampler_cfg_lds(sh, 2, 2, false, 2 * split_slots(sh, 2));
     case 6: return sampler_cfg_lds(sh, 2, 4, true, 4 * split_slots(sh, 4));
-    case 7: return sampler_cfg_lds(sh, 4, 2, true, 2 * split_slots(sh, 2));
-    case 8: return sampler_cfg_lds(sh, 4, 4, true, 4 * split_slots(sh, 4));
+    case 7: return sampler_cfg_lds(sh, 4, 2, true, 2 * split_slots(sh, 2), true);
+    case 8: return sampler_cfg_lds(sh, 4, 4, true, 4 * split_slots(sh, 4), true);
   }
   return ~(size_t)0;
 }

@@ -312,6 +312,12 @@ struct Red {
   uint32_t h;
 };
 
+// Complex-plane layouts: how many of the packed matrices' passes (proposal passes first, then the
+// energy passes) a workgroup keeps in LDS for all its transitions; the rest stream from L2 every
+// transition.  128 dimensions: 3 passes of 16 KiB (two workgroups per CU); 256 dimensions: one pass of
+// 64 KiB beside the window layout's two 16-chain blocks, two otherwise (one workgroup per CU).
+constexpr int cx_lds_passes(int rt, bool win) { return rt <= 8 ? 3 : (win ? 1 : 2); }
+
 // Template parameters: RTW row tiles of 16 dimensions per wave, WD waves per
 // chain block splitting the dimensions (RT = RTW * WD tiles in all), MG = the
 // packed matrices are read from the instance block in global memory (L2) instead
@@ -393,9 +399,11 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
   // planes) 2 planes x RT/2 antenna tiles x RT/4 K blocks of 32 antennas
   constexpr size_t PASS = CX ? (size_t)RT * RT / 4 * 1024 : (size_t)RT * KB * 1024;
   const size_t mat_bytes = F64 ? 0 : (size_t)(NPP + kEPasses) * PASS;
+  constexpr int SPL = CX ? cx_lds_passes(RT, WIN > 0) : 0;   // complex planes: passes staged in LDS
   size_t staged = 0;
   if constexpr (F64) staged = a.frag_bytes;
   else if constexpr (!MG) staged = (RT <= 4) ? (size_t)a.frag_bytes : mat_bytes;
+  else if constexpr (CX) staged = (size_t)SPL * PASS;
   for (size_t o = threadIdx.x * 16; o < staged; o += blockDim.x * 16)
     *(uint4*)(smem + o) = *(const uint4*)(blk + kParamBytes + o);
   const InstParams ip = *(const InstParams*)blk;
@@ -563,8 +571,10 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
         }
       }
       const uint32_t fo = opaque_zero() + (uint32_t)lane * 16;
+      // the first SPL passes from LDS (p is a compile-time index at every call), the others from L2
       auto frag = [&](int p, int pl, int atg, int kb) -> const unsigned char* {
         const uint32_t off = fo + (uint32_t)(((p * 2 + pl) * AT + atg) * KBX + kb) * 1024u;
+        if (p < SPL) return smem + off;
         return blk + kParamBytes + off;
       };
 #pragma unroll
@@ -1209,11 +1219,12 @@ inline int split_slots(const Shape& sh, int wd) {
   return n < blocks ? n : blocks;
 }
 
-inline size_t sampler_cfg_lds(const Shape& sh, int rtw, int wd, bool mg, int waves) {
+inline size_t sampler_cfg_lds(const Shape& sh, int rtw, int wd, bool mg, int waves, bool cx = false) {
   if (sh.fp64) return sh.frag_bytes + (size_t)waves * 16 * sh.Npad * sizeof(double);
   const int RT = rtw * wd, KB = RT / 2;
   const size_t mat = (size_t)(p_passes(sh.pm) + kEPasses) * RT * KB * 1024;
   size_t staged = mg ? 0 : (RT <= 4 ? sh.frag_bytes : mat);
+  if (cx) staged = (size_t)cx_lds_passes(RT, sh.win > 0) * RT * RT / 4 * 1024;
   staged = (staged + 15) & ~(size_t)15;
   if (wd > 1) staged += (size_t)(waves / wd) * (2 * (size_t)KB * 1024 + 2 * (size_t)wd * 16 * sizeof(Red));
   if (sh.lrn) staged += kMlpLdsBytes;
@@ -1238,7 +1249,7 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
     gy = (chain_blocks + waves - 1) / waves;
   }
   const dim3 grid(a.n_inst, gy);
-  const size_t lds = sampler_cfg_lds(sh, RTW, WD, MG, waves);
+  const size_t lds = sampler_cfg_lds(sh, RTW, WD, MG, waves, CX);
   // two waves per SIMD where the chain loop fits 256 registers without spilling: the learned
   // two-tile layouts, and the plain four-tile layouts except the naive proposal's four-wave one
   // (the evaluation kernels keep the default).  The four-wave layout without the window table
