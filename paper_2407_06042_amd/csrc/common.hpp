@@ -227,19 +227,15 @@ int estimate_chunk(int nt, int nr, int M, int N, int C, bool fp64);
 
 // ------------------------------------------------------------------ device helpers
 
-// a ^ b ^ k as one three-input bit operation (truth table 0x96; the compiler emits
-// two xors).  k must be wave-uniform: it is bound to a scalar register.
-__device__ __forceinline__ uint32_t xor3_uniform(uint32_t a, uint32_t b, uint32_t k) {
-  uint32_t r;
-  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
-  return r;
+// a ^ b ^ k as one three-input bit operation (v_bitop3_b32, truth table 0x96; from two
+// xors the compiler emits two instructions).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k) {
+  return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
 }
 
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the 4x32 S-box, key bumped
 // by the Weyl constants between rounds.  BITOP3: the xors as three-input bit
-// operations (the key (k0, k1) must then be wave-uniform); they pay on the
-// one-wave layouts, while on the dimension-split layouts the pinned asm slows
-// the schedule down.
+// operations.
 template <bool BITOP3>
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -249,8 +245,8 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
     uint32_t n0, n2;
     if constexpr (BITOP3) {
-      n0 = xor3_uniform((uint32_t)(p1 >> 32), c[1], k0);
-      n2 = xor3_uniform((uint32_t)(p0 >> 32), c[3], k1);
+      n0 = xor3((uint32_t)(p1 >> 32), c[1], k0);
+      n2 = xor3((uint32_t)(p0 >> 32), c[3], k1);
     } else {
       n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
       n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;

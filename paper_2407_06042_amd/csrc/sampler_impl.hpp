@@ -936,7 +936,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
 #pragma unroll
     for (int rt = 0; rt < RTW; ++rt) {
       uint32_t c[4] = {(uint32_t)(gdim(rt) >> 2), 0u, (uint32_t)chain, rctr};
-      philox4x32_10<PIPE>(c, key0, key1);
+      philox4x32_10<true>(c, key0, key1);
 #pragma unroll
       for (int i = 0; i < 4; ++i) kc[rt * 4 + i] = (int)(((uint64_t)(c[i] >> 8) * Q) >> 24);
     }
@@ -979,7 +979,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
     uint32_t w[RTW][4];
     auto word_block = [&](int rt, int tt) {
       w[rt][0] = (uint32_t)(gdim(rt) >> 2); w[rt][1] = (uint32_t)tt; w[rt][2] = (uint32_t)chain; w[rt][3] = rctr;
-      philox4x32_10<PIPE>(w[rt], key0, key1);
+      philox4x32_10<true>(w[rt], key0, key1);
     };
     if constexpr (PIPE) {
 #pragma unroll
@@ -996,7 +996,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
       bool useL = false;
       if constexpr (LRN) {
         uint32_t wm[4] = {1u, (uint32_t)t, (uint32_t)chain, rctr};
-        philox4x32_10<PIPE>(wm, key0, key1);
+        philox4x32_10<true>(wm, key0, key1);
         useL = low_bytes24(wm[0], wm[1], wm[2]) >= a.mix_thr;
       }
       // 1. draw x' (padding dimensions never move) and -log q(x'|x); the plain
