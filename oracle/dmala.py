@@ -235,7 +235,7 @@ def dmala_sample(prob, seed, instance, n_chains, n_iters, trace=False):
             tr["E_from"] = np.zeros((n_iters, n_chains))
     for t in range(1, n_iters + 1):
         w = philox.words(seed, instance, chains, t, N)
-        u = philox.uniform24(w[:, :N])
+        u = philox.uniform_draw(w[:, :N])
         # sample x'_n ~ q_n(. | x_n) for every n in parallel
         kp, cmarg = inverse_cdf(logq, u)
         # q(x' | x)

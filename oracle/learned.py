@@ -235,7 +235,7 @@ def mixture_sample(prob, P, eps, seed, instance, n_chains, n_iters, trace=False)
                   mix_margin=np.zeros((n_iters, n_chains)), init_hash=state_hash(k))
     for t in range(1, n_iters + 1):
         w = philox.words(seed, instance, chains, t, N)
-        u = philox.uniform24(w[:, :N])
+        u = philox.uniform_draw(w[:, :N])
         um = mixture_uniform(w)
         use_l = um >= eps
         logq = np.where(use_l[:, None, None], lq_learn, lq_plain)

@@ -17,8 +17,10 @@ Word layout (shared convention, implemented separately on each side):
   word j of the stream of (instance, chain, t) = block j>>2, lane j&3
   * t = 0: initial state, real dimension n takes word n; level index
     k = ((w >> 8) * Q) >> 24  (a uniform 24-bit fraction times Q, floored)
-  * t >= 1 (transition t): real dimension n takes word n, the uniform is
-    (w >> 8) * 2^-24; the MH uniform is the 24-bit number formed from the low
+  * t >= 1 (transition t): real dimension n takes word n, the uniform of its
+    draw is ((w >> 9) + 1/2) * 2^-23 (the midpoint of the word's 23-bit cell:
+    in (0, 1), so the inverse CDF never compares against an exact zero, and
+    exact in fp32); the MH uniform is the 24-bit number formed from the low
     bytes of words 0, 1, 2 (word 0 least significant), times 2^-24; the kernel
     mixture uniform is formed the same way from the low bytes of words 4, 5, 6.
   The real dimensions are interleaved per antenna: n = 2m is Re x_m, n = 2m+1 is
@@ -80,6 +82,11 @@ def words(seed, instance, chains, t, n_words):
 def uniform24(w):
     """High 24 bits of a word as a fraction in [0, 1) (exact in fp32 and fp64)."""
     return (np.asarray(w, dtype=np.uint32) >> np.uint32(8)).astype(np.float64) * 2.0 ** -24
+
+
+def uniform_draw(w):
+    """Uniform of a proposal draw: ((w >> 9) + 1/2) * 2^-23, in (0, 1), exact in fp32 and fp64."""
+    return ((np.asarray(w, dtype=np.uint32) >> np.uint32(9)).astype(np.float64) + 0.5) * 2.0 ** -23
 
 
 def low_byte_uniform(w, j0):

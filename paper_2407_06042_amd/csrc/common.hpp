@@ -257,6 +257,12 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 
 __device__ __forceinline__ float u24f(uint32_t w) { return (float)(w >> 8) * 5.9604644775390625e-08f; }
 __device__ __forceinline__ double u24d(uint32_t w) { return (double)(w >> 8) * 5.9604644775390625e-08; }
+// Uniform of a proposal draw: the midpoint (x + 1/2) 2^-23 of the cell of x = w >> 9, in (0, 1) and
+// exact in fp32: the bits of 1 + x 2^-23 (one funnel shift) minus 1 - 2^-24.
+__device__ __forceinline__ float u23f(uint32_t w) {
+  return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9)) - 0.999999940395355224609375f;
+}
+__device__ __forceinline__ double u23d(uint32_t w) { return ((double)(w >> 9) + 0.5) * 1.1920928955078125e-07; }
 __device__ __forceinline__ uint32_t low_bytes24(uint32_t a, uint32_t b, uint32_t c) {
   return (a & 0xFFu) | ((b & 0xFFu) << 8) | ((c & 0xFFu) << 16);
 }

@@ -68,10 +68,10 @@ __device__ __forceinline__ R gauss_of_word(uint32_t w) {
 // of N(mu, sig^2) (index units, levels 0..Q-1, edge cells unbounded) is j.  Each cell
 // is integrated on the tail side away from mu, where erfc keeps small cells accurate.
 template <int Q, typename R>
-__device__ __forceinline__ R mhgd_log2_cell(int j, R mu, R sig) {
+__device__ __forceinline__ R mhgd_log2_cell(R j, R mu, R sig) {
   const R r2 = R(0.70710678118654752440) / sig;
-  const R lo = (R(j) - R(0.5) - mu) * r2, hi = (R(j) + R(0.5) - mu) * r2;
-  const bool first = j == 0, last = j == Q - 1;
+  const R lo = (j - R(0.5) - mu) * r2, hi = (j + R(0.5) - mu) * r2;
+  const bool first = j == R(0), last = j == R(Q - 1);
   R p;
   if (!first && lo > R(0)) p = R(0.5) * (erfc_(lo) - (last ? R(0) : erfc_(hi)));
   else if (!last && hi < R(0)) p = R(0.5) * (erfc_(-hi) - (first ? R(0) : erfc_(-lo)));
@@ -140,11 +140,14 @@ struct WinCoef {
 };
 
 template <int Q, int W, bool TAB>
-__device__ __forceinline__ void window_weights(float mu, float kL, const WinCoef& wc, float (&e)[2 * W + 1], int& js,
+__device__ __forceinline__ void window_weights(float mu, float kL, const WinCoef& wc, float (&e)[2 * W + 1], float& jf,
                                                float& delta) {
   static_assert(W == 3, "the coefficient table holds a 3-level window");
-  const float jf = mode_of<Q>(mu);
-  js = (int)jf;
+  // The mode from the clamped centre plus 2^23: the addition rounds to the nearest integer
+  // (ties to even, as rint) and leaves the integer in the low 23 bits of the sum's pattern,
+  // so that the table row needs no float-to-integer conversion.
+  const float jb = __builtin_amdgcn_fmed3f(mu, 0.0f, float(Q - 1)) + 8388608.0f;
+  jf = jb - 8388608.0f;
   delta = jf - mu;
   if constexpr (TAB) {
     // the row by its 32-bit LDS address (generic pointer arithmetic would be 64-bit),
@@ -153,7 +156,8 @@ __device__ __forceinline__ void window_weights(float mu, float kL, const WinCoef
     typedef float v2f __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(3))) const v4f lds_v4f;
     typedef __attribute__((address_space(3))) const v2f lds_v2f;
-    const uint32_t row = __umul24((uint32_t)js, (uint32_t)(kCtabStride * sizeof(float))) + wc.tab;   // one v_mad_u32_u24
+    // one v_mad_u32_u24, which reads only the low 24 bits (the mode) of jb's pattern
+    const uint32_t row = __umul24(__float_as_uint(jb), (uint32_t)(kCtabStride * sizeof(float))) + wc.tab;
     const v4f lo = *(lds_v4f*)(uintptr_t)row;         // c_3, c_2, c_1 below; c_1 above
     const v2f hi = *(lds_v2f*)(uintptr_t)(row + 16);  // c_2, c_3 above
     const float x = 2.0f * kL * __builtin_amdgcn_fmed3f(delta, -wc.dmax, wc.dmax);
@@ -176,8 +180,8 @@ __device__ __forceinline__ void window_weights(float mu, float kL, const WinCoef
     for (int o = 1; o <= W; ++o) {
       pf *= F;
       pg *= G;
-      e[W + o] = (js + o <= Q - 1) ? wc.c[o] * pf : 0.0f;
-      e[W - o] = (js - o >= 0) ? wc.c[o] * pg : 0.0f;
+      e[W + o] = (jf + float(o) <= float(Q - 1)) ? wc.c[o] * pf : 0.0f;
+      e[W - o] = (jf - float(o) >= 0.0f) ? wc.c[o] * pg : 0.0f;
     }
   }
 }
@@ -203,8 +207,8 @@ __device__ __forceinline__ void norm_parts(R mu, R kL, const WinCoef& wc, R& Z, 
   // zero start would cost a separate fused multiply-add)
   if constexpr (WIN > 0) {
     R e[2 * W + 1];
-    int js;
-    window_weights<Q, W, TAB>(mu, kL, wc, e, js, base);
+    R jf;
+    window_weights<Q, W, TAB>(mu, kL, wc, e, jf, base);
     // from the mode outwards: every other weight's product fuses into the sum
     Z = e[W];
 #pragma unroll
@@ -230,27 +234,31 @@ __device__ __forceinline__ R log2_norm(R mu, R kL, const WinCoef& wc) {
 }
 
 // Inverse-CDF draw: the smallest level j with u Z < sum_{i <= j} w_i
-// (ascending levels), Z = sum_i w_i.
+// (ascending levels), Z = sum_i w_i; the level as a floating-point integer.
 template <int Q, int WIN, int W, bool TAB, typename R>
-__device__ __forceinline__ int draw_level(R mu, R kL, const WinCoef& wc, R u) {
+__device__ __forceinline__ R draw_level(R mu, R kL, const WinCoef& wc, R u) {
   if constexpr (WIN > 0) {
     R e[2 * W + 1];
-    int js;
-    R delta;
-    window_weights<Q, W, TAB>(mu, kL, wc, e, js, delta);
+    R jf, delta;
+    window_weights<Q, W, TAB>(mu, kL, wc, e, jf, delta);
     R Z = e[0];
 #pragma unroll
     for (int i = 1; i <= 2 * W; ++i) Z += e[i];
-    const R target = u * Z;
+    // The partial sums above the target, counted in fp32 without compares: with B = 2^100,
+    // B (cum - target) is exact in sign and, since target >= 2^-24 Z and cum, target are
+    // fp32 numbers, at least B 2^-47 when positive; clamped to [0, 1] it is the 0/1
+    // indicator of cum > target (one fused multiply-add with the clamp modifier each).
+    constexpr float kB = 0x1p100f;
+    const R tB = (u * Z) * kB;
     R cum = e[0];
-    int cnt = (cum <= target) ? 1 : 0;
+    R above = __builtin_amdgcn_fmed3f(0.0f, 1.0f, __builtin_fmaf(cum, kB, -tB));
 #pragma unroll
     for (int i = 1; i < 2 * W; ++i) {
       cum += e[i];
-      cnt += (cum <= target) ? 1 : 0;
+      above += __builtin_amdgcn_fmed3f(0.0f, 1.0f, __builtin_fmaf(cum, kB, -tB));
     }
-    const int k = js - W + cnt;
-    return k < 0 ? 0 : (k > Q - 1 ? Q - 1 : k);
+    // js - W + (2 W - above), clamped to the levels
+    return __builtin_amdgcn_fmed3f((jf + R(W)) - above, 0.0f, R(Q - 1));
   } else {
     R e[Q], base;
     level_weights<Q>(mu, kL, e, base);
@@ -265,7 +273,7 @@ __device__ __forceinline__ int draw_level(R mu, R kL, const WinCoef& wc, R u) {
       cum += e[j];
       cnt += (cum <= target) ? 1 : 0;
     }
-    return cnt;
+    return R(cnt);
   }
 }
 
@@ -288,6 +296,16 @@ __device__ __forceinline__ int draw_level_lz(float mu, float kL, float u, float&
   }
   lz = lg2(Z) - kL * base;
   return cnt;
+}
+
+// The f16 pair (2 ka - QM1, 2 kb - QM1) of two levels in one word (exact: |2k - QM1| <= 15),
+// low half first, by one packing conversion.
+template <int QM1, typename R>
+__device__ __forceinline__ uint32_t lv_pair(R ka, R kb) {
+  const auto h = __builtin_amdgcn_cvt_pkrtz(float(2 * ka - R(QM1)), float(2 * kb - R(QM1)));
+  uint32_t u;
+  __builtin_memcpy(&u, &h, 4);
+  return u;
 }
 
 // An opaque zero: added to LDS offsets inside the loop so that the optimiser
@@ -486,7 +504,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
 
   // [P; EG] x lv(k): accP/accE hold the lane's D outputs.  hook(rt) runs after the
   // products of row tile rt are issued (independent work placed there overlaps them).
-  auto contract = [&](const int (&k)[D], Real (&accP)[D], Real (&accE)[D], auto&& hook) {
+  auto contract = [&](const Real (&k)[D], Real (&accP)[D], Real (&accE)[D], auto&& hook) {
     if constexpr (F64) {
       __syncthreads();
 #pragma unroll
@@ -523,12 +541,16 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
       half8 ownr[KBWX], owni[KBWX];
 #pragma unroll
       for (int kbl = 0; kbl < KBWX; ++kbl) {
+        uint32_t wr[4], wi[4];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int d = ((2 * kbl + (j >> 2)) * 4 + (j & 3)) * 2;
-          ownr[kbl][j] = (_Float16)(int16_t)(2 * k[d] - QM1);        // exact: |lv| <= 15
-          owni[kbl][j] = (_Float16)(int16_t)(2 * k[d + 1] - QM1);
+        for (int q = 0; q < 4; ++q) {
+          // elements j = 2q, 2q + 1: dimensions d and d + 2 (Re), d + 1 and d + 3 (Im)
+          const int d = ((2 * kbl + (q >> 1)) * 4 + 2 * (q & 1)) * 2;
+          wr[q] = lv_pair<QM1>(k[d], k[d + 2]);
+          wi[q] = lv_pair<QM1>(k[d + 1], k[d + 3]);
         }
+        __builtin_memcpy(&ownr[kbl], wr, 16);
+        __builtin_memcpy(&owni[kbl], wi, 16);
       }
       if constexpr (WD > 1) {
         // every wave's K blocks of both planes through LDS (no register array indexed by the
@@ -656,12 +678,19 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
       bf16x8 bb[KB];
 #pragma unroll
       for (int kb = 0; kb < KBW; ++kb) {
+        uint32_t wh[4];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int d = (2 * kb + (j >> 2)) * 4 + (j & 3);
-          const int lv = 2 * k[d] - QM1;
-          bh[wd * KBW + kb][j] = (_Float16)(int16_t)lv;   // exact: |lv| <= 15
-          if constexpr (PM == PM_BF16X1) bb[wd * KBW + kb][j] = (__bf16)(float)lv;
+        for (int q = 0; q < 4; ++q) {
+          const int d = (2 * kb + (q >> 1)) * 4 + 2 * (q & 1);   // elements 2q, 2q + 1
+          wh[q] = lv_pair<QM1>(k[d], k[d + 1]);
+        }
+        __builtin_memcpy(&bh[wd * KBW + kb], wh, 16);
+        if constexpr (PM == PM_BF16X1) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int d = (2 * kb + (j >> 2)) * 4 + (j & 3);
+            bb[wd * KBW + kb][j] = (__bf16)(float)(2 * k[d] - QM1);
+          }
         }
       }
       if constexpr (WD > 1) {
@@ -760,7 +789,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
 
   // Proposal centre and energy gradient at state k from the contraction.
   auto nohook = [](int) {};
-  auto grad_at = [&](const int (&k)[D], Real (&mu)[D], Real (&eg)[D], auto&& hook) {
+  auto grad_at = [&](const Real (&k)[D], Real (&mu)[D], Real (&eg)[D], auto&& hook) {
     Real accP[D], accE[D];
     contract(k, accP, accE, hook);
 #pragma unroll
@@ -775,7 +804,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
     }
   };
   // ... and the log2 normalisers.
-  auto proposal_at = [&](const int (&k)[D], Real (&mu)[D], Real (&lz)[D], Real (&eg)[D]) {
+  auto proposal_at = [&](const Real (&k)[D], Real (&mu)[D], Real (&lz)[D], Real (&eg)[D]) {
     grad_at(k, mu, eg, nohook);
 #pragma unroll
     for (int d = 0; d < D; ++d) lz[d] = log2_norm<Q, WIN, W, TAB>(mu[d], kL, wc);
@@ -784,7 +813,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
   // Network features of the lane's antenna in slot (rt, i2) at state k with plain centre mu.
   constexpr float kCq = 0.5f * (Q - 1), kIhq = 2.0f / Q;
   const float lq4 = 0.25f * (Q == 2 ? 1.f : Q == 4 ? 2.f : Q == 8 ? 3.f : 4.f);
-  auto feats = [&](const int (&k)[D], const Real (&m)[D], int rt, int i2, float (&f)[kMlpIn]) {
+  auto feats = [&](const Real (&k)[D], const Real (&m)[D], int rt, int i2, float (&f)[kMlpIn]) {
     const int d0 = rt * 4 + 2 * i2;
     const int n0 = dim_of(d0);
     f[0] = ((float)m[d0] - kCq) * kIhq;
@@ -796,7 +825,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
     f[6] = lq4;
   };
   // Learned proposal (centre muL, log2 precision kLL) at state k with plain centre m.
-  auto learned_at = [&](const int (&k)[D], const Real (&m)[D], Real (&muL)[D], Real (&kLL)[D]) {
+  auto learned_at = [&](const Real (&k)[D], const Real (&m)[D], Real (&muL)[D], Real (&kLL)[D]) {
     const uint32_t mo = opaque_zero();
 #pragma unroll
     for (int rt = 0; rt < RTW; ++rt)
@@ -815,7 +844,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
       }
   };
   // Training rows (features, plain centre, natural-log precision, Q) of the lane's antennas at k.
-  auto write_rows = [&](const int (&k)[D], const Real (&m)[D]) {
+  auto write_rows = [&](const Real (&k)[D], const Real (&m)[D]) {
     const int Nt = N >> 1;
     const int64_t sym0 = a.desc ? a.desc[inst].sym_off : (int64_t)inst * Nt;
 #pragma unroll
@@ -840,12 +869,12 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
   };
 
   // log2 q_n(j | .) for a level j given the cached mode and normaliser
-  auto lq = [&](int j, Real mu, Real lz) {
-    const Real t = Real(j) - mu;
+  auto lq = [&](Real j, Real mu, Real lz) {
+    const Real t = j - mu;
     return -kL * t * t - lz;
   };
 
-  int kc[D];
+  Real kc[D];   // levels (small integers, exact in Real)
   Real mu[D], lz[D], eg[D];
   bool valid[D];
 #pragma unroll
@@ -854,12 +883,12 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
   if constexpr (EVAL) {
     // transition quantities for a given pair (x_from -> x_to)
     const size_t row = ((size_t)inst * a.C + (live ? chain : 0)) * N;
-    int kt[D];
+    Real kt[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int n = dim_of(d);
-      kc[d] = (live && valid[d]) ? (int)a.x_from[row + n] : 0;
-      kt[d] = (live && valid[d]) ? (int)a.x_to[row + n] : 0;
+      kc[d] = (live && valid[d]) ? Real(a.x_from[row + n]) : Real(0);
+      kt[d] = (live && valid[d]) ? Real(a.x_to[row + n]) : Real(0);
     }
     Real lqf = 0, lqr = 0, T2 = 0;
     Real mup[D], lzp[D], egp[D];
@@ -938,7 +967,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
       uint32_t c[4] = {(uint32_t)(gdim(rt) >> 2), 0u, (uint32_t)chain, rctr};
       philox4x32_10<true>(c, key0, key1);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) kc[rt * 4 + i] = (int)(((uint64_t)(c[i] >> 8) * Q) >> 24);
+      for (int i = 0; i < 4; ++i) kc[rt * 4 + i] = Real((int)(((uint64_t)(c[i] >> 8) * Q) >> 24));
     }
     Real muL[D], kLL[D];  // cached learned proposal (LRN)
     Real lzs = 0;         // sum of the lane's log2 normalisers at the current state (plain kernel)
@@ -964,10 +993,21 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
     const Real eunit = (Real)ip.eunit;
     Real E = (Real)ip.yy + Real(0.5) * eunit * ep;
     Real Ebest = E;
+    // the levels of group rt as 4 bytes
+    // (the conversions stay in the branches that use them: an empty asm per value keeps the
+    // compiler from hoisting them into every transition)
+    auto pack4 = [&](int rt) {
+      Real v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        v[i] = kc[rt * 4 + i];
+        asm volatile("" : "+v"(v[i]));
+      }
+      return (uint32_t)v[0] | ((uint32_t)v[1] << 8) | ((uint32_t)v[2] << 16) | ((uint32_t)v[3] << 24);
+    };
     uint32_t kbest[RTW];
 #pragma unroll
-    for (int rt = 0; rt < RTW; ++rt)
-      kbest[rt] = (uint32_t)kc[rt * 4] | ((uint32_t)kc[rt * 4 + 1] << 8) | ((uint32_t)kc[rt * 4 + 2] << 16) | ((uint32_t)kc[rt * 4 + 3] << 24);
+    for (int rt = 0; rt < RTW; ++rt) kbest[rt] = pack4(rt);
     int nacc = 0;
     uint32_t abits = 0;
     const size_t trow = (size_t)rid * a.C + (live ? chain : 0);
@@ -1001,26 +1041,26 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
       }
       // 1. draw x' (padding dimensions never move) and -log q(x'|x); the plain
       // kernel's terms are collected as kL sum (x'_n - mu_n)^2 + sum lz_n
-      int kp[D];
+      Real kp[D];
       Real S = 0, tq = 0;
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         Real u;
-        if constexpr (F64) u = u24d(w[d >> 2][d & 3]);
-        else u = u24f(w[d >> 2][d & 3]);
+        if constexpr (F64) u = u23d(w[d >> 2][d & 3]);
+        else u = u23f(w[d >> 2][d & 3]);
         if constexpr (MHG) {
           // gradient step + Gaussian random walk, mapped to the nearest level (rint, clamped)
-          const int kd = (int)mode_of<Q>(mu[d] + msig * gauss_of_word<Real>(w[d >> 2][d & 3]));
+          const Real kd = mode_of<Q>(mu[d] + msig * gauss_of_word<Real>(w[d >> 2][d & 3]));
           kp[d] = valid[d] ? kd : kc[d];
         } else if constexpr (LRN) {
           const float ms = useL ? muL[d] : mu[d], ks = useL ? kLL[d] : (float)kL;
           float lzf;
-          const int kd = draw_level_lz<Q>(ms, ks, u, lzf);
+          const float kd = (float)draw_level_lz<Q>(ms, ks, u, lzf);
           kp[d] = valid[d] ? kd : kc[d];
           const float t0 = float(kp[d]) - ms;
           S -= valid[d] ? (-ks * t0 * t0 - lzf) : 0.f;
         } else {
-          const int kd = draw_level<Q, WIN, W, TAB>(mu[d], kL, wc, u);
+          const Real kd = draw_level<Q, WIN, W, TAB>(mu[d], kL, wc, u);
           kp[d] = valid[d] ? kd : kc[d];
           const Real t0 = Real(kp[d]) - mu[d];
           tq += t0 * t0;
@@ -1109,8 +1149,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
       if (E < Ebest) {
         Ebest = E;
 #pragma unroll
-        for (int rt = 0; rt < RTW; ++rt)
-          kbest[rt] = (uint32_t)kc[rt * 4] | ((uint32_t)kc[rt * 4 + 1] << 8) | ((uint32_t)kc[rt * 4 + 2] << 16) | ((uint32_t)kc[rt * 4 + 3] << 24);
+        for (int rt = 0; rt < RTW; ++rt) kbest[rt] = pack4(rt);
       }
       if (a.trace_accept) {
         abits |= (acc ? 1u : 0u) << ((t - 1) & 31);
@@ -1122,7 +1161,11 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
       if (a.trace_hash) {
         uint32_t hs = 0;
 #pragma unroll
-        for (int d = 0; d < D; ++d) hs += valid[d] ? (uint32_t)(kc[d] + 1) * hash_mult(dim_of(d)) : 0u;
+        for (int d = 0; d < D; ++d) {
+          Real v = kc[d];
+          asm volatile("" : "+v"(v));
+          hs += valid[d] ? ((uint32_t)v + 1u) * hash_mult(dim_of(d)) : 0u;
+        }
         if constexpr (WD > 1) {
           hs = chain_sum(Red{0.f, 0.f, 0.f, hs}).h;
         } else {
@@ -1143,13 +1186,13 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
 #pragma unroll
       for (int rt = 0; rt < RTW; ++rt) {
         const int n0 = gdim(rt);
-        const uint32_t cur = (uint32_t)kc[rt * 4] | ((uint32_t)kc[rt * 4 + 1] << 8) | ((uint32_t)kc[rt * 4 + 2] << 16) | ((uint32_t)kc[rt * 4 + 3] << 24);
+        const uint32_t cur = pack4(rt);
         *(uint32_t*)(st + so.k + (size_t)chain * Npad + n0) = cur;
         *(uint32_t*)(st + so.kbest + (size_t)chain * Npad + n0) = kbest[rt];
         if (a.final_state) {
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if (n0 + i < N) a.final_state[fs_base + (size_t)chain * N + n0 + i] = (int8_t)kc[rt * 4 + i];
+            if (n0 + i < N) a.final_state[fs_base + (size_t)chain * N + n0 + i] = (int8_t)(int)kc[rt * 4 + i];
         }
       }
       if (h == 0 && wd == 0) {

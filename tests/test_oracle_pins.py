@@ -44,6 +44,12 @@ def test_philox_uniformity_and_counter_independence():
     w2 = philox.words(12345, 7, np.arange(4096), 4, 64)
     c = np.corrcoef(u, philox.uniform24(w2).reshape(-1))[0, 1]
     assert abs(c) < 0.01
+    # the draw uniform: midpoints of the 23-bit cells, in (0, 1) and exact in fp32
+    ud = philox.uniform_draw(np.array([0, 0x1FF, 0x200, 0xFFFFFFFF], np.uint32))
+    np.testing.assert_array_equal(ud, [2.0 ** -24, 2.0 ** -24, 3 * 2.0 ** -24, 1 - 2.0 ** -24])
+    ua = philox.uniform_draw(w).reshape(-1)
+    assert np.all(ua.astype(np.float32) == ua)
+    assert stats.kstest(ua, "uniform").pvalue > 1e-4
     # low-byte MH uniforms are uniform too
     um = philox.low_byte_uniform(w, 0)
     assert stats.kstest(um, "uniform").pvalue > 1e-4
@@ -162,7 +168,7 @@ def test_inverse_cdf_semantics():
     assert np.all(margin >= 0)
     # frequencies follow the probabilities
     lg = np.array([0.3, -1.0, 2.0, 0.0])
-    uu = philox.uniform24(philox.words(1, 0, np.arange(40000), 1, 4)[:, 0])
+    uu = philox.uniform_draw(philox.words(1, 0, np.arange(40000), 1, 4)[:, 0])
     ii, _ = dmala.inverse_cdf(np.broadcast_to(lg, (40000, 4)), uu)
     exp_p = np.exp(dmala.log_softmax(lg))
     assert stats.chisquare(np.bincount(ii, minlength=4), 40000 * exp_p).pvalue > 1e-4
