@@ -435,7 +435,7 @@ def main():
             r = extra_uniform(dm, torch, c5, C5_C, C5_T, ["fp32", "bf16"], args.steps, args.warmup, tile=args.tile)
         elif args.only == "c2":
             r = extra_uniform(dm, torch, W.c2_snr_sweep().as_precision(np.float32), 32, 100, ["fp32", "bf16"],
-                              args.steps, args.warmup)
+                              args.steps, args.warmup, tile=args.tile)
         elif args.only == "c4":
             r = extra_uniform(dm, torch, W.c4_correlated().as_precision(np.float32), 64, 200,
                               ["fp32", "bf16", "fp16"], args.steps, args.warmup, tile=args.tile)

@@ -121,8 +121,8 @@ typedef struct {
   double alpha_mult;         /* alpha = alpha_mult * sigma^2;          <= 0 selects 1 */
   double beta_mult;          /* beta  = beta_mult * dmin^2 / sigma^2;  <= 0 selects 1 */
   double gamma_mult;         /* gamma = gamma_mult * sigma^2 / (2 dmin^2); <= 0 selects 1 */
-  int32_t tile_config;       /* sampler work layout: 0 = automatic (32 dims: layout 0, 64: 1, 128: 7,
-                                256: 8 (NAIVE: 3, 4); LEARNED 64: 5, 128: 6); k >= 1 selects layout k - 1:
+  int32_t tile_config;       /* sampler work layout: 0 = automatic (32 dims: layout 0, 64: 9, 128: 7,
+                                256: 8 (NAIVE: 1, 3, 4); LEARNED 64: 5, 128: 6); k >= 1 selects layout k - 1:
                                 0: 32 dims, 1 wave / 16 chains, matrices in LDS
                                 1: 64 dims, 1 wave / 16 chains, LDS
                                 2: 128 dims, 1 wave / 16 chains, LDS
@@ -133,6 +133,7 @@ typedef struct {
                                 7: layout 3 with the matrices stored as complex planes (half the bytes;
                                    not LEARNED, not FP64)
                                 8: layout 4 with complex-plane matrices (not LEARNED, not FP64)
+                                9: layout 1 with complex-plane matrices in LDS (not LEARNED, not FP64)
                                 (dims = 2 Nt rounded up to a power of two >= 32; a layout that does
                                 not match the shape returns DMALA_ERR_UNSUPPORTED) */
   int32_t wg_chain_blocks;   /* 16-chain blocks of one instance per workgroup: 0 = automatic (up to 4),

@@ -93,7 +93,7 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
   };
   sh.cx = 0;
   set_frag_bytes();
-  if (p->tile_config < 0 || p->tile_config > 9) return fail(DMALA_ERR_ARG, "tile_config must be in [0, 9]");
+  if (p->tile_config < 0 || p->tile_config > 10) return fail(DMALA_ERR_ARG, "tile_config must be in [0, 10]");
   if (p->wg_chain_blocks != 0 && p->wg_chain_blocks != 1 && p->wg_chain_blocks != 2 && p->wg_chain_blocks != 4)
     return fail(DMALA_ERR_ARG, "wg_chain_blocks must be 0, 1, 2 or 4");
   sh.cbw = p->wg_chain_blocks ? p->wg_chain_blocks : 4;
@@ -104,7 +104,7 @@ dmala_status make_plan(int32_t n_inst, int32_t nt, int32_t nr, int32_t M, const 
       return fail(DMALA_ERR_UNSUPPORTED, "tile_config %d does not fit this shape", p->tile_config);
     sh.cfg = p->tile_config - 1;
   }
-  sh.cx = (sh.cfg == 7 || sh.cfg == 8) ? 1 : 0;
+  sh.cx = (sh.cfg == 7 || sh.cfg == 8 || sh.cfg == 9) ? 1 : 0;
   set_frag_bytes();
   if (sampler_lds_bytes(sh) > 160 * 1024)
     return fail(DMALA_ERR_UNSUPPORTED, "shape needs %zu bytes of LDS (> 160 KiB)", sampler_lds_bytes(sh));

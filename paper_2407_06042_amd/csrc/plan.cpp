@@ -546,7 +546,7 @@ dmala_status dmala_plan_autotune(dmala_plan P, const void* H, const void* y, con
     }
     double best = INFINITY;
     ClassInfo best_c = c;
-    for (int tc = 1; tc <= 9; ++tc) {
+    for (int tc = 1; tc <= 10; ++tc) {
       for (int cb : {1, 2, 4}) {
         ClassInfo t = c;
         t.tile_config = tc;

@@ -34,13 +34,14 @@ size_t sampler_lds_bytes(const Shape& sh) {
     case 6: return sampler_cfg_lds(sh, 2, 4, true, 4 * split_slots(sh, 4));
     case 7: return sampler_cfg_lds(sh, 4, 2, true, 2 * split_slots(sh, 2), true);
     case 8: return sampler_cfg_lds(sh, 4, 4, true, 4 * split_slots(sh, 4), true);
+    case 9: return sampler_cfg_lds(sh, 4, 1, false, 4, true);
   }
   return ~(size_t)0;
 }
 
 bool sampler_cfg_valid(const Shape& sh, int cfg) {
-  static const int rt_of[9] = {2, 4, 8, 8, 16, 4, 8, 8, 16};
-  if (cfg < 0 || cfg > 8 || rt_of[cfg] != sh.RT) return false;
+  static const int rt_of[10] = {2, 4, 8, 8, 16, 4, 8, 8, 16, 4};
+  if (cfg < 0 || cfg > 9 || rt_of[cfg] != sh.RT) return false;
   if (sh.lrn && cfg == 2) return false;   // the learned variant keeps at most 4 row tiles per wave
   if ((sh.lrn || sh.fp64) && cfg >= 7) return false;   // complex planes: the plain and MHGD float chains
   if (!sh.lrn && (cfg == 5 || cfg == 6)) return false;  // layouts 5, 6 are built for the learned variant only
@@ -50,13 +51,14 @@ bool sampler_cfg_valid(const Shape& sh, int cfg) {
 }
 
 int sampler_default_cfg(const Shape& sh) {
-  // 128 and 256 dimensions: the complex-plane layouts (half the fragment bytes) for the
+  // 64, 128 and 256 dimensions: the complex-plane layouts (half the fragment bytes) for the
   // preconditioned and MHGD chains (64x64 64-QAM fp32 sampler 18.7 -> 15.1 ms, 128x128 256-QAM
-  // 9.7 -> 6.9 ms); two waves of 4 tiles at two waves per SIMD beat one wave of 8 tiles
+  // 9.7 -> 6.9 ms; at 64 dimensions the halved LDS copy lets four workgroups share a CU); two
+  // waves of 4 tiles at two waves per SIMD beat one wave of 8 tiles
   const bool cx = !sh.lrn && sh.pm != PM_NAIVE;
   switch (sh.RT) {
     case 2: return 0;
-    case 4: return sh.lrn ? 5 : 1;
+    case 4: return sh.lrn ? 5 : (cx ? 9 : 1);   // 32x32 64-QAM fp32 sampler 4.63 -> 3.47 ms (4 workgroups per CU)
     case 8: return sh.lrn ? 6 : (cx ? 7 : 3);
     case 16: return cx ? 8 : 4;
   }

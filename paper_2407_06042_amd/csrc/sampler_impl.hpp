@@ -348,8 +348,8 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
   static_assert(!F64 || (WD == 1 && !MG), "the float64 path uses one wave per chain block and LDS matrices");
   static_assert(!LRN || (!F64 && PM != PM_NAIVE && WIN == 0 && RTW <= 4), "learned variant: float, preconditioned, no window");
   static_assert(!MHG || (PM != PM_NAIVE && WIN == 0), "MHGD: the preconditioned gradient step, no proposal window");
-  static_assert(!CX || (!F64 && !LRN && MG && RTW * WD >= 8 && RTW % 4 == 0),
-                "complex-plane matrices: float, matrices from L2, whole 32-antenna K blocks per wave");
+  static_assert(!CX || (!F64 && !LRN && RTW % 4 == 0 && (MG ? RTW * WD >= 8 : RTW * WD == 4)),
+                "complex-plane matrices: float, whole 32-antenna K blocks per wave, from L2 or (64 dimensions) LDS");
   static_assert(WD == 1 || RTW % 2 == 0, "dimension-split waves own whole K blocks");
   constexpr int RT = RTW * WD;
   constexpr int D = 4 * RTW;
@@ -417,7 +417,8 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
   // planes) 2 planes x RT/2 antenna tiles x RT/4 K blocks of 32 antennas
   constexpr size_t PASS = CX ? (size_t)RT * RT / 4 * 1024 : (size_t)RT * KB * 1024;
   const size_t mat_bytes = F64 ? 0 : (size_t)(NPP + kEPasses) * PASS;
-  constexpr int SPL = CX ? cx_lds_passes(RT, WIN > 0) : 0;   // complex planes: passes staged in LDS
+  // complex planes: passes staged in LDS (every pass when the matrices are not read from L2)
+  constexpr int SPL = CX ? (MG ? cx_lds_passes(RT, WIN > 0) : NPP + kEPasses) : 0;
   size_t staged = 0;
   if constexpr (F64) staged = a.frag_bytes;
   else if constexpr (!MG) staged = (RT <= 4) ? (size_t)a.frag_bytes : mat_bytes;
@@ -1267,7 +1268,7 @@ inline size_t sampler_cfg_lds(const Shape& sh, int rtw, int wd, bool mg, int wav
   const int RT = rtw * wd, KB = RT / 2;
   const size_t mat = (size_t)(p_passes(sh.pm) + kEPasses) * RT * KB * 1024;
   size_t staged = mg ? 0 : (RT <= 4 ? sh.frag_bytes : mat);
-  if (cx) staged = (size_t)cx_lds_passes(RT, sh.win > 0) * RT * RT / 4 * 1024;
+  if (cx && mg) staged = (size_t)cx_lds_passes(RT, sh.win > 0) * RT * RT / 4 * 1024;
   staged = (staged + 15) & ~(size_t)15;
   if (wd > 1) staged += (size_t)(waves / wd) * (2 * (size_t)KB * 1024 + 2 * (size_t)wd * 16 * sizeof(Red));
   if (sh.lrn) staged += kMlpLdsBytes;
@@ -1370,6 +1371,7 @@ hipError_t launch_q(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
 //   cfg 0: RT 2, 1 wave, LDS     cfg 1: RT 4, 1 wave, LDS     cfg 2: RT 8, 1 wave, LDS
 //   cfg 3: RT 8 as 2 waves x 4, L2     cfg 4: RT 16 as 4 waves x 4, L2
 //   cfg 7, 8: cfg 3, 4 with the matrices stored as complex planes
+//   cfg 9: cfg 1 with complex-plane matrices (half the LDS: four workgroups per CU at fp32)
 template <typename Real, int PM>
 hipError_t launch_rt(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_t s, const Persist* p, int gn,
                     KernelCfg* cfg) {
@@ -1388,6 +1390,7 @@ hipError_t launch_rt(const Shape& sh, const SamplerArgs& a, bool eval, hipStream
       case 4: return launch_q<Real, 4, 4, true, PM>(sh, a, eval, s, p, gn, cfg);
       case 7: return launch_q<Real, 4, 2, true, PM, true>(sh, a, eval, s, p, gn, cfg);
       case 8: return launch_q<Real, 4, 4, true, PM, true>(sh, a, eval, s, p, gn, cfg);
+      case 9: return launch_q<Real, 4, 1, false, PM, true>(sh, a, eval, s, p, gn, cfg);
     }
     return hipErrorInvalidValue;
   }
@@ -1423,6 +1426,7 @@ hipError_t launch_rt_mhg(const Shape& sh, const SamplerArgs& a, bool eval, hipSt
       case 4: return launch_q_mhg<Real, 4, 4, true, PM>(sh, a, eval, s, p, gn, cfg);
       case 7: return launch_q_mhg<Real, 4, 2, true, PM, true>(sh, a, eval, s, p, gn, cfg);
       case 8: return launch_q_mhg<Real, 4, 4, true, PM, true>(sh, a, eval, s, p, gn, cfg);
+      case 9: return launch_q_mhg<Real, 4, 1, false, PM, true>(sh, a, eval, s, p, gn, cfg);
     }
   }
   return hipErrorInvalidValue;

@@ -27,7 +27,11 @@ def test_library_exports_every_declared_symbol():
 
 def test_workspace_size_validation():
     p = dm.make_params(32, 100, 1)
-    assert dm.workspace_size(8, 32, 32, 64, p) > 8 * 32 * 1024
+    # 64 dimensions: complex-plane matrices by default (5 passes x 4 KiB per instance), the real-equivalent
+    # layout 1 on request (5 x 8 KiB)
+    ws_cx = dm.workspace_size(8, 32, 32, 64, p)
+    ws_re = dm.workspace_size(8, 32, 32, 64, dm.make_params(32, 100, 1, tile_config=2))
+    assert ws_cx > 8 * 20 * 1024 and ws_re - ws_cx == 8 * 20 * 1024
     for args, msg in [((8, 32, 32, 8), "qam_order"), ((0, 32, 32, 64), "n_inst"), ((8, 0, 4, 16), "nt"),
                       ((8, 129, 129, 16), "nt > 128"), ((8, 4, 5000, 16), "nr")]:
         with pytest.raises(dm.DmalaError) as e:

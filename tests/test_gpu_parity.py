@@ -236,6 +236,9 @@ def test_windowed_proposal_matches_oracle(M, snr, shift):
     (128, 256, 0.5, 30.0, 48, 20, 9),    # complex planes, four waves per 16 chains, 512-thread workgroups
     (100, 64, 0.0, 24.0, 32, 20, 9),     # complex planes, 100 antennas
     (41, 16, 0.0, 18.0, 32, 30, 0),      # 1024-thread setup, 41 rows over 16 threads per row (ragged slots)
+    (32, 64, 0.0, 22.0, 32, 30, 10),     # complex planes in LDS, one wave per 16 chains
+    (32, 64, 0.0, 22.0, 32, 30, 2),      # real-equivalent matrices in LDS, one wave per 16 chains
+    (20, 16, 0.0, 18.0, 48, 30, 10),     # the same, 20 antennas (padding rows and K columns), three chain blocks
     (70, 64, 0.0, 22.0, 32, 20, 0),      # working matrix in the workspace, 70 rows over 8 threads per row
     (128, 4, 0.0, 8.0, 32, 20, 0),       # QPSK: 256 marginal rows, H read from global memory (1024 threads)
 ])
@@ -259,7 +262,7 @@ def test_large_shapes_fp32(nt, M, rho, snr, C, T, tile):
 
 
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
-@pytest.mark.parametrize("nt,M,tile", [(32, 64, 0), (64, 64, 0), (128, 256, 0), (64, 64, 8), (128, 256, 9)])
+@pytest.mark.parametrize("nt,M,tile", [(32, 64, 0), (64, 64, 0), (128, 256, 0), (64, 64, 8), (128, 256, 9), (32, 64, 10)])
 def test_reduced_precision_kernel_is_reversible(precision, nt, M, tile):
     """Reduced-precision proposals keep the exact target: device log-ratios are antisymmetric
     and the energy term matches the float64 metric on random state pairs (tile 8, 9: complex-plane
