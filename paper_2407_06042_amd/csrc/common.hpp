@@ -263,6 +263,11 @@ __device__ __forceinline__ float u23f(uint32_t w) {
   return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9)) - 0.999999940395355224609375f;
 }
 __device__ __forceinline__ double u23d(uint32_t w) { return ((double)(w >> 9) + 0.5) * 1.1920928955078125e-07; }
+// The same uniform times 2^100, in one fused multiply-add (exact: (x + 1/2) 2^77).
+__device__ __forceinline__ float u23f_x2p100(uint32_t w) {
+  return __builtin_fmaf(__uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9)), 0x1p100f,
+                        -0.999999940395355224609375f * 0x1p100f);
+}
 __device__ __forceinline__ uint32_t low_bytes24(uint32_t a, uint32_t b, uint32_t c) {
   return (a & 0xFFu) | ((b & 0xFFu) << 8) | ((c & 0xFFu) << 16);
 }

@@ -139,9 +139,11 @@ struct WinCoef {
   float c[4];
 };
 
+// The window's factors: F = exp2(-2 kL delta), G = 1 / F as two exponentials, and the
+// coefficients c_1..c_3 of the levels above (cu) and below (cl) the mode, zero outside [0, Q).
 template <int Q, int W, bool TAB>
-__device__ __forceinline__ void window_weights(float mu, float kL, const WinCoef& wc, float (&e)[2 * W + 1], float& jf,
-                                               float& delta) {
+__device__ __forceinline__ void window_coefs(float mu, float kL, const WinCoef& wc, float& F, float& G,
+                                             float (&cu)[W], float (&cl)[W], float& jf, float& delta) {
   static_assert(W == 3, "the coefficient table holds a 3-level window");
   // The mode from the clamped centre plus 2^23: the addition rounds to the nearest integer
   // (ties to even, as rint) and leaves the integer in the low 23 bits of the sum's pattern,
@@ -161,29 +163,36 @@ __device__ __forceinline__ void window_weights(float mu, float kL, const WinCoef
     const v4f lo = *(lds_v4f*)(uintptr_t)row;         // c_3, c_2, c_1 below; c_1 above
     const v2f hi = *(lds_v2f*)(uintptr_t)(row + 16);  // c_2, c_3 above
     const float x = 2.0f * kL * __builtin_amdgcn_fmed3f(delta, -wc.dmax, wc.dmax);
-    const float F = ex2(-x);
-    const float G = ex2(x);
-    const float F2 = F * F, G2 = G * G;
-    e[W] = 1.0f;
-    e[W + 1] = lo.w * F;
-    e[W - 1] = lo.z * G;
-    e[W + 2] = hi.x * F2;
-    e[W - 2] = lo.y * G2;
-    e[W + 3] = hi.y * (F2 * F);
-    e[W - 3] = lo.x * (G2 * G);
+    F = ex2(-x);
+    G = ex2(x);
+    cl[0] = lo.z; cl[1] = lo.y; cl[2] = lo.x;
+    cu[0] = lo.w; cu[1] = hi.x; cu[2] = hi.y;
   } else {
     const float x = 2.0f * kL * delta;
-    const float F = ex2(-x), G = ex2(x);
-    float pf = 1.0f, pg = 1.0f;
-    e[W] = 1.0f;
+    F = ex2(-x);
+    G = ex2(x);
 #pragma unroll
     for (int o = 1; o <= W; ++o) {
-      pf *= F;
-      pg *= G;
-      e[W + o] = (jf + float(o) <= float(Q - 1)) ? wc.c[o] * pf : 0.0f;
-      e[W - o] = (jf - float(o) >= 0.0f) ? wc.c[o] * pg : 0.0f;
+      cu[o - 1] = (jf + float(o) <= float(Q - 1)) ? wc.c[o] : 0.0f;
+      cl[o - 1] = (jf - float(o) >= 0.0f) ? wc.c[o] : 0.0f;
     }
   }
+}
+
+// The window's weights in ascending level order: c_o F^o above the mode, c_o G^o below it.
+template <int Q, int W, bool TAB>
+__device__ __forceinline__ void window_weights(float mu, float kL, const WinCoef& wc, float (&e)[2 * W + 1], float& jf,
+                                               float& delta) {
+  float F, G, cu[W], cl[W];
+  window_coefs<Q, W, TAB>(mu, kL, wc, F, G, cu, cl, jf, delta);
+  const float F2 = F * F, G2 = G * G;
+  e[W] = 1.0f;
+  e[W + 1] = cu[0] * F;
+  e[W - 1] = cl[0] * G;
+  e[W + 2] = cu[1] * F2;
+  e[W - 2] = cl[1] * G2;
+  e[W + 3] = cu[2] * (F2 * F);
+  e[W - 3] = cl[2] * (G2 * G);
 }
 
 // All Q weights relative to the mode, one exponential per level (any kL).
@@ -206,16 +215,11 @@ __device__ __forceinline__ void norm_parts(R mu, R kL, const WinCoef& wc, R& Z, 
   // the sums start from the first weight, not from zero (0 + x is exact, and a
   // zero start would cost a separate fused multiply-add)
   if constexpr (WIN > 0) {
-    R e[2 * W + 1];
-    R jf;
-    window_weights<Q, W, TAB>(mu, kL, wc, e, jf, base);
-    // from the mode outwards: every other weight's product fuses into the sum
-    Z = e[W];
-#pragma unroll
-    for (int o = 1; o <= W; ++o) {
-      Z += e[W - o];
-      Z += e[W + o];
-    }
+    // Z = 1 + F (c1 + F (c2 + F c3)) + G (c1' + G (c2' + G c3')): six fused multiply-adds, no powers
+    R F, G, cu[W], cl[W], jf;
+    window_coefs<Q, W, TAB>(mu, kL, wc, F, G, cu, cl, jf, base);
+    const R zu = __builtin_fmaf(F, __builtin_fmaf(F, __builtin_fmaf(F, cu[2], cu[1]), cu[0]), 1.0f);
+    Z = __builtin_fmaf(G, __builtin_fmaf(G, __builtin_fmaf(G, cl[2], cl[1]), cl[0]), zu);
     base *= base;
   } else {
     R e[Q];
@@ -236,7 +240,7 @@ __device__ __forceinline__ R log2_norm(R mu, R kL, const WinCoef& wc) {
 // Inverse-CDF draw: the smallest level j with u Z < sum_{i <= j} w_i
 // (ascending levels), Z = sum_i w_i; the level as a floating-point integer.
 template <int Q, int WIN, int W, bool TAB, typename R>
-__device__ __forceinline__ R draw_level(R mu, R kL, const WinCoef& wc, R u) {
+__device__ __forceinline__ R draw_level(R mu, R kL, const WinCoef& wc, uint32_t word) {
   if constexpr (WIN > 0) {
     R e[2 * W + 1];
     R jf, delta;
@@ -249,7 +253,7 @@ __device__ __forceinline__ R draw_level(R mu, R kL, const WinCoef& wc, R u) {
     // fp32 numbers, at least B 2^-47 when positive; clamped to [0, 1] it is the 0/1
     // indicator of cum > target (one fused multiply-add with the clamp modifier each).
     constexpr float kB = 0x1p100f;
-    const R tB = (u * Z) * kB;
+    const R tB = u23f_x2p100(word) * Z;   // (u Z) 2^100, rounded once as u Z
     R cum = e[0];
     R above = __builtin_amdgcn_fmed3f(0.0f, 1.0f, __builtin_fmaf(cum, kB, -tB));
 #pragma unroll
@@ -265,6 +269,9 @@ __device__ __forceinline__ R draw_level(R mu, R kL, const WinCoef& wc, R u) {
     R Z = R(0);
 #pragma unroll
     for (int j = 0; j < Q; ++j) Z += e[j];
+    R u;
+    if constexpr (std::is_same<R, double>::value) u = u23d(word);
+    else u = u23f(word);
     const R target = u * Z;
     R cum = R(0);
     int cnt = 0;
@@ -1046,9 +1053,6 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
       Real S = 0, tq = 0;
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        Real u;
-        if constexpr (F64) u = u23d(w[d >> 2][d & 3]);
-        else u = u23f(w[d >> 2][d & 3]);
         if constexpr (MHG) {
           // gradient step + Gaussian random walk, mapped to the nearest level (rint, clamped)
           const Real kd = mode_of<Q>(mu[d] + msig * gauss_of_word<Real>(w[d >> 2][d & 3]));
@@ -1056,12 +1060,12 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
         } else if constexpr (LRN) {
           const float ms = useL ? muL[d] : mu[d], ks = useL ? kLL[d] : (float)kL;
           float lzf;
-          const float kd = (float)draw_level_lz<Q>(ms, ks, u, lzf);
+          const float kd = (float)draw_level_lz<Q>(ms, ks, u23f(w[d >> 2][d & 3]), lzf);
           kp[d] = valid[d] ? kd : kc[d];
           const float t0 = float(kp[d]) - ms;
           S -= valid[d] ? (-ks * t0 * t0 - lzf) : 0.f;
         } else {
-          const Real kd = draw_level<Q, WIN, W, TAB>(mu[d], kL, wc, u);
+          const Real kd = draw_level<Q, WIN, W, TAB>(mu[d], kL, wc, w[d >> 2][d & 3]);
           kp[d] = valid[d] ? kd : kc[d];
           const Real t0 = Real(kp[d]) - mu[d];
           tq += t0 * t0;
