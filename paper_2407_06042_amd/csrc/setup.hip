@@ -205,6 +205,7 @@ __device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
   // P = BS / RMAX consecutive threads share an antenna m and split the receive
   // antennas, then sum over those lanes.
   double nonfinite = 0.0;
+  double yy = 0.0;
   {
     constexpr int kIC = RMAX <= 32 ? 16 : 32;
     constexpr int NW = BS / 64;
@@ -231,14 +232,39 @@ __device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
     }
     const int zm = tid / P, zp = tid % P;
     cd zacc = {0.0, 0.0};
+    // The chunk of receive antennas i0 .. i0 + kIC - 1 is loaded into registers (every load
+    // issued before the first is waited for), then stored to LDS; the next chunk's loads are
+    // issued before this chunk's products, so that they overlap.  Element e of a chunk:
+    // receive antenna i0 + e % kIC, column e / kIC (column nt: y).
+    constexpr int kSt = (kIC * (RMAX + 1) + BS - 1) / BS;
+    TIn hv[kSt][2];
+    auto load_chunk = [&](int i0) {
+      const int ic = nr - i0 < kIC ? nr - i0 : kIC;
+#pragma unroll
+      for (int k = 0; k < kSt; ++k) {
+        const int e = tid + k * BS, mm = e / kIC, ii = e % kIC;
+        if (mm <= nt && ii < ic) {
+          const TIn* src = mm < nt ? Hg + 2 * ((size_t)mm * nr + i0 + ii) : y + 2 * (i0 + ii);
+          hv[k][0] = src[0];
+          hv[k][1] = src[1];
+        }
+      }
+    };
+    load_chunk(0);
     for (int i0 = 0; i0 < nr; i0 += kIC) {
       const int ic = nr - i0 < kIC ? nr - i0 : kIC;
-      for (int e = tid; e < ic * (nt + 1); e += BS) {
-        const int mm = e / ic, ii = e % ic;
-        const TIn* src = mm < nt ? Hg + 2 * ((size_t)mm * nr + i0 + ii) : y + 2 * (i0 + ii);
-        Ht[ii * ld + mm] = {(double)src[0], (double)src[1]};
+#pragma unroll
+      for (int k = 0; k < kSt; ++k) {
+        const int e = tid + k * BS, mm = e / kIC, ii = e % kIC;
+        if (mm <= nt && ii < ic) Ht[ii * ld + mm] = {(double)hv[k][0], (double)hv[k][1]};
       }
       __syncthreads();
+      if (i0 + kIC < nr) load_chunk(i0 + kIC);
+      // |y|^2 from the staged y
+      if (tid < ic) {
+        const cd yv = Ht[tid * ld + nt];
+        yy = fma(yv.re, yv.re, fma(yv.im, yv.im, yy));
+      }
 #pragma unroll
       for (int q = 0; q < kTPW; ++q) {
         if (wv + q * NW < ntiles) {
@@ -290,11 +316,6 @@ __device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
         }
       }
     }
-  }
-  double yy = 0.0;
-  for (int i = tid; i < nr; i += blockDim.x) {
-    const double re = (double)y[2 * i], im = (double)y[2 * i + 1];
-    yy += re * re + im * im;
   }
   __syncthreads();
   yy = block_reduce(yy, red, false);
