@@ -77,7 +77,7 @@ struct Shape {
 
 // Offsets inside the per-instance state block.
 struct StateOff {
-  size_t k, kbest, ebest, nacc, end;
+  size_t k, kbest, ebest, nacc, eg, end;
 };
 __host__ __device__ inline StateOff state_offsets(int Cpad, int Npad) {
   StateOff o;
@@ -85,7 +85,9 @@ __host__ __device__ inline StateOff state_offsets(int Cpad, int Npad) {
   o.kbest = o.k + (size_t)Cpad * Npad;
   o.ebest = (o.kbest + (size_t)Cpad * Npad + 15) & ~(size_t)15;
   o.nacc = o.ebest + (size_t)Cpad * 8;
-  o.end = (o.nacc + (size_t)Cpad * 4 + 255) & ~(size_t)255;
+  // the float chains' energy gradient at the final state (Cpad x Npad floats), for the estimator
+  o.eg = (o.nacc + (size_t)Cpad * 4 + 255) & ~(size_t)255;
+  o.end = (o.eg + (size_t)Cpad * Npad * 4 + 255) & ~(size_t)255;
   return o;
 }
 

@@ -88,6 +88,7 @@ __device__ __forceinline__ void estimate_body(const EstArgs& a, const int b) {
   const R s = (R)ip.s, tau = (R)ip.tau;
   const R inv_s2 = R(1) / (R)ip.sigma2, inv_tau = R(1) / tau;
   const R cw = (tau - R(1)) * inv_tau;
+  const R kA = R(-2) * tau * R(0.69314718055994530942);
   const StateOff so = state_offsets(a.Cpad, Npad);
   const unsigned char* st = a.ws_state + (size_t)b * a.state_stride;
   const int8_t* K = (const int8_t*)(st + so.k);
@@ -239,16 +240,25 @@ __device__ __forceinline__ void estimate_body(const EstArgs& a, const int b) {
         // antenna share each cache line of its column
         for (int it = tid; it < ch * nt; it += nth) {
           const int c = SH ? it / nt : it % ch, m = SH ? it % nt : it / ch;
-          R re = 0, im = 0;
-          for (int i = 0; i < nr; ++i) {
-            const R hr = hre(m, i), hi = him(m, i);
-            const R rr = rs[c * lrs + 2 * i], ri = rs[c * lrs + 2 * i + 1];
-            re += hr * rr + hi * ri;
-            im += hr * ri - hi * rr;
-          }
           CM<R> v;
-          v.aI = R(4) * s * re * inv_s2;
-          v.aQ = R(4) * s * im * inv_s2;
+          if constexpr (std::is_same<R, float>::value) {
+            // from the sampler's energy gradient at the final state,
+            // g = 2 s log2(e) (G x - z) / (tau sigma^2) = -2 s log2(e) H^H r / (tau sigma^2):
+            // 4 s (H^H r) / sigma^2 = -2 tau ln(2) g
+            const float* egc = (const float*)(st + so.eg) + (size_t)(c0 + c) * Npad;
+            v.aI = kA * egc[2 * m];
+            v.aQ = kA * egc[2 * m + 1];
+          } else {
+            R re = 0, im = 0;
+            for (int i = 0; i < nr; ++i) {
+              const R hr = hre(m, i), hi = him(m, i);
+              const R rr = rs[c * lrs + 2 * i], ri = rs[c * lrs + 2 * i + 1];
+              re += hr * rr + hi * ri;
+              im += hr * ri - hi * rr;
+            }
+            v.aI = R(4) * s * re * inv_s2;
+            v.aQ = R(4) * s * im * inv_s2;
+          }
           v.kI = Ks[c * N + 2 * m];
           v.kQ = Ks[c * N + 2 * m + 1];
           const R q2 = a2[m];

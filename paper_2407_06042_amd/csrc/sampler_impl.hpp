@@ -1188,6 +1188,12 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
     if (live) {
       const StateOff so = state_offsets(a.Cpad, Npad);
       unsigned char* st = a.ws_state + (size_t)inst * a.state_stride;
+      if constexpr (!F64) {
+        // the energy gradient at the final state: the estimator's H^H r comes from it
+        float* egs = (float*)(st + so.eg) + (size_t)chain * Npad;
+#pragma unroll
+        for (int d = 0; d < D; ++d) egs[dim_of(d)] = valid[d] ? (float)eg[d] : 0.0f;
+      }
 #pragma unroll
       for (int rt = 0; rt < RTW; ++rt) {
         const int n0 = gdim(rt);
