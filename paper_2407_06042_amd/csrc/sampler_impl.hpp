@@ -337,11 +337,12 @@ struct Red {
   uint32_t h;
 };
 
-// Complex-plane layouts: how many of the packed matrices' passes (proposal passes first, then the
-// energy passes) a workgroup keeps in LDS for all its transitions; the rest stream from L2 every
-// transition.  128 dimensions: 3 passes of 16 KiB (two workgroups per CU); 256 dimensions: one pass of
-// 64 KiB beside the window layout's two 16-chain blocks, two otherwise (one workgroup per CU).
-constexpr int cx_lds_passes(int rt, bool win) { return rt <= 8 ? 3 : (win ? 1 : 2); }
+// Complex-plane layouts: how many half passes (one plane of a pass; proposal passes first, then the
+// energy passes) of the packed matrices a workgroup keeps in LDS for all its transitions; the rest
+// stream from L2 every transition.  128 dimensions: 3.5 passes of 16 KiB (two workgroups per CU);
+// 256 dimensions: 1.5 passes of 64 KiB beside the window layout's two 16-chain blocks, two otherwise
+// (one workgroup per CU).
+constexpr int cx_lds_halves(int rt, bool win) { return rt <= 8 ? 7 : (win ? 3 : 4); }
 
 // Template parameters: RTW row tiles of 16 dimensions per wave, WD waves per
 // chain block splitting the dimensions (RT = RTW * WD tiles in all), MG = the
@@ -425,11 +426,14 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
   constexpr size_t PASS = CX ? (size_t)RT * RT / 4 * 1024 : (size_t)RT * KB * 1024;
   const size_t mat_bytes = F64 ? 0 : (size_t)(NPP + kEPasses) * PASS;
   // complex planes: passes staged in LDS (every pass when the matrices are not read from L2)
-  constexpr int SPL = CX ? (MG ? cx_lds_passes(RT, WIN > 0) : NPP + kEPasses) : 0;
+  constexpr int SPH = CX ? (MG ? (cx_lds_halves(RT, WIN > 0) < 2 * (NPP + kEPasses) ? cx_lds_halves(RT, WIN > 0)
+                                                                          : 2 * (NPP + kEPasses))
+                              : 2 * (NPP + kEPasses))
+                       : 0;
   size_t staged = 0;
   if constexpr (F64) staged = a.frag_bytes;
   else if constexpr (!MG) staged = (RT <= 4) ? (size_t)a.frag_bytes : mat_bytes;
-  else if constexpr (CX) staged = (size_t)SPL * PASS;
+  else if constexpr (CX) staged = (size_t)SPH * (PASS / 2);
   for (size_t o = threadIdx.x * 16; o < staged; o += blockDim.x * 16)
     *(uint4*)(smem + o) = *(const uint4*)(blk + kParamBytes + o);
   const InstParams ip = *(const InstParams*)blk;
@@ -601,10 +605,10 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
         }
       }
       const uint32_t fo = opaque_zero() + (uint32_t)lane * 16;
-      // the first SPL passes from LDS (p is a compile-time index at every call), the others from L2
+      // the first SPH half passes (planes) from LDS (p, pl are compile-time indices at every call), the others from L2
       auto frag = [&](int p, int pl, int atg, int kb) -> const unsigned char* {
         const uint32_t off = fo + (uint32_t)(((p * 2 + pl) * AT + atg) * KBX + kb) * 1024u;
-        if (p < SPL) return smem + off;
+        if (p * 2 + pl < SPH) return smem + off;
         return blk + kParamBytes + off;
       };
 #pragma unroll
@@ -1278,7 +1282,10 @@ inline size_t sampler_cfg_lds(const Shape& sh, int rtw, int wd, bool mg, int wav
   const int RT = rtw * wd, KB = RT / 2;
   const size_t mat = (size_t)(p_passes(sh.pm) + kEPasses) * RT * KB * 1024;
   size_t staged = mg ? 0 : (RT <= 4 ? sh.frag_bytes : mat);
-  if (cx && mg) staged = (size_t)cx_lds_passes(RT, sh.win > 0) * RT * RT / 4 * 1024;
+  if (cx && mg) {
+    const int halves = cx_lds_halves(RT, sh.win > 0), all = 2 * (p_passes(sh.pm) + kEPasses);
+    staged = (size_t)(halves < all ? halves : all) * RT * RT / 8 * 1024;
+  }
   staged = (staged + 15) & ~(size_t)15;
   if (wd > 1) staged += (size_t)(waves / wd) * (2 * (size_t)KB * 1024 + 2 * (size_t)wd * 16 * sizeof(Red));
   if (sh.lrn) staged += kMlpLdsBytes;
