@@ -200,6 +200,61 @@ __device__ __forceinline__ void estimate_body(const EstArgs& a, const int b) {
         }
         __syncthreads();
         // residuals of the final and of the best states
+        if constexpr (std::is_same<R, float>::value && BS >= 512) {
+          // (the 256-thread workgroups, held to 96 registers, keep the loop below)
+          // On the float32 matrix cores (v_mfma_f32_16x16x4f32, exact float32 products of H and the
+          // level indices): [Re r; Im r] = y' - 2 s [Hr -Hi; Hi Hr] k over the real dimensions
+          // n = 2m (kI of antenna m), 2m + 1 (kQ), so that B[n][c] is the staged level byte of
+          // chain c.  A unit is one 16-row tile of receive antennas (its real and imaginary rows)
+          // and one 16-chain tile, for the final and the best states together; lane l holds
+          // A[l % 16][4 s + l / 16], B[4 s + l / 16][l % 16] and the outputs at rows 4 (l / 16) + j.
+          typedef float f32x4 __attribute__((ext_vector_type(4)));
+          const int lane = tid & 63, nrt = (nr + 15) >> 4, nct = (ch + 15) >> 4, ksteps = (N + 3) >> 2;
+          const R s2 = R(2) * s;
+          for (int u = tid >> 6; u < nrt * nct; u += nth >> 6) {
+            const int rt = u % nrt, ct = u / nrt;
+            const int ia = 16 * rt + (lane & 15), c = 16 * ct + (lane & 15);
+            // every load in bounds (indices clamped, values masked after), so that none is predicated
+            const int iac = ia < nr ? ia : nr - 1, cc = c < ch ? c : ch - 1;
+            f32x4 fre = {0.f, 0.f, 0.f, 0.f}, fim = fre, bre = fre, bim = fre;
+            // two K steps per pass: all their loads issue before the first product
+            constexpr int kU = 2;
+            for (int st0 = 0; st0 < ksteps; st0 += kU) {
+              R hr0[kU], hi0[kU];
+              uint8_t kf0[kU], kb0[kU];
+#pragma unroll
+              for (int u = 0; u < kU; ++u) {
+                const int n = 4 * (st0 + u) + (lane >> 4), nc = n < N ? n : N - 1, m = nc >> 1;
+                hr0[u] = hre(m, iac);
+                hi0[u] = him(m, iac);
+                kf0[u] = (uint8_t)Ks[cc * N + nc];
+                kb0[u] = (uint8_t)Kbs[cc * N + nc];
+              }
+#pragma unroll
+              for (int u = 0; u < kU; ++u) {
+                const int n = 4 * (st0 + u) + (lane >> 4);   // n >= N (K padding, steps past the end): zero
+                const bool aok = n < N && ia < nr, bok = n < N && c < ch;
+                const R hr = aok ? hr0[u] : R(0), hi = aok ? hi0[u] : R(0);
+                const R are = (n & 1) ? -hi : hr, aim = (n & 1) ? hr : hi;
+                const R kf = bok ? R(kf0[u]) : R(0), kb = bok ? R(kb0[u]) : R(0);
+                fre = __builtin_amdgcn_mfma_f32_16x16x4f32(are, kf, fre, 0, 0, 0);
+                fim = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, kf, fim, 0, 0, 0);
+                bre = __builtin_amdgcn_mfma_f32_16x16x4f32(are, kb, bre, 0, 0, 0);
+                bim = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, kb, bim, 0, 0, 0);
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int i = 16 * rt + 4 * (lane >> 4) + j;
+              if (i < nr && c < ch) {
+                rs[c * lrs + 2 * i] = ys[2 * i] - s2 * fre[j];
+                rs[c * lrs + 2 * i + 1] = ys[2 * i + 1] - s2 * fim[j];
+                const R br = ys[2 * i] - s2 * bre[j], bi = ys[2 * i + 1] - s2 * bim[j];
+                rb2[c * nr + i] = br * br + bi * bi;
+              }
+            }
+          }
+        } else
         for (int it = tid; it < ch * nr; it += nth) {
           const int c = it / nr, i = it % nr;
           const uint16_t* kf = (const uint16_t*)(Ks + c * N);   // (k_I, k_Q) of antenna m, as bytes
