@@ -202,7 +202,7 @@ __device__ __forceinline__ void estimate_body(const EstArgs& a, const int b) {
         // residuals of the final and of the best states
         if constexpr (std::is_same<R, float>::value && BS >= 512) {
           // (the 256-thread workgroups, held to 96 registers, keep the loop below)
-          // On the float32 matrix cores (v_mfma_f32_16x16x4f32, exact float32 products of H and the
+          // On the float32 matrix cores (v_mfma_f32_16x16x4f32: float32 H times the integer
           // level indices): [Re r; Im r] = y' - 2 s [Hr -Hi; Hi Hr] k over the real dimensions
           // n = 2m (kI of antenna m), 2m + 1 (kQ), so that B[n][c] is the staged level byte of
           // chain c.  A unit is one 16-row tile of receive antennas (its real and imaginary rows)
