@@ -85,6 +85,25 @@ __device__ inline void mlp_stage(const float* __restrict__ w, unsigned char* lds
     bias[i] = bf16_round(i < 64 ? w[kOffB2 + i] : w[kOffB3 + i - 64]);
 }
 
+// ReLU of 8 hidden values (accumulator registers u then v) rounded to bf16: the packed
+// conversion first, then a packed 16-bit signed maximum with 0 (a bf16 with the sign bit set is a
+// negative 16-bit integer, so this is max(x, +0) on the bf16 values, -0 and negatives to +0).
+__device__ __forceinline__ mlp_bf16x8 relu_bf16x8(mlp_f32x4 u, mlp_f32x4 v) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef short s16x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const f32x2 pr[4] = {{u[0], u[1]}, {u[2], u[3]}, {v[0], v[1]}, {v[2], v[3]}};
+  const s16x2 z = {0, 0};
+  u32x4 w;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const bf16x2 p = __builtin_convertvector(pr[q], bf16x2);
+    w[q] = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p), z));
+  }
+  return __builtin_bit_cast(mlp_bf16x8, w);
+}
+
 // Inputs of one antenna for this lane (7 features and the constant 1), rounded to bf16.
 __device__ __forceinline__ mlp_bf16x8 mlp_inputs(float f0, float f1, float f2, float f3, float f4, float f5, float f6) {
   mlp_bf16x8 x;
@@ -116,9 +135,7 @@ __device__ __forceinline__ mlp_f32x4 mlp_eval4(const unsigned char* lds, uint32_
     }
     mlp_bf16x8 a1[2];
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) a1[s][j] = (__bf16)fmaxf(z1[2 * s + (j >> 2)][j & 3], 0.0f);
+    for (int s = 0; s < 2; ++s) a1[s] = relu_bf16x8(z1[2 * s], z1[2 * s + 1]);
     mlp_f32x4 z2[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -131,9 +148,7 @@ __device__ __forceinline__ mlp_f32x4 mlp_eval4(const unsigned char* lds, uint32_
     }
     mlp_bf16x8 a2[2];
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) a2[s][j] = (__bf16)fmaxf(z2[2 * s + (j >> 2)][j & 3], 0.0f);
+    for (int s = 0; s < 2; ++s) a2[s] = relu_bf16x8(z2[2 * s], z2[2 * s + 1]);
     const bool mine = (r >> 2) == g;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
