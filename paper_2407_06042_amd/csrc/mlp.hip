@@ -35,14 +35,14 @@ static_assert(kTrainRow == DMALA_TRAIN_ROW, "training row size");
 __global__ __launch_bounds__(256) void mlp_forward_kernel(const float* __restrict__ w, const float* __restrict__ rows,
                                                           int n, int stride, float* __restrict__ out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  mlp_stage(w, lds);
+  mlp_stage<false>(w, lds);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = (blockIdx.x * 4 + wave) * 64 + (lane >> 4) * 16 + (lane & 15);
   float f[kMlpIn];
 #pragma unroll
   for (int i = 0; i < kMlpIn; ++i) f[i] = row < n ? rows[(size_t)row * stride + i] : 0.f;
-  const mlp_f32x4 o = mlp_eval4(lds, 0u, mlp_inputs(f[0], f[1], f[2], f[3], f[4], f[5], f[6]));
+  const mlp_f32x4 o = mlp_eval4<false>(lds, 0u, mlp_inputs(f[0], f[1], f[2], f[3], f[4], f[5], f[6]));
   if (row < n) {
 #pragma unroll
     for (int i = 0; i < kMlpOut; ++i) out[(size_t)row * kMlpOut + i] = o[i];
@@ -254,7 +254,7 @@ dmala_status dmala_mlp_forward(const float* weights, const float* rows, int32_t 
   if (row_stride < kMlpIn) return fail(DMALA_ERR_ARG, "row_stride must be >= %d", kMlpIn);
   if (n_rows == 0) return DMALA_OK;
   const int blocks = (n_rows + 255) / 256;
-  hipLaunchKernelGGL(mlp_forward_kernel, dim3(blocks), dim3(256), kMlpLdsBytes, (hipStream_t)stream, weights, rows,
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3(blocks), dim3(256), mlp_lds_bytes<false>(), (hipStream_t)stream, weights, rows,
                      n_rows, row_stride, out);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "mlp forward launch");

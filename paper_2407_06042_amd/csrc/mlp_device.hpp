@@ -11,13 +11,14 @@
 // antenna a_h for column c, and receives that antenna's 4 outputs.  No data
 // moves between lanes:
 //   * layer 1 for the antenna of lane group g is one MFMA per 16 hidden units
-//     whose A operand (W1) is non-zero only in the K slice 8g..8g+7 -- exactly
-//     the inputs that group g supplies in its B registers;
+//     in which only the K slice 8g..8g+7 -- the inputs that group g supplies --
+//     contributes (zero weights or zero inputs elsewhere, see MlpImage);
 //   * layers 2 and 3 take their B operand from the lane's own accumulator
 //     registers; the K order of the packed weights follows the accumulator
 //     layout (lane group h holds hidden units 16 t + 4 h + i);
-//   * the output layer of antenna a_g writes rows 4g..4g+3 of one shared
-//     accumulator tile, so lane group g ends up with the outputs of a_g.
+//   * the output layer of antenna a_g (W3, a per-group copy non-zero only in rows
+//     4g..4g+3) writes those rows of one shared accumulator tile, so lane group g
+//     ends up with the outputs of a_g.
 // 56 MFMAs per 4 x 16 network evaluations.
 #pragma once
 #include "common.hpp"
@@ -38,12 +39,22 @@ constexpr int kOffW2 = kOffB1 + kMlpHid;
 constexpr int kOffB2 = kOffW2 + kMlpHid * kMlpHid;
 constexpr int kOffW3 = kOffB2 + kMlpHid;
 constexpr int kOffB3 = kOffW3 + kMlpOut * kMlpHid;
-// LDS image: W1 fragments [4], W2 fragments [4 out tiles][2 K steps], W3 fragments [2], b2 [64], b3 [4]
-constexpr int kMlpFragW1 = 0;
-constexpr int kMlpFragW2 = 4;
-constexpr int kMlpFragW3 = 12;
-constexpr int kMlpFrags = 14;
-constexpr size_t kMlpLdsBytes = (size_t)kMlpFrags * 1024 + 64 * 4 + 4 * 4;
+// LDS image: W1 fragments, W2 fragments [4 out tiles][2 K steps], W3 fragments [4 antenna
+// groups][2 K steps] (non-zero only in the group's 4 rows), b2 [64], b3 [4].  W1 comes in one of
+// two forms (GW1):
+//   false: [4 hidden tiles], the same weights in every K slice; the B operand is masked to the
+//          K slice of the antenna group being evaluated (a select per input register);
+//   true:  [4 antenna groups][4 hidden tiles], non-zero only in the group's K slice, so the
+//          unmasked inputs can be used (12 KiB more LDS, no selects: for the kernels whose
+//          register pressure makes the selects' lane masks spill).
+template <bool GW1> struct MlpImage {
+  static constexpr int kW1 = 0;
+  static constexpr int kW2 = GW1 ? 16 : 4;
+  static constexpr int kW3 = kW2 + 8;
+  static constexpr int kFrags = kW3 + 8;
+  static constexpr size_t kBytes = (size_t)kFrags * 1024 + 64 * 4 + 4 * 4;
+};
+template <bool GW1> constexpr size_t mlp_lds_bytes() { return MlpImage<GW1>::kBytes; }
 
 // Hidden unit that K element j of lane group h feeds in K step s (layers 2, 3).
 __device__ __forceinline__ int mlp_kidx(int s, int h, int j) { return 16 * (2 * s + (j >> 2)) + 4 * h + (j & 3); }
@@ -59,28 +70,30 @@ __device__ __forceinline__ uint32_t opaque_zero_u32() {
 
 // Build the LDS image of the network from the flat float32 parameters (all
 // threads of the block take part; the caller synchronises afterwards).
+template <bool GW1>
 __device__ inline void mlp_stage(const float* __restrict__ w, unsigned char* lds) {
-  for (int it = threadIdx.x; it < kMlpFrags * 64; it += blockDim.x) {
+  using I = MlpImage<GW1>;
+  for (int it = threadIdx.x; it < I::kFrags * 64; it += blockDim.x) {
     const int f = it >> 6, l = it & 63, r = l & 15, h = l >> 4;
     mlp_bf16x8 v;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       float x;
-      if (f < kMlpFragW2) {
-        const int u = 16 * f + r;
-        x = j < kMlpIn ? w[kOffW1 + u * kMlpIn + j] : w[kOffB1 + u];
-      } else if (f < kMlpFragW3) {
-        const int ot = (f - kMlpFragW2) >> 1, s = (f - kMlpFragW2) & 1;
+      if (f < I::kW2) {
+        const int u = 16 * (f & 3) + r;
+        x = (GW1 && h != (f >> 2)) ? 0.0f : (j < kMlpIn ? w[kOffW1 + u * kMlpIn + j] : w[kOffB1 + u]);
+      } else if (f < I::kW3) {
+        const int ot = (f - I::kW2) >> 1, s = (f - I::kW2) & 1;
         x = w[kOffW2 + (16 * ot + r) * kMlpHid + mlp_kidx(s, h, j)];
       } else {
-        const int s = f - kMlpFragW3;
-        x = w[kOffW3 + (r & 3) * kMlpHid + mlp_kidx(s, h, j)];
+        const int g = (f - I::kW3) >> 1, s = (f - I::kW3) & 1;
+        x = (r >> 2) != g ? 0.0f : w[kOffW3 + (r & 3) * kMlpHid + mlp_kidx(s, h, j)];
       }
       v[j] = (__bf16)x;
     }
     *(mlp_bf16x8*)(lds + (size_t)f * 1024 + l * 16) = v;
   }
-  float* bias = (float*)(lds + (size_t)kMlpFrags * 1024);
+  float* bias = (float*)(lds + (size_t)I::kFrags * 1024);
   for (int i = threadIdx.x; i < 64 + 4; i += blockDim.x)
     bias[i] = bf16_round(i < 64 ? w[kOffB2 + i] : w[kOffB3 + i - 64]);
 }
@@ -116,22 +129,27 @@ __device__ __forceinline__ mlp_bf16x8 mlp_inputs(float f0, float f1, float f2, f
 // lane receives the 4 outputs of its own antenna.  All 64 lanes must call it.
 // `lds_off` must be an LDS byte offset hidden from the optimiser (so that the
 // fragments are reloaded per call instead of being pinned in registers).
+template <bool GW1>
 __device__ __forceinline__ mlp_f32x4 mlp_eval4(const unsigned char* lds, uint32_t lds_off, mlp_bf16x8 x) {
-  const int lane = threadIdx.x & 63, h = lane >> 4, r = lane & 15;
-  const float* bias = (const float*)(lds + lds_off + (size_t)kMlpFrags * 1024);
+  using I = MlpImage<GW1>;
+  const int lane = threadIdx.x & 63, h = lane >> 4;
+  const float* bias = (const float*)(lds + lds_off + (size_t)I::kFrags * 1024);
   mlp_f32x4 out = *(const mlp_f32x4*)(bias + 64);
-  const mlp_bf16x8 zero8 = {};
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     // fragments are re-read for every antenna group (an opaque offset keeps the
     // compiler from holding all 14 of them in registers across the groups)
     const unsigned char* base = lds + lds_off + opaque_zero_u32() + (uint32_t)lane * 16;
+    // only the K slice of antenna group g may contribute: zero weights elsewhere (GW1) or
+    // zero inputs of the other groups
+    const mlp_bf16x8 zero8 = {};
+    const mlp_bf16x8 xg = (GW1 || h == g) ? x : zero8;
     mlp_f32x4 z1[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const mlp_f32x4 c0 = {0.f, 0.f, 0.f, 0.f};
-      const mlp_bf16x8 w1 = *(const mlp_bf16x8*)(base + (kMlpFragW1 + t) * 1024);
-      z1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h == g ? w1 : zero8, x, c0, 0, 0, 0);
+      const mlp_bf16x8 w1 = *(const mlp_bf16x8*)(base + (I::kW1 + (GW1 ? 4 * g : 0) + t) * 1024);
+      z1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, xg, c0, 0, 0, 0);
     }
     mlp_bf16x8 a1[2];
 #pragma unroll
@@ -142,18 +160,17 @@ __device__ __forceinline__ mlp_f32x4 mlp_eval4(const unsigned char* lds, uint32_
       z2[t] = *(const mlp_f32x4*)(bias + 16 * t + 4 * h);
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        const mlp_bf16x8 w2 = *(const mlp_bf16x8*)(base + (kMlpFragW2 + 2 * t + s) * 1024);
+        const mlp_bf16x8 w2 = *(const mlp_bf16x8*)(base + (I::kW2 + 2 * t + s) * 1024);
         z2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2, a1[s], z2[t], 0, 0, 0);
       }
     }
     mlp_bf16x8 a2[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) a2[s] = relu_bf16x8(z2[2 * s], z2[2 * s + 1]);
-    const bool mine = (r >> 2) == g;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      const mlp_bf16x8 w3 = *(const mlp_bf16x8*)(base + (kMlpFragW3 + s) * 1024);
-      out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mine ? w3 : zero8, a2[s], out, 0, 0, 0);
+      const mlp_bf16x8 w3 = *(const mlp_bf16x8*)(base + (I::kW3 + 2 * g + s) * 1024);
+      out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, a2[s], out, 0, 0, 0);
     }
   }
   return out;

@@ -101,6 +101,10 @@ constexpr int kCtabStride = 12;
 constexpr size_t kCtabBytes = 16 * kCtabStride * sizeof(float);  // up to Q = 16
 // every layout but one wave of 8 LDS row tiles (whose matrices take all 160 KiB at fp32)
 constexpr bool win_table(int rtw, int wd, bool mg) { return !(rtw == 8 && wd == 1 && !mg); }
+// form of the network's first-layer weights in LDS: per-group copies for the dimension-split
+// kernels (whose register pressure makes the input selects spill), one copy elsewhere (where the
+// 12 KiB more would lower the number of workgroups per CU)
+constexpr bool mlp_gw1(int wd) { return wd > 1; }
 
 template <int Q>
 __device__ __forceinline__ void ctab_fill(float* ctab, float kL) {
@@ -445,13 +449,13 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
   rbuf += (size_t)slot * 2 * WD * 16;
   // window coefficients: a per-mode LDS table, except where the matrices fill the LDS
   constexpr bool TAB = WIN > 0 && win_table(RTW, WD, MG);
-  float* ctab_p = (float*)(mlp_lds + (LRN ? kMlpLdsBytes : 0));
+  float* ctab_p = (float*)(mlp_lds + (LRN ? mlp_lds_bytes<mlp_gw1(WD)>() : 0));
   WinCoef wc;
   wc.tab = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) float*)ctab_p;
   wc.dmax = fmaxf(0.5f, 12.5f / (float)ip.kL);
 #pragma unroll
   for (int o = 0; o < 4; ++o) wc.c[o] = ex2(-(float)ip.kL * float(o * o));
-  if constexpr (LRN) mlp_stage(a.mlp, mlp_lds);
+  if constexpr (LRN) mlp_stage<mlp_gw1(WD)>(a.mlp, mlp_lds);
   if constexpr (TAB) ctab_fill<Q>(ctab_p, (float)ip.kL);
   __syncthreads();
 
@@ -845,7 +849,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
       for (int i2 = 0; i2 < 2; ++i2) {
         float f[kMlpIn];
         feats(k, m, rt, i2, f);
-        const mlp_f32x4 o = mlp_eval4(mlp_lds, mo, mlp_inputs(f[0], f[1], f[2], f[3], f[4], f[5], f[6]));
+        const mlp_f32x4 o = mlp_eval4<mlp_gw1(WD)>(mlp_lds, mo, mlp_inputs(f[0], f[1], f[2], f[3], f[4], f[5], f[6]));
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
           const int d = rt * 4 + 2 * i2 + p;
@@ -1288,7 +1292,7 @@ inline size_t sampler_cfg_lds(const Shape& sh, int rtw, int wd, bool mg, int wav
   }
   staged = (staged + 15) & ~(size_t)15;
   if (wd > 1) staged += (size_t)(waves / wd) * (2 * (size_t)KB * 1024 + 2 * (size_t)wd * 16 * sizeof(Red));
-  if (sh.lrn) staged += kMlpLdsBytes;
+  if (sh.lrn) staged += wd > 1 ? mlp_lds_bytes<mlp_gw1(2)>() : mlp_lds_bytes<mlp_gw1(1)>();
   if (sh.win > 0 && win_table(rtw, wd, mg)) staged += kCtabBytes;
   return staged;
 }
