@@ -98,13 +98,15 @@ __device__ __forceinline__ float via_float(double v) {
 // holds plane(X)[16 at + l%16][16 (2 kb + j/4) + 4 (l/16) + j%4] -- the same K permutation over
 // antennas that the real-equivalent packing applies to real dimensions.
 __device__ float pack_fragments(const cd* X, int ld, double c, int nt, int N, int RT, int KB, int npass, int bf16,
-                                unsigned char* dst, double* red, int cx) {
+                                unsigned char* dst, int cx) {
+  // X is Hermitian positive semidefinite (G, and A = I - gamma M, whose eigenvalues lie in [0, 1)),
+  // so |Re x_ij|, |Im x_ij| <= |x_ij| <= sqrt(x_ii x_jj) <= max_i x_ii: the largest entry is the
+  // largest diagonal one.  Every wavefront reads the diagonal and reduces it for itself (no barrier).
   double mx = 0.0;
-  for (int e = threadIdx.x; e < nt * nt; e += blockDim.x) {
-    const cd v = X[(e / nt) * ld + e % nt];
-    mx = fmax(mx, fmax(fabs(v.re), fabs(v.im)));
-  }
-  mx = block_reduce(mx, red, true) * fabs(c);
+  for (int i = threadIdx.x & 63; i < nt; i += 64) mx = fmax(mx, fabs(X[i * ld + i].re));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  mx *= fabs(c);
   int ex = 0;
   if (mx > 0.0) frexp(mx, &ex);
   const int e2 = 14 - ex;  // scaled max in [2^13, 2^14)
@@ -112,6 +114,8 @@ __device__ float pack_fragments(const cd* X, int ld, double c, int nt, int N, in
   const int AT = RT / 2, KBX = RT / 4;
   const size_t pass_stride = cx ? (size_t)2 * AT * KBX * 1024 : (size_t)RT * KB * 1024;
   const int items = (int)(pass_stride / 16);
+  // two items per trip: their load-convert-store chains are independent
+#pragma unroll 2
   for (int it = threadIdx.x; it < items; it += blockDim.x) {
     const int l = it & 63;
     const int t = it >> 6;
@@ -339,7 +343,7 @@ __device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
     double* ezd = (double*)(blk + kParamBytes) + 2 * (size_t)Npad * Npad + Npad;
     for (int n = tid; n < Npad; n += blockDim.x) ezd[n] = n < N ? cz * realeq_vec(z, n) : 0.0;
   } else {
-    scaleE = pack_fragments(W, ld, cE, nt, N, a.RT, a.KB, kEPasses, 0, frag + (size_t)npP * pass_bytes, red, a.cx);
+    scaleE = pack_fragments(W, ld, cE, nt, N, a.RT, a.KB, kEPasses, 0, frag + (size_t)npP * pass_bytes, a.cx);
     float* ezf = (float*)(frag + (size_t)(npP + kEPasses) * pass_bytes) + Npad;
     for (int n = tid; n < Npad; n += blockDim.x) ezf[n] = n < N ? (float)(cz * realeq_vec(z, n)) : 0.0f;
     float* afv = ezf + Npad;
@@ -528,7 +532,7 @@ __device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
       double* pbd = (double*)(blk + kParamBytes) + 2 * (size_t)Npad * Npad;
       for (int n = tid; n < Npad; n += blockDim.x) pbd[n] = n < N ? cb * realeq_vec(bv, n) : 0.0;
     } else {
-      scaleP = pack_fragments(W, ld, cP, nt, N, a.RT, a.KB, npP, a.pm == PM_BF16X1, frag, red, a.cx);
+      scaleP = pack_fragments(W, ld, cP, nt, N, a.RT, a.KB, npP, a.pm == PM_BF16X1, frag, a.cx);
       float* pbf = (float*)(frag + (size_t)(npP + kEPasses) * pass_bytes);
       for (int n = tid; n < Npad; n += blockDim.x) pbf[n] = n < N ? (float)(cb * realeq_vec(bv, n)) : 0.0f;
     }
