@@ -61,6 +61,8 @@ __device__ __forceinline__ void lds_read4(uint32_t a, d2v (&r)[4]) {
       : "memory");
 }
 
+constexpr int kRedSlots = 16;   // one per wavefront of a workgroup of up to 1024 threads
+
 // Sum (or maximum) of v over the workgroup, returned to every thread: a butterfly within each
 // wavefront, then one pass over the per-wave partials in a fixed order (two barriers).
 __device__ double block_reduce(double v, double* red, bool is_max) {
@@ -114,8 +116,6 @@ __device__ float pack_fragments(const cd* X, int ld, double c, int nt, int N, in
   const int AT = RT / 2, KBX = RT / 4;
   const size_t pass_stride = cx ? (size_t)2 * AT * KBX * 1024 : (size_t)RT * KB * 1024;
   const int items = (int)(pass_stride / 16);
-  // two items per trip: their load-convert-store chains are independent
-#pragma unroll 2
   for (int it = threadIdx.x; it < items; it += blockDim.x) {
     const int l = it & 63;
     const int t = it >> 6;
@@ -189,7 +189,7 @@ __device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
   cd* bv = z + nt;
   cd* rowp = bv + nt;       // 2 x 2 x nt (alternating Gauss-Jordan steps, two pivot rows each)
   cd* colp = rowp + 4 * nt; // 2 x 2 x nt
-  double* red = (double*)(colp + 4 * nt);
+  double* red = (double*)(colp + 4 * nt);   // kRedSlots partials of block_reduce
   unsigned char* blk = a.ws_inst + (size_t)b * a.inst_stride;
 
   const int Q = a.Q, M = Q * Q;
@@ -219,7 +219,7 @@ __device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
     static_assert(P >= 1 && 64 % P == 0, "the threads of an antenna share a wavefront");
     // kIC x ld, then one spare row; with the working matrix in LDS (33 to 64
     // antennas) the staging buffer is its first rows, written only after the last read
-    cd* Ht = (!WGLOB && RMAX > 32) ? W : (cd*)(red + BS);
+    cd* Ht = (!WGLOB && RMAX > 32) ? W : (cd*)(red + kRedSlots);
     const int lane = tid & 63, wv = tid >> 6;
     const int ntr = (nt + 15) >> 4, ntiles = ntr * (ntr + 1) / 2;
     int m0[kTPW], m1[kTPW];
@@ -356,62 +356,68 @@ __device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
 
   if (!a.naive) {
     // W <- (G + gamma I)^-1 by in-place Gauss-Jordan with the working matrix in
-    // registers, in S x S blocks on a T x T thread grid: thread (ti, tj) keeps
-    // rows ti + T a and columns tj + T c (a, c < S) for the whole sweep.  A step
-    // on pivot p: the owners of column p publish it (colp); the threads of row p,
-    // which share a wavefront with the pivot, read the pivot from its lane, scale
+    // registers, in SR x SC blocks on a TR x TC thread grid: thread (ti, tj) keeps
+    // rows ti + TR a (a < SR) and columns tj + TC c (c < SC) for the whole sweep.  A
+    // step on pivot p: the owners of column p publish it (colp); the threads of row
+    // p, which share a wavefront with the pivot, read the pivot from its lane, scale
     // their row by its inverse (the inverse itself in column p) and publish it
-    // (rowp); after one barrier every other row i clears its column p and
-    // subtracts colp[i] * rowp, which leaves -w_ip / w_pp there.  Per step a
-    // thread reads S entries of each vector for S^2 updates.  The steps on
-    // different pivots commute (G + gamma I is Hermitian positive definite, so
-    // every pivot stays nonzero in any order), so they run in the order
-    // p = o + T kb, o outer: row and column p then sit in register slot kb, a
-    // compile-time index of the unrolled inner loop.  The two vectors alternate
-    // between steps, so one barrier per step orders all reads and writes.
-    constexpr int T = BS >= 1024 ? 32 : 16;
-    constexpr int S = RMAX / T;
-    static_assert(T * T == BS && S * T == RMAX && 64 % T == 0, "square thread grid, a row's threads in one wavefront");
-    const int ti = tid / T, tj = tid % T;
-    cd w[S][S];
+    // (rowp); after one barrier every other row i clears its column p and subtracts
+    // colp[i] * rowp, which leaves -w_ip / w_pp there.  Per step a thread reads SC
+    // entries of the row vector and SR of the column for SR SC updates.  The steps on
+    // different pivots commute (G + gamma I is Hermitian positive definite, so every
+    // pivot stays nonzero in any order), so they run in the order p = o + TR kb, o
+    // outer: row p then sits in register slot kb and column p in slot kb / (TC / TR)
+    // of thread column o + TR (kb % (TC / TR)), compile-time indices of the unrolled
+    // inner loop.  The two vectors alternate between steps, so one barrier per step
+    // orders all reads and writes.
+    constexpr int TR = BS >= 1024 ? 32 : 16;
+    constexpr int TC = BS / TR;
+    constexpr int SR = RMAX / TR, SC = RMAX / TC;
+    static_assert(TR * TC == BS && SR * TR == RMAX && SC * TC == RMAX && TC % TR == 0 && 64 % TC == 0,
+                  "thread grid: a row's threads in one wavefront");
+    const int ti = tid / TC, tj = tid % TC;
+    cd w[SR][SC];
 #pragma unroll
-    for (int ra = 0; ra < S; ++ra)
+    for (int ra = 0; ra < SR; ++ra)
 #pragma unroll
-      for (int c = 0; c < S; ++c) {
-        const int i = ti + T * ra, j = tj + T * c;
+      for (int c = 0; c < SC; ++c) {
+        const int i = ti + TR * ra, j = tj + TC * c;
         w[ra][c] = (i < nt && j < nt) ? W[i * ld + j] : cd{0.0, 0.0};
         if (i == j && i < nt) w[ra][c].re += gamma;
       }
     // Pivots are taken two at a time where they can be (rows p and p + 1 of the same
     // register slot, owned by thread rows o and o + 1 of one wavefront): the 2 x 2
     // pivot block B is inverted in registers, rows p and p + 1 become B^-1 times
-    // themselves (the partner row's entries come from lane + T), and every other row
+    // themselves (the partner row's entries come from lane + TC), and every other row
     // subtracts colp0[i] * rowp0 + colp1[i] * rowp1 -- one barrier per two pivots.
     // (1024 threads: single pivots, as the pair step would not fit in 128 registers.)
     constexpr bool kPair = BS < 1024;
     int par = 0;
 #pragma unroll 1
-    for (int o = 0; o < T && o < nt; o += kPair ? 2 : 1) {
+    for (int o = 0; o < TR && o < nt; o += kPair ? 2 : 1) {
 #pragma unroll
-      for (int kb = 0; kb < S; ++kb) {
-        const int p = o + T * kb;
+      for (int kb = 0; kb < SR; ++kb) {
+        const int p = o + TR * kb;
         if (p >= nt) continue;
+        constexpr int kR = TC / TR;
+        const int cs = kb / kR;              // column slot of p (compile time)
+        const int po = o + TR * (kb % kR);   // thread column that owns column p
         cd* rp = rowp + par * 2 * nt;
         cd* cp = colp + par * 2 * nt;
         par ^= 1;
         if (kPair && p + 1 < nt) {
-          if (tj == o || tj == o + 1) {
-            cd* cpx = cp + (tj == o ? 0 : nt);
+          if (tj == po || tj == po + 1) {
+            cd* cpx = cp + (tj == po ? 0 : nt);
 #pragma unroll
-            for (int ra = 0; ra < S; ++ra)
-              if (ti + T * ra < nt) cpx[ti + T * ra] = w[ra][kb];
+            for (int ra = 0; ra < SR; ++ra)
+              if (ti + TR * ra < nt) cpx[ti + TR * ra] = w[ra][cs];
           }
-          if (tid >> 6 == (o * T) >> 6) {   // the wavefront of rows p and p + 1
-            const int l0 = (o * T + o) & 63;
-            const cd pa = {readlane_f64(w[kb][kb].re, l0), readlane_f64(w[kb][kb].im, l0)};
-            const cd pb = {readlane_f64(w[kb][kb].re, l0 + 1), readlane_f64(w[kb][kb].im, l0 + 1)};
-            const cd pc = {readlane_f64(w[kb][kb].re, l0 + T), readlane_f64(w[kb][kb].im, l0 + T)};
-            const cd pd = {readlane_f64(w[kb][kb].re, l0 + T + 1), readlane_f64(w[kb][kb].im, l0 + T + 1)};
+          if (tid >> 6 == (o * TC) >> 6) {   // the wavefront of rows p and p + 1
+            const int l0 = (o * TC + po) & 63;
+            const cd pa = {readlane_f64(w[kb][cs].re, l0), readlane_f64(w[kb][cs].im, l0)};
+            const cd pb = {readlane_f64(w[kb][cs].re, l0 + 1), readlane_f64(w[kb][cs].im, l0 + 1)};
+            const cd pc = {readlane_f64(w[kb][cs].re, l0 + TC), readlane_f64(w[kb][cs].im, l0 + TC)};
+            const cd pd = {readlane_f64(w[kb][cs].re, l0 + TC + 1), readlane_f64(w[kb][cs].im, l0 + TC + 1)};
             const cd det = {pa.re * pd.re - pa.im * pd.im - (pb.re * pc.re - pb.im * pc.im),
                             pa.re * pd.im + pa.im * pd.re - (pb.re * pc.im + pb.im * pc.re)};
             const double rd = 1.0 / (det.re * det.re + det.im * det.im);
@@ -421,36 +427,36 @@ __device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
             const bool top = ti == o;
             const cd qs = top ? q00 : q11, qo = top ? q01 : q10;   // own row, partner row
 #pragma unroll
-            for (int c = 0; c < S; ++c) {
-              const cd oth = {__shfl_xor(w[kb][c].re, T, 64), __shfl_xor(w[kb][c].im, T, 64)};
+            for (int c = 0; c < SC; ++c) {
+              const cd oth = {__shfl_xor(w[kb][c].re, TC, 64), __shfl_xor(w[kb][c].im, TC, 64)};
               if (ti == o || ti == o + 1) w[kb][c] = cadd(cmul(qs, w[kb][c]), cmul(qo, oth));
             }
             if (ti == o || ti == o + 1) {
-              if (tj == o) w[kb][kb] = top ? q00 : q10;
-              if (tj == o + 1) w[kb][kb] = top ? q01 : q11;
+              if (tj == po) w[kb][cs] = top ? q00 : q10;
+              if (tj == po + 1) w[kb][cs] = top ? q01 : q11;
               cd* rpx = rp + (top ? 0 : nt);
 #pragma unroll
-              for (int c = 0; c < S; ++c)
-                if (tj + T * c < nt) rpx[tj + T * c] = w[kb][c];
+              for (int c = 0; c < SC; ++c)
+                if (tj + TC * c < nt) rpx[tj + TC * c] = w[kb][c];
             }
           }
           __syncthreads();
           // row entries past column nt - 1 read whatever follows the row vectors in LDS
           // (inside the allocation); they update register entries that are never stored
-          cd r0[S], r1[S];
+          cd r0[SC], r1[SC];
 #pragma unroll
-          for (int c = 0; c < S; ++c) {
-            r0[c] = rp[tj + T * c];
-            r1[c] = rp[nt + tj + T * c];
+          for (int c = 0; c < SC; ++c) {
+            r0[c] = rp[tj + TC * c];
+            r1[c] = rp[nt + tj + TC * c];
           }
 #pragma unroll
-          for (int ra = 0; ra < S; ++ra) {
-            const int i = ti + T * ra;
+          for (int ra = 0; ra < SR; ++ra) {
+            const int i = ti + TR * ra;
             if (i < nt && i != p && i != p + 1) {
               const cd c0 = cp[i], c1 = cp[nt + i];
-              if (tj == o || tj == o + 1) w[ra][kb] = {0.0, 0.0};
+              if (tj == po || tj == po + 1) w[ra][cs] = {0.0, 0.0};
 #pragma unroll
-              for (int c = 0; c < S; ++c) {
+              for (int c = 0; c < SC; ++c) {
                 cd& v = w[ra][c];
                 v.re = fma(-c0.re, r0[c].re, fma(c0.im, r0[c].im, v.re));
                 v.im = fma(-c0.re, r0[c].im, fma(-c0.im, r0[c].re, v.im));
@@ -461,35 +467,35 @@ __device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
           }
         } else {
           // a single pivot (1024 threads, or the last row of a slot that nt leaves unpaired)
-          if (tj == o) {
+          if (tj == po) {
 #pragma unroll
-            for (int ra = 0; ra < S; ++ra)
-              if (ti + T * ra < nt) cp[ti + T * ra] = w[ra][kb];
+            for (int ra = 0; ra < SR; ++ra)
+              if (ti + TR * ra < nt) cp[ti + TR * ra] = w[ra][cs];
           }
           if (ti == o) {
-            const int l0 = (o * T + o) & 63;
-            const cd piv = {readlane_f64(w[kb][kb].re, l0), readlane_f64(w[kb][kb].im, l0)};
+            const int l0 = (o * TC + po) & 63;
+            const cd piv = {readlane_f64(w[kb][cs].re, l0), readlane_f64(w[kb][cs].im, l0)};
             const double rd = 1.0 / (piv.re * piv.re + piv.im * piv.im);
             const cd inv = {piv.re * rd, -piv.im * rd};
 #pragma unroll
-            for (int c = 0; c < S; ++c) w[kb][c] = cmul(w[kb][c], inv);
-            if (tj == o) w[kb][kb] = inv;
+            for (int c = 0; c < SC; ++c) w[kb][c] = cmul(w[kb][c], inv);
+            if (tj == po) w[kb][cs] = inv;
 #pragma unroll
-            for (int c = 0; c < S; ++c)
-              if (tj + T * c < nt) rp[tj + T * c] = w[kb][c];
+            for (int c = 0; c < SC; ++c)
+              if (tj + TC * c < nt) rp[tj + TC * c] = w[kb][c];
           }
           __syncthreads();
-          cd r[S];
+          cd r[SC];
 #pragma unroll
-          for (int c = 0; c < S; ++c) r[c] = rp[tj + T * c];
+          for (int c = 0; c < SC; ++c) r[c] = rp[tj + TC * c];
 #pragma unroll
-          for (int ra = 0; ra < S; ++ra) {
-            const int i = ti + T * ra;
+          for (int ra = 0; ra < SR; ++ra) {
+            const int i = ti + TR * ra;
             if (i < nt && i != p) {
               const cd ci = cp[i];
-              if (tj == o) w[ra][kb] = {0.0, 0.0};
+              if (tj == po) w[ra][cs] = {0.0, 0.0};
 #pragma unroll
-              for (int c = 0; c < S; ++c) {
+              for (int c = 0; c < SC; ++c) {
                 cd& v = w[ra][c];
                 v.re = fma(-ci.re, r[c].re, fma(ci.im, r[c].im, v.re));
                 v.im = fma(-ci.re, r[c].im, fma(-ci.im, r[c].re, v.im));
@@ -499,32 +505,34 @@ __device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
         }
       }
     }
-    // From the registers of M's blocks: b = M z (each thread's columns, then summed over the T
+    // From the registers of M's blocks: b = M z (each thread's columns, then summed over the TC
     // threads of a row, which every one of them ends with bit for bit), the preconditioned
     // variance feature from M's diagonal, and A = I - gamma M written back over the matrix.
     float* afv = (float*)(frag + (size_t)(npP + kEPasses) * pass_bytes) + 2 * Npad;
-    cd zc[S];
+    cd zc[SC];
 #pragma unroll
-    for (int c = 0; c < S; ++c) zc[c] = tj + T * c < nt ? z[tj + T * c] : cd{0.0, 0.0};
+    for (int c = 0; c < SC; ++c) zc[c] = tj + TC * c < nt ? z[tj + TC * c] : cd{0.0, 0.0};
 #pragma unroll
-    for (int ra = 0; ra < S; ++ra) {
-      const int i = ti + T * ra;
+    for (int ra = 0; ra < SR; ++ra) {
+      const int i = ti + TR * ra;
       cd bp = {0.0, 0.0};
 #pragma unroll
-      for (int c = 0; c < S; ++c) {
-        const int j = tj + T * c;
+      for (int c = 0; c < SC; ++c) {
+        const int j = tj + TC * c;
         // register entries of columns j >= nt hold whatever the sweep read past the row
         // vectors (possibly not finite): they are left out, not multiplied by zero
         if (j < nt) bp = cadd(bp, cmul(w[ra][c], zc[c]));
         if (i < nt && j < nt) W[i * ld + j] = {(j == i ? 1.0 : 0.0) - gamma * w[ra][c].re, -gamma * w[ra][c].im};
       }
 #pragma unroll
-      for (int o = T >> 1; o > 0; o >>= 1) {
+      for (int o = TC >> 1; o > 0; o >>= 1) {
         bp.re += __shfl_xor(bp.re, o, 64);
         bp.im += __shfl_xor(bp.im, o, 64);
       }
       if (i < nt && tj == 0) bv[i] = bp;
-      if (i < nt && tj == ti && !a.fp64) afv[2 * i] = (float)(log2(sigma2 * w[ra][ra].re / (8.0 * s * s)) / 8.0);
+      // diagonal entry (i, i): thread column ti + TR (ra % (TC / TR)), slot ra / (TC / TR)
+      if (i < nt && tj == ti + TR * (ra % (TC / TR)) && !a.fp64)
+        afv[2 * i] = (float)(log2(sigma2 * w[ra][ra / (TC / TR)].re / (8.0 * s * s)) / 8.0);
     }
     __syncthreads();
     if (a.fp64) {
@@ -564,7 +572,7 @@ __device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
 // Direct launch (PERS false): instance blockIdx.x.  Persistent launch: items from the list, each
 // with its class's arguments.
 template <typename TIn, bool WGLOB, int BS, int RMAX, bool PERS = false>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RMAX <= 32 ? 5 : (BS == 256 ? 2 : 1))))
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RMAX <= 32 ? 5 : (BS == 512 ? 4 : (BS == 256 ? 2 : 1)))))
 void setup_kernel(SetupArgs a, Persist p) {
   if constexpr (!PERS) {
     setup_body<TIn, WGLOB, BS, RMAX>(a, blockIdx.x);
@@ -588,7 +596,7 @@ hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s, const Persist* p, 
   if (WG != setup_w_global(a.nt) || a.nt > RMAX) return hipErrorInvalidValue;
   constexpr int kIC = RMAX <= 32 ? 16 : 32;
   const bool alias = !WG && RMAX > 32;   // the staging buffer is the working matrix's first rows
-  const size_t lds = (size_t)((WG ? 0 : a.nt * (a.nt + 1)) + 10 * a.nt) * sizeof(cd) + BS * sizeof(double) +
+  const size_t lds = (size_t)((WG ? 0 : a.nt * (a.nt + 1)) + 10 * a.nt) * sizeof(cd) + kRedSlots * sizeof(double) +
                      (alias ? 0 : (kIC * (size_t)(a.nt + 1) + 32) * sizeof(cd));
   void (*k)(SetupArgs, Persist);
   if (p || cfg) k = a.fp64 ? setup_kernel<double, WG, BS, RMAX, true> : setup_kernel<float, WG, BS, RMAX, true>;
@@ -619,7 +627,7 @@ hipError_t launch_setup_bs(const SetupArgs& a, hipStream_t s, const Persist* p, 
 // holds only the staging buffers: 1024 threads.
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s, const Persist* p, int gn, KernelCfg* cfg) {
   if (a.nt <= 32) return launch_setup_bs<256, false, 32>(a, s, p, gn, cfg);
-  return a.nt <= 64 ? launch_setup_bs<256, false, 64>(a, s, p, gn, cfg) : launch_setup_bs<1024, true, 128>(a, s, p, gn, cfg);
+  return a.nt <= 64 ? launch_setup_bs<512, false, 64>(a, s, p, gn, cfg) : launch_setup_bs<1024, true, 128>(a, s, p, gn, cfg);
 }
 
 }  // namespace dmala
