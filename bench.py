@@ -163,6 +163,12 @@ class HipEvents:
         return ms.value
 
 
+# the estimator's outputs written in every timed step: the hard decision, the bit LLRs and the
+# symbol marginals (all of them are computed whichever are requested; requesting them all makes
+# the timed step store them too)
+EST_OUTPUTS = ("symbols", "llrs", "marginals")
+
+
 def time_detector(det, args_, steps, warmup):
     """Mean step and stage times (HIP events on the launch stream) of a Detector over `steps` calls."""
     import torch
@@ -282,7 +288,7 @@ def matched_ser_sweep(dm, torch, b, w, sweep, ref_T, reps):
         prec, prop = ("bf16", "learned") if form == "bf16+learned" else (form, "precond")
         for T in Ts:
             kw = dict(mlp_weights=w, mix_eps=0.1) if prop == "learned" else {}
-            det = dm.Detector(B, nt, nt, M, C5_C, T, SEED, prec, prop, outputs=("symbols", "accept_count"), **kw)
+            det = dm.Detector(B, nt, nt, M, C5_C, T, SEED, prec, prop, outputs=EST_OUTPUTS + ("accept_count",), **kw)
             out, tm = time_detector(det, (Hc, yc, sc), reps, 1)
             sym = out["symbols"].cpu().numpy()
             errs[(form, T)] = (sym != b.x_idx).reshape(-1).astype(np.float64)
@@ -321,7 +327,7 @@ def extra_uniform(dm, torch, b, C, T, forms, steps, warmup, snr_split=None, tile
     B = len(b.sigma2)
     res = {}
     for f in forms:
-        det = dm.Detector(B, b.nt, b.nr, b.M, C, T, SEED, f, "precond", outputs=("symbols",), tile_config=tile)
+        det = dm.Detector(B, b.nt, b.nr, b.M, C, T, SEED, f, "precond", outputs=EST_OUTPUTS, tile_config=tile)
         out, tm = time_detector(det, (Hc, yc, sc), steps, warmup)
         err = out["symbols"].cpu().numpy() != b.x_idx
         r = dict(tm, chain_iters_per_s=B * C * T / (tm["step_ms"] * 1e-3), vectors_per_s=B / (tm["step_ms"] * 1e-3),
@@ -341,7 +347,7 @@ def extra_uneven(dm, torch, forms, steps, warmup, autotune=None):
     truth = np.concatenate(d["x_idx"])
     res = {}
     for f in forms:
-        plan = dm.Plan(shapes, C, T, SEED, precision=f, outputs=("symbols",))
+        plan = dm.Plan(shapes, C, T, SEED, precision=f, outputs=EST_OUTPUTS)
         if autotune:
             plan.autotune(H, y, sig, autotune)
         ev = HipEvents(2 * steps)
@@ -450,7 +456,7 @@ def main():
     # headline: plain fp32 form at 100 transitions
     B = len(c5.sigma2)
     Hc, yc, sc = dm.device_inputs(c5.H, c5.y, c5.sigma2)
-    det = dm.Detector(B, C5_NT, C5_NT, C5_M, C5_C, C5_T, SEED, "fp32", "precond", outputs=("symbols",))
+    det = dm.Detector(B, C5_NT, C5_NT, C5_M, C5_C, C5_T, SEED, "fp32", "precond", outputs=EST_OUTPUTS)
     out, tm = time_detector(det, (Hc, yc, sc), args.steps, args.warmup)
     err = out["symbols"].cpu().numpy() != c5.x_idx
     ci = B * C5_C * C5_T
@@ -534,7 +540,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "64x64 64-QAM i.i.d. Rayleigh CN(0,1/Nr), SNR 20:2:26 dB x 2048 realisations "
                                "(8192 problems), 32 chains x 100 transitions, preconditioned DMALA, tau=2, "
-                               "fp32-class (fp16-split MFMA)", "instances": B, "chains": C5_C, "iters": C5_T},
+                               "fp32-class (fp16-split MFMA); each step writes hard decisions, IS bit LLRs and "
+                               "symbol marginals", "instances": B, "chains": C5_C, "iters": C5_T},
         "vectors_per_s": B / (tm["step_ms"] * 1e-3),
         "ser": {str(s): float(err[k * 2048:(k + 1) * 2048].mean()) for k, s in enumerate(C5_SNRS)},
         "stage_ms": tm,
