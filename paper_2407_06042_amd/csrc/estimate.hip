@@ -37,17 +37,12 @@ struct OnlineLse {
   R mx, sum;
   __device__ OnlineLse() : mx(-INFINITY), sum(R(0)) {}
   __device__ __forceinline__ void add(R v) {  // branch-free: both lanes of a divergent update cost the same
-    const R m2 = v > mx ? v : mx;
+    const R m2 = fmax(v, mx);
     sum = sum * fexp(mx - m2) + fexp(v - m2);
     mx = m2;
   }
   __device__ R value() const { return mx + flog(sum); }
 };
-
-__device__ __forceinline__ int ungray(int g) {
-  g ^= g >> 1; g ^= g >> 2; g ^= g >> 4;
-  return g;
-}
 
 constexpr int kLlrPerThread = 4;  // bits per instance <= 128 antennas x 8 bits = 4 x 256 threads
 // Workgroups of 1024 threads serve instances with more than 256 (antenna, kI) rows: fewer row
@@ -334,25 +329,27 @@ __device__ __forceinline__ void estimate_body(const EstArgs& a, const int b) {
         __syncthreads();
       }
 
-      // symbol marginals and the plain Monte Carlo histogram: row (m, kI)
+      // symbol marginals and the plain Monte Carlo histogram: row (m, kI).  The level offsets are
+      // differences of small integers, exact in floating point; the maxima are plain max
+      // instructions.
       if (row < n_rows) {
         const int m = row / Q, kIt = row % Q;
         const R q2 = a2[m];
         const R l2e = R(1.4426950408889634), q2l = q2 * l2e;
         for (int c = 0; c < ch; ++c) {
           const CM<R> v = cm[c * nt + m];
-          const R eI = R(kIt - v.kI);
+          const R eI = R(kIt) - R(v.kI), kQf = R(v.kQ);
           const R b0 = (v.base + eI * (v.aI - q2 * eI)) * l2e;
           const R aQl = v.aQ * l2e;
           R val[Q];
           R lm = R(-INFINITY);
 #pragma unroll
           for (int kQt = 0; kQt < Q; ++kQt) {
-            const R eQ = R(kQt - v.kQ);
+            const R eQ = R(kQt) - kQf;
             val[kQt] = b0 + eQ * (aQl - q2l * eQ);
-            lm = val[kQt] > lm ? val[kQt] : lm;
+            lm = fmax(lm, val[kQt]);
           }
-          const R Mn = lm > Mx ? lm : Mx;
+          const R Mn = fmax(lm, Mx);
           const R sc = fex2(Mx - Mn);
 #pragma unroll
           for (int kQt = 0; kQt < Q; ++kQt) sums[kQt] = sums[kQt] * sc + fex2(val[kQt] - Mn);
@@ -377,9 +374,12 @@ __device__ __forceinline__ void estimate_body(const EstArgs& a, const int b) {
               for (int c = 0; c < ch; ++c) {
                 const CM<R> v = cm[c * nt + m];
                 const int k = ax ? v.kQ : v.kI;
-                const int g = k ^ (k >> 1);
                 const R av = ax ? v.aQ : v.aI;
-                const R ep = R(ungray(g & ~mask) - k), em = R(ungray(g | mask) - k);
+                // the level with this Gray bit cleared (ep) or set (em), as an offset from k: changing
+                // Gray bit j of k flips the binary bits j..0, and one of the two is k itself
+                const bool gb = ((k ^ (k >> 1)) & mask) != 0;
+                const R d = R((k ^ (2 * mask - 1)) - k);
+                const R ep = gb ? d : R(0), em = gb ? R(0) : d;
                 const R Fp = fs[c] + ep * (av - q2 * ep);
                 const R Fm = fs[c] + em * (av - q2 * em);
                 const R gm = (Fp - Fm) * inv_tau;
