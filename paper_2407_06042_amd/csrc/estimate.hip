@@ -311,15 +311,35 @@ __device__ __forceinline__ void estimate_body(const EstArgs& a, const int b) {
           }
           v.kI = Ks[c * N + 2 * m];
           v.kQ = Ks[c * N + 2 * m + 1];
-          const R q2 = a2[m];
-          OnlineLse<R> li, lq;
+          if constexpr (std::is_same<R, float>::value) {
+            // per-axis log normalisers over the Q levels, accumulated in log2 units (no scaling
+            // before each exponential); the level offsets are exact float differences
+            const R sc = inv_tau * R(1.4426950408889634);
+            const R q2s = a2[m] * sc, aIs = v.aI * sc, aQs = v.aQ * sc;
+            const R kIf = R(v.kI), kQf = R(v.kQ);
+            R mi = R(-INFINITY), mq = R(-INFINITY), si = R(0), sq = R(0);
 #pragma unroll
-          for (int k = 0; k < Q; ++k) {
-            const R eI = R(k - v.kI), eQ = R(k - v.kQ);
-            li.add(eI * (v.aI - q2 * eI) * inv_tau);
-            lq.add(eQ * (v.aQ - q2 * eQ) * inv_tau);
+            for (int k = 0; k < Q; ++k) {
+              const R eI = R(k) - kIf, eQ = R(k) - kQf;
+              const R ti = eI * (aIs - q2s * eI), tq = eQ * (aQs - q2s * eQ);
+              const R ni = fmax(mi, ti), nq = fmax(mq, tq);
+              si = si * fex2(mi - ni) + fex2(ti - ni);
+              sq = sq * fex2(mq - nq) + fex2(tq - nq);
+              mi = ni;
+              mq = nq;
+            }
+            v.base = cw * fs[c] - (mi + flg2(si) + mq + flg2(sq)) * R(0.6931471805599453);
+          } else {
+            const R q2 = a2[m];
+            OnlineLse<R> li, lq;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+              const R eI = R(k - v.kI), eQ = R(k - v.kQ);
+              li.add(eI * (v.aI - q2 * eI) * inv_tau);
+              lq.add(eQ * (v.aQ - q2 * eQ) * inv_tau);
+            }
+            v.base = cw * fs[c] - li.value() - lq.value();
           }
-          v.base = cw * fs[c] - li.value() - lq.value();
           cm[c * nt + m] = v;
         }
         if (tid == 0 && rb == 0) {
