@@ -138,7 +138,7 @@ __device__ __forceinline__ mlp_f32x4 mlp_eval4(const unsigned char* lds, uint32_
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     // fragments are re-read for every antenna group (an opaque offset keeps the
-    // compiler from holding all 14 of them in registers across the groups)
+    // compiler from holding all of them in registers across the groups)
     const unsigned char* base = lds + lds_off + opaque_zero_u32() + (uint32_t)lane * 16;
     // only the K slice of antenna group g may contribute: zero weights elsewhere (GW1) or
     // zero inputs of the other groups
