@@ -235,7 +235,7 @@ def test_windowed_proposal_matches_oracle(M, snr, shift):
     (128, 256, 0.5, 30.0, 32, 20, 0),    # Kronecker-correlated 128x128 256-QAM, four waves per 16 chains
     (128, 256, 0.5, 30.0, 48, 20, 9),    # complex planes, four waves per 16 chains, 512-thread workgroups
     (100, 64, 0.0, 24.0, 32, 20, 9),     # complex planes, 100 antennas
-    (41, 16, 0.0, 18.0, 32, 30, 0),      # 1024-thread setup, 41 rows over 16 threads per row (ragged slots)
+    (41, 16, 0.0, 18.0, 32, 30, 0),      # 512-thread setup: 41 antennas, one single pivot, ragged register slots
     (32, 64, 0.0, 22.0, 32, 30, 10),     # complex planes in LDS, one wave per 16 chains
     (32, 64, 0.0, 22.0, 32, 30, 2),      # real-equivalent matrices in LDS, one wave per 16 chains
     (20, 16, 0.0, 18.0, 48, 30, 10),     # the same, 20 antennas (padding rows and K columns), three chain blocks
