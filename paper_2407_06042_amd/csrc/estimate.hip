@@ -204,48 +204,123 @@ __device__ __forceinline__ void estimate_body(const EstArgs& a, const int b) {
           // and one 16-chain tile, for the final and the best states together; lane l holds
           // A[l % 16][4 s + l / 16], B[4 s + l / 16][l % 16] and the outputs at rows 4 (l / 16) + j.
           typedef float f32x4 __attribute__((ext_vector_type(4)));
-          const int lane = tid & 63, nrt = (nr + 15) >> 4, nct = (ch + 15) >> 4, ksteps = (N + 3) >> 2;
-          const R s2 = R(2) * s;
-          for (int u = tid >> 6; u < nrt * nct; u += nth >> 6) {
-            const int rt = u % nrt, ct = u / nrt;
-            const int ia = 16 * rt + (lane & 15), c = 16 * ct + (lane & 15);
-            // every load in bounds (indices clamped, values masked after), so that none is predicated
-            const int iac = ia < nr ? ia : nr - 1, cc = c < ch ? c : ch - 1;
-            f32x4 fre = {0.f, 0.f, 0.f, 0.f}, fim = fre, bre = fre, bim = fre;
-            // two K steps per pass: all their loads issue before the first product
-            constexpr int kU = 2;
-            for (int st0 = 0; st0 < ksteps; st0 += kU) {
-              R hr0[kU], hi0[kU];
-              uint8_t kf0[kU], kb0[kU];
+          // With at least twice as many waves as units (1024-thread workgroups), every unit's K
+          // steps are split between two waves (otherwise half the waves would idle): the second
+          // half's accumulators go through the per-(chain, antenna) array, unused until the
+          // normalisers below, and are added to the first half's in a fixed order.  (In the
+          // 512-thread workgroups the split form's registers would cost the second workgroup per CU.)
+          bool ksplit = false;
+          if constexpr (BS >= 1024) {
+            const int lane = tid & 63, wv = tid >> 6, nwv = nth >> 6;
+            const int nrt = (nr + 15) >> 4, nct = (ch + 15) >> 4, ksteps = (N + 3) >> 2, units = nrt * nct;
+            ksplit = 2 * units <= nwv && (size_t)units * 64 * 16 * sizeof(float) <= (size_t)ch * nt * sizeof(CM<R>);
+            if (ksplit) {
+              constexpr int kU = 2;
+              const int uu = wv % units, kh = wv / units;   // one item per wave
+              const int half = ((ksteps + 1) / 2 + kU - 1) / kU * kU;
+              const int st_a = kh ? half : 0, st_b = kh ? ksteps : half;
+              const int rt = uu % nrt, ct = uu / nrt;
+              const int ia = 16 * rt + (lane & 15), c = 16 * ct + (lane & 15);
+              const int iac = ia < nr ? ia : nr - 1, cc = c < ch ? c : ch - 1;
+              f32x4 fre = {0.f, 0.f, 0.f, 0.f}, fim = fre, bre = fre, bim = fre;
+              for (int st0 = st_a; kh < 2 && st0 < st_b; st0 += kU) {
+                R hr0[kU], hi0[kU];
+                uint8_t kf0[kU], kb0[kU];
 #pragma unroll
-              for (int u = 0; u < kU; ++u) {
-                const int n = 4 * (st0 + u) + (lane >> 4), nc = n < N ? n : N - 1, m = nc >> 1;
-                hr0[u] = hre(m, iac);
-                hi0[u] = him(m, iac);
-                kf0[u] = (uint8_t)Ks[cc * N + nc];
-                kb0[u] = (uint8_t)Kbs[cc * N + nc];
+                for (int u = 0; u < kU; ++u) {
+                  const int n = 4 * (st0 + u) + (lane >> 4), nc = n < N ? n : N - 1, m = nc >> 1;
+                  hr0[u] = hre(m, iac);
+                  hi0[u] = him(m, iac);
+                  kf0[u] = (uint8_t)Ks[cc * N + nc];
+                  kb0[u] = (uint8_t)Kbs[cc * N + nc];
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                  // steps past N or past this half's end: zero
+                  const int n = 4 * (st0 + u) + (lane >> 4);
+                  const bool kin = n < N && st0 + u < st_b;
+                  const bool aok = kin && ia < nr, bok = kin && c < ch;
+                  const R hr = aok ? hr0[u] : R(0), hi = aok ? hi0[u] : R(0);
+                  const R are = (n & 1) ? -hi : hr, aim = (n & 1) ? hr : hi;
+                  const R kf = bok ? R(kf0[u]) : R(0), kb = bok ? R(kb0[u]) : R(0);
+                  fre = __builtin_amdgcn_mfma_f32_16x16x4f32(are, kf, fre, 0, 0, 0);
+                  fim = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, kf, fim, 0, 0, 0);
+                  bre = __builtin_amdgcn_mfma_f32_16x16x4f32(are, kb, bre, 0, 0, 0);
+                  bim = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, kb, bim, 0, 0, 0);
+                }
               }
+              float* part = (float*)cm + (size_t)uu * 64 * 16;
+              if (kh == 1) {
 #pragma unroll
-              for (int u = 0; u < kU; ++u) {
-                const int n = 4 * (st0 + u) + (lane >> 4);   // n >= N (K padding, steps past the end): zero
-                const bool aok = n < N && ia < nr, bok = n < N && c < ch;
-                const R hr = aok ? hr0[u] : R(0), hi = aok ? hi0[u] : R(0);
-                const R are = (n & 1) ? -hi : hr, aim = (n & 1) ? hr : hi;
-                const R kf = bok ? R(kf0[u]) : R(0), kb = bok ? R(kb0[u]) : R(0);
-                fre = __builtin_amdgcn_mfma_f32_16x16x4f32(are, kf, fre, 0, 0, 0);
-                fim = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, kf, fim, 0, 0, 0);
-                bre = __builtin_amdgcn_mfma_f32_16x16x4f32(are, kb, bre, 0, 0, 0);
-                bim = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, kb, bim, 0, 0, 0);
+                for (int j = 0; j < 4; ++j) {
+                  part[(0 + j) * 64 + lane] = fre[j];
+                  part[(4 + j) * 64 + lane] = fim[j];
+                  part[(8 + j) * 64 + lane] = bre[j];
+                  part[(12 + j) * 64 + lane] = bim[j];
+                }
+              }
+              __syncthreads();
+              if (kh == 0) {
+                const R s2 = R(2) * s;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                  const int i = 16 * rt + 4 * (lane >> 4) + j;
+                  const float pre = fre[j] + part[(0 + j) * 64 + lane], pim = fim[j] + part[(4 + j) * 64 + lane];
+                  const float pbr = bre[j] + part[(8 + j) * 64 + lane], pbi = bim[j] + part[(12 + j) * 64 + lane];
+                  if (i < nr && c < ch) {
+                    rs[c * lrs + 2 * i] = ys[2 * i] - s2 * pre;
+                    rs[c * lrs + 2 * i + 1] = ys[2 * i + 1] - s2 * pim;
+                    const R br = ys[2 * i] - s2 * pbr, bi = ys[2 * i + 1] - s2 * pbi;
+                    rb2[c * nr + i] = br * br + bi * bi;
+                  }
+                }
               }
             }
+          }
+          if (!ksplit) {
+            const int lane = tid & 63, nrt = (nr + 15) >> 4, nct = (ch + 15) >> 4, ksteps = (N + 3) >> 2;
+            const R s2 = R(2) * s;
+            for (int u = tid >> 6; u < nrt * nct; u += nth >> 6) {
+              const int rt = u % nrt, ct = u / nrt;
+              const int ia = 16 * rt + (lane & 15), c = 16 * ct + (lane & 15);
+              // every load in bounds (indices clamped, values masked after), so that none is predicated
+              const int iac = ia < nr ? ia : nr - 1, cc = c < ch ? c : ch - 1;
+              f32x4 fre = {0.f, 0.f, 0.f, 0.f}, fim = fre, bre = fre, bim = fre;
+              // two K steps per pass: all their loads issue before the first product
+              constexpr int kU = 2;
+              for (int st0 = 0; st0 < ksteps; st0 += kU) {
+                R hr0[kU], hi0[kU];
+                uint8_t kf0[kU], kb0[kU];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int i = 16 * rt + 4 * (lane >> 4) + j;
-              if (i < nr && c < ch) {
-                rs[c * lrs + 2 * i] = ys[2 * i] - s2 * fre[j];
-                rs[c * lrs + 2 * i + 1] = ys[2 * i + 1] - s2 * fim[j];
-                const R br = ys[2 * i] - s2 * bre[j], bi = ys[2 * i + 1] - s2 * bim[j];
-                rb2[c * nr + i] = br * br + bi * bi;
+                for (int u = 0; u < kU; ++u) {
+                  const int n = 4 * (st0 + u) + (lane >> 4), nc = n < N ? n : N - 1, m = nc >> 1;
+                  hr0[u] = hre(m, iac);
+                  hi0[u] = him(m, iac);
+                  kf0[u] = (uint8_t)Ks[cc * N + nc];
+                  kb0[u] = (uint8_t)Kbs[cc * N + nc];
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                  const int n = 4 * (st0 + u) + (lane >> 4);   // n >= N (K padding, steps past the end): zero
+                  const bool aok = n < N && ia < nr, bok = n < N && c < ch;
+                  const R hr = aok ? hr0[u] : R(0), hi = aok ? hi0[u] : R(0);
+                  const R are = (n & 1) ? -hi : hr, aim = (n & 1) ? hr : hi;
+                  const R kf = bok ? R(kf0[u]) : R(0), kb = bok ? R(kb0[u]) : R(0);
+                  fre = __builtin_amdgcn_mfma_f32_16x16x4f32(are, kf, fre, 0, 0, 0);
+                  fim = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, kf, fim, 0, 0, 0);
+                  bre = __builtin_amdgcn_mfma_f32_16x16x4f32(are, kb, bre, 0, 0, 0);
+                  bim = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, kb, bim, 0, 0, 0);
+                }
+              }
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                const int i = 16 * rt + 4 * (lane >> 4) + j;
+                if (i < nr && c < ch) {
+                  rs[c * lrs + 2 * i] = ys[2 * i] - s2 * fre[j];
+                  rs[c * lrs + 2 * i + 1] = ys[2 * i + 1] - s2 * fim[j];
+                  const R br = ys[2 * i] - s2 * bre[j], bi = ys[2 * i + 1] - s2 * bim[j];
+                  rb2[c * nr + i] = br * br + bi * bi;
+                }
               }
             }
           }
