@@ -48,6 +48,28 @@ constexpr int kLlrPerThread = 4;  // bits per instance <= 128 antennas x 8 bits 
 // Workgroups of 1024 threads serve instances with more than 256 (antenna, kI) rows: fewer row
 // blocks, so the chain chunks are staged (residuals, H^H r) fewer times, and 16 waves per CU.
 
+// Exchanges inside groups of Q consecutive lanes (Q <= 16, so a group never straddles a 32-lane
+// half) by ds_swizzle in its bit mode: lane j reads lane ((j & and) | or) ^ xor of its half, an
+// immediate pattern, so no lane-address registers are needed.
+template <int PAT> __device__ __forceinline__ float swz(float x) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), PAT));
+}
+template <int PAT> __device__ __forceinline__ double swz(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)u, PAT), hi = __builtin_amdgcn_ds_swizzle((int)(u >> 32), PAT);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// x of every member of the lane's group, in member order
+template <int Q, int K = 0, typename R> __device__ __forceinline__ void group_gather(R x, R (&out)[Q]) {
+  out[K] = swz<(0x1F & ~(Q - 1)) | (K << 5)>(x);
+  if constexpr (K + 1 < Q) group_gather<Q, K + 1>(x, out);
+}
+// the largest x of the group (a butterfly)
+template <int Q, int O = 1, typename R> __device__ __forceinline__ R group_max(R x) {
+  if constexpr (O < Q) return group_max<Q, 2 * O>(fmax(x, swz<0x1F | (O << 10)>(x)));
+  else return x;
+}
+
 // Per (chain, antenna) values staged in LDS.
 template <typename R>
 struct CM {
@@ -424,30 +446,29 @@ __device__ __forceinline__ void estimate_body(const EstArgs& a, const int b) {
         __syncthreads();
       }
 
-      // symbol marginals and the plain Monte Carlo histogram: row (m, kI).  The level offsets are
-      // differences of small integers, exact in floating point; the maxima are plain max
-      // instructions.
+      // symbol marginals and the plain Monte Carlo histogram: row (m, kI).  For chain c the row's
+      // terms are b0 + B(kQ), the kI part b0 plus a kQ part B shared by the Q rows of antenna m,
+      // which sit in Q consecutive lanes: lane kI of the group forms B(kQ = kI) and its
+      // exponential relative to the largest B once, and the group exchanges those Q values by
+      // shuffles, so that a row takes three exponentials per chain instead of Q + 1.  The level
+      // offsets are differences of small integers, exact in floating point.
       if (row < n_rows) {
         const int m = row / Q, kIt = row % Q;
         const R q2 = a2[m];
         const R l2e = R(1.4426950408889634), q2l = q2 * l2e;
         for (int c = 0; c < ch; ++c) {
           const CM<R> v = cm[c * nt + m];
-          const R eI = R(kIt) - R(v.kI), kQf = R(v.kQ);
+          const R eI = R(kIt) - R(v.kI), eQ = R(kIt) - R(v.kQ);
           const R b0 = (v.base + eI * (v.aI - q2 * eI)) * l2e;
-          const R aQl = v.aQ * l2e;
-          R val[Q];
-          R lm = R(-INFINITY);
-#pragma unroll
-          for (int kQt = 0; kQt < Q; ++kQt) {
-            const R eQ = R(kQt) - kQf;
-            val[kQt] = b0 + eQ * (aQl - q2l * eQ);
-            lm = fmax(lm, val[kQt]);
-          }
+          const R bq = eQ * (v.aQ * l2e - q2l * eQ);       // B(kQ = kIt)
+          const R bmax = group_max<Q>(bq);
+          R eqs[Q];
+          group_gather<Q>(fex2(bq - bmax), eqs);
+          const R lm = b0 + bmax;                          // the row's largest term for chain c
           const R Mn = fmax(lm, Mx);
-          const R sc = fex2(Mx - Mn);
+          const R sc = fex2(Mx - Mn), w = fex2(lm - Mn);
 #pragma unroll
-          for (int kQt = 0; kQt < Q; ++kQt) sums[kQt] = sums[kQt] * sc + fex2(val[kQt] - Mn);
+          for (int kQt = 0; kQt < Q; ++kQt) sums[kQt] = sums[kQt] * sc + w * eqs[kQt];
           Mx = Mn;
           if (want_mc) {
 #pragma unroll
