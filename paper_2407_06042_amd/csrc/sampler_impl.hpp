@@ -352,7 +352,10 @@ constexpr int cx_lds_halves(int rt, bool win) { return rt <= 8 ? 7 : (win ? 3 : 
 // chain block splitting the dimensions (RT = RTW * WD tiles in all), MG = the
 // packed matrices are read from the instance block in global memory (L2) instead
 // of being staged in LDS.
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false>
+// FULL: the instance has no padding dimensions (N == Npad), so that no dimension needs the
+// padding masks (the caller checks; the results are the same either way).
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false,
+          bool FULL = false>
 __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int inst, const int cgy) {
   constexpr bool F64 = std::is_same<Real, double>::value;
   constexpr bool LRN = KND == 1;   // plain/learned kernel mixture
@@ -894,7 +897,7 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
   Real mu[D], lz[D], eg[D];
   bool valid[D];
 #pragma unroll
-  for (int d = 0; d < D; ++d) valid[d] = dim_of(d) < N;
+  for (int d = 0; d < D; ++d) valid[d] = FULL || dim_of(d) < N;
 
   if constexpr (EVAL) {
     // transition quantities for a given pair (x_from -> x_to)
@@ -1226,10 +1229,11 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
 // Direct launch (PERS false): instance blockIdx.x, chain group blockIdx.y.  Persistent launch:
 // items from the list until it is exhausted, each with its class's arguments (a separate
 // instantiation, so that the direct kernels keep their registers).
-template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX, bool PERS>
+template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX, bool PERS,
+          bool FULL = false>
 __device__ __forceinline__ void sampler_entry(const SamplerArgs& a, const Persist& p) {
   if constexpr (!PERS) {
-    sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX>(a, blockIdx.x, blockIdx.y);
+    sampler_body<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX, FULL>(a, blockIdx.x, blockIdx.y);
   } else {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     for (;;) {
@@ -1253,16 +1257,16 @@ __global__ __launch_bounds__(256) void sampler_kernel(SamplerArgs a, Persist p) 
 // The same kernel held to two waves per SIMD (at most 256 registers): the
 // learned variant with two row tiles per wave fits without spilling.
 template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false,
-          bool PERS = false>
+          bool PERS = false, bool FULL = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sampler_kernel_w2(SamplerArgs a, Persist p) {
-  sampler_entry<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX, PERS>(a, p);
+  sampler_entry<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX, PERS, FULL>(a, p);
 }
 
 // ... in 512-thread workgroups (two chain blocks of the four-wave layout).
 template <typename Real, int RTW, int WD, bool MG, int Q, int PM, bool EVAL, int WIN, int KND, bool CX = false,
-          bool PERS = false>
+          bool PERS = false, bool FULL = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void sampler_kernel_w2_512(SamplerArgs a, Persist p) {
-  sampler_entry<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX, PERS>(a, p);
+  sampler_entry<Real, RTW, WD, MG, Q, PM, EVAL, WIN, KND, CX, PERS, FULL>(a, p);
 }
 
 // LDS bytes of a configuration.
@@ -1326,6 +1330,10 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
   void (*k)(SamplerArgs, Persist);
   // persistent instantiations (plans): the plain float chains
   constexpr bool kPersOK = KND == 0 && !std::is_same<Real, double>::value;
+  // direct launches of the plain float complex-plane chains: a variant without the padding masks
+  // for instances whose dimensions fill the tiles (fewer instructions per transition)
+  constexpr bool kFull = KND == 0 && CX && !std::is_same<Real, double>::value;
+  const bool full = sh.N == sh.Npad;
   const bool pers = (p != nullptr || cfg != nullptr) && !eval;
   if (pers) {
     if constexpr (kPersOK) {
@@ -1344,10 +1352,17 @@ hipError_t launch_t(const Shape& sh, const SamplerArgs& a, bool eval, hipStream_
     if constexpr (kW2Eval) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, true, WIN, KND, CX>;
     else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, true, WIN, KND, CX>;
   } else if (waves > 4) {
-    if constexpr (kW2 && WD == 4 && !LRN) k = sampler_kernel_w2_512<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>;
-    else return hipErrorInvalidConfiguration;
+    if constexpr (kW2 && WD == 4 && !LRN) {
+      if constexpr (kFull) k = full ? sampler_kernel_w2_512<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX, false, true>
+                                    : sampler_kernel_w2_512<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>;
+      else k = sampler_kernel_w2_512<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>;
+    } else {
+      return hipErrorInvalidConfiguration;
+    }
   } else {
-    if constexpr (kW2) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>;
+    if constexpr (kW2 && kFull) k = full ? sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX, false, true>
+                                         : sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>;
+    else if constexpr (kW2) k = sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>;
     else if constexpr (kW2Alone) k = sh.share ? sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>
                                               : sampler_kernel_w2<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>;
     else k = sampler_kernel<Real, RTW, WD, MG, Q, PM, false, WIN, KND, CX>;
