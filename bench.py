@@ -551,9 +551,9 @@ def main():
                      "unit": "T lane-ops/s", "frac": achieved / PEAK_VALU_OPS, "traffic": traffic,
                      "peak_definition": "non-packed VALU lane operations: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz",
                      "frac_of_packed_fp32_flop_peak": achieved / PEAK_FP32_VECTOR,
-                     "kernel": "sampler_kernel_w2<float, 4, 2, true, 8, PM_F16X2, false, 3, 0, true> (two waves "
-                               "per 16 chains, two chain blocks per workgroup, complex-plane matrices from L2, "
-                               "3-level window)",
+                     "kernel": "sampler_kernel_w2<float, 4, 2, true, 8, PM_F16X2, false, 3, 0, true, false, "
+                               "true> (two waves per 16 chains, two chain blocks per workgroup, complex-plane "
+                               "matrices from L2, 3-level window, no padding dimensions)",
                      "ops_per_chain_iter": ops,
                      "gx_frac": gx5["frac"], "gx_tflops": gx5["tflops"],
                      "gx_kernel": "gx_loop_kernel<8, 1, 1, true> (dmala_gx_loop, bf16)"},
