@@ -607,8 +607,13 @@ __device__ __forceinline__ void sampler_body(const SamplerArgs& a, const int ins
           for (int j = 0; j < 8; ++j) {
             br[kb][j] = (__bf16)(float)xr[kb][j];
             bi[kb][j] = (__bf16)(float)xi[kb][j];
-            bn[kb][j] = (__bf16)(float)xn[kb][j];
           }
+          // -x_im: the sign bits of the converted values (exact, as for the fp16 form)
+          uint32_t ub[4];
+          __builtin_memcpy(ub, &bi[kb], 16);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) ub[q] ^= 0x80008000u;
+          __builtin_memcpy(&bn[kb], ub, 16);
         }
       }
       const uint32_t fo = opaque_zero() + (uint32_t)lane * 16;
