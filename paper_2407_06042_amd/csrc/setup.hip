@@ -18,6 +18,8 @@
 // matrix is scaled by a power of two and split into fp16 (or bf16) terms laid
 // out as 16x16x32 MFMA A-operand fragments; on the float64 path it is stored
 // as a dense row-major array.
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace dmala {
@@ -99,8 +101,13 @@ __device__ __forceinline__ float via_float(double v) {
 // plane pl (real, imaginary), antenna tile at (16 rows), K block kb of 32 antennas; lane l element j
 // holds plane(X)[16 at + l%16][16 (2 kb + j/4) + 4 (l/16) + j%4] -- the same K permutation over
 // antennas that the real-equivalent packing applies to real dimensions.
-__device__ float pack_fragments(const cd* X, int ld, double c, int nt, int N, int RT, int KB, int npass, int bf16,
-                                unsigned char* dst, int cx) {
+// The form (NPASS terms, bf16, complex planes) is a compile-time choice and the function is inlined,
+// so that the element loop has no branches and X keeps its address space (LDS reads, not flat loads).
+template <int NPASS, bool BF16, bool CX>
+__device__ __forceinline__ float pack_fragments(const cd* X, int ld, double c, int nt, int N, int RT, int KB,
+                                                unsigned char* dst) {
+  constexpr int npass = NPASS;
+  constexpr bool bf16 = BF16, cx = CX;
   // X is Hermitian positive semidefinite (G, and A = I - gamma M, whose eigenvalues lie in [0, 1)),
   // so |Re x_ij|, |Im x_ij| <= |x_ij| <= sqrt(x_ii x_jj) <= max_i x_ii: the largest entry is the
   // largest diagonal one.  Every wavefront reads the diagonal and reduces it for itself (no barrier).
@@ -129,28 +136,28 @@ __device__ float pack_fragments(const cd* X, int ld, double c, int nt, int N, in
     for (int j = 0; j < 8; ++j) {
       const int n2 = 16 * (2 * kb + (j >> 2)) + 4 * (l >> 4) + (j & 3);
       double v;
-      if (cx) {
+      if constexpr (cx) {
         const cd e = X[(n < nt && n2 < nt ? n : 0) * ld + (n2 < nt ? n2 : 0)];
         v = (n < nt && n2 < nt) ? sc * (pl ? e.im : e.re) : 0.0;
       } else {
         v = (n < N && n2 < N) ? sc * realeq(X, ld, n, n2) : 0.0;
       }
-      if (bf16) {
+      if constexpr (bf16) {
         f0.b[j] = (__bf16)via_float(v);
       } else {
         const _Float16 hi = (_Float16)via_float(v);
         const double r1 = v - (double)hi;
         const _Float16 mid = (_Float16)via_float(r1);
         const double r2 = r1 - (double)mid;
-        if (npass == 3) { f0.h[j] = (_Float16)via_float(r2); f1.h[j] = mid; f2.h[j] = hi; }
-        else if (npass == 2) { f0.h[j] = mid; f1.h[j] = hi; }
+        if constexpr (npass == 3) { f0.h[j] = (_Float16)via_float(r2); f1.h[j] = mid; f2.h[j] = hi; }
+        else if constexpr (npass == 2) { f0.h[j] = mid; f1.h[j] = hi; }
         else f0.h[j] = hi;
       }
     }
     unsigned char* o = dst + (size_t)t * 1024 + l * 16;
     *(uint4*)o = f0.u;
-    if (npass > 1) *(uint4*)(o + pass_stride) = f1.u;
-    if (npass > 2) *(uint4*)(o + 2 * pass_stride) = f2.u;
+    if constexpr (npass > 1) *(uint4*)(o + pass_stride) = f1.u;
+    if constexpr (npass > 2) *(uint4*)(o + 2 * pass_stride) = f2.u;
   }
   return (float)ldexp(1.0, -e2);
 }
@@ -343,7 +350,9 @@ __device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
     double* ezd = (double*)(blk + kParamBytes) + 2 * (size_t)Npad * Npad + Npad;
     for (int n = tid; n < Npad; n += blockDim.x) ezd[n] = n < N ? cz * realeq_vec(z, n) : 0.0;
   } else {
-    scaleE = pack_fragments(W, ld, cE, nt, N, a.RT, a.KB, kEPasses, 0, frag + (size_t)npP * pass_bytes, a.cx);
+    unsigned char* fe = frag + (size_t)npP * pass_bytes;
+    scaleE = a.cx ? pack_fragments<kEPasses, false, true>(W, ld, cE, nt, N, a.RT, a.KB, fe)
+                  : pack_fragments<kEPasses, false, false>(W, ld, cE, nt, N, a.RT, a.KB, fe);
     float* ezf = (float*)(frag + (size_t)(npP + kEPasses) * pass_bytes) + Npad;
     for (int n = tid; n < Npad; n += blockDim.x) ezf[n] = n < N ? (float)(cz * realeq_vec(z, n)) : 0.0f;
     float* afv = ezf + Npad;
@@ -540,7 +549,13 @@ __device__ __forceinline__ void setup_body(const SetupArgs& a, const int b) {
       double* pbd = (double*)(blk + kParamBytes) + 2 * (size_t)Npad * Npad;
       for (int n = tid; n < Npad; n += blockDim.x) pbd[n] = n < N ? cb * realeq_vec(bv, n) : 0.0;
     } else {
-      scaleP = pack_fragments(W, ld, cP, nt, N, a.RT, a.KB, npP, a.pm == PM_BF16X1, frag, a.cx);
+      auto packP = [&](auto CXC) {
+        constexpr bool C = decltype(CXC)::value;
+        if (a.pm == PM_BF16X1) return pack_fragments<1, true, C>(W, ld, cP, nt, N, a.RT, a.KB, frag);
+        if (npP == 2) return pack_fragments<2, false, C>(W, ld, cP, nt, N, a.RT, a.KB, frag);
+        return pack_fragments<1, false, C>(W, ld, cP, nt, N, a.RT, a.KB, frag);
+      };
+      scaleP = a.cx ? packP(std::true_type{}) : packP(std::false_type{});
       float* pbf = (float*)(frag + (size_t)(npP + kEPasses) * pass_bytes);
       for (int n = tid; n < Npad; n += blockDim.x) pbf[n] = n < N ? (float)(cb * realeq_vec(bv, n)) : 0.0f;
     }
